@@ -1,0 +1,496 @@
+"""Oracle: parameters, packing, planner, BFV client side and layer references.
+
+TEST INFRASTRUCTURE ONLY -- see oracle/__init__.py.
+
+Paper passages (SecONNds, arXiv 2506.11586):
+  ring and notation ................ Sec. 2.1
+  BFV encryption b = a*sk+d*m+e .... App. C (encryption equation)
+  product as coefficient convolution App. C (its printed sum lacks the
+                                     negacyclic wrap term; included here)
+  NTT multiplication ............... App. C.1
+  NTT preprocessing flow ........... Sec. 6.2 (NTT preprocessing)
+  coefficient encoding, sparse
+  results, extraction .............. Sec. 6.1 (HE kernels) and Sec. 2.3
+                                     (Cheetah paragraph)
+The paper gives no formula for the packing, no HE parameters and no tiling
+rule; the readings used (packing layout, largest primes, smallest root,
+bytes-objective planner, round-half-up decode) are listed with the design
+notes and pinned by the CPU tests.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import build as _build
+
+# --------------------------------------------------------------------------
+# C core binding
+# --------------------------------------------------------------------------
+_lib = None
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def lib():
+    """Load oracle/liboracle.so, compiling it with gcc first if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        L.or_is_prime.argtypes = [u64]
+        L.or_is_prime.restype = i32
+        L.or_find_primes.argtypes = [u32, u32, u32, _u64p]
+        L.or_find_primes.restype = i32
+        L.or_find_psi.argtypes = [u64, u32]
+        L.or_find_psi.restype = u64
+        L.or_negacyclic_mul.argtypes = [_u64p, _u64p, _u64p, u32, u64]
+        L.or_negacyclic_coeff.argtypes = [_u64p, _u64p, u32, u32, u64]
+        L.or_negacyclic_coeff.restype = u64
+        L.or_ntt_def.argtypes = [_u64p, _u64p, u32, u64, u64]
+        L.or_intt_def.argtypes = [_u64p, _u64p, u32, u64, u64]
+        L.or_ntt_fast.argtypes = [_u64p, u32, u64, u64]
+        L.or_intt_fast.argtypes = [_u64p, u32, u64, u64]
+        L.or_ntt_batch.argtypes = [_u64p, u64, u32, u32, _u64p, _u64p, i32, i32]
+        L.or_conv_mac.argtypes = [_u64p, _u64p, _u64p, u32, u32, u32, u32, u32, u32, _u64p]
+        L.or_conv_layer_def.argtypes = [_u64p, _u64p, _u64p, u32, u32, u32, u32, u32, u32, _u64p]
+        L.or_conv_layer_coeff.argtypes = [_u64p, _u64p, u32, u32, u32, u32, _u64p, u32, u32, u32, u32, u32, u32]
+        L.or_conv_layer_coeff.restype = u64
+        L.or_bfv_encrypt.argtypes = [u64, u32, u32, _u64p, _u64p, _i64p, _u64p, _i64p, _u64p, _u64p, _u64p, i32]
+        L.or_bfv_phase.argtypes = [u64, u32, u32, _u64p, _u64p, _i64p, _u64p, _u64p, i32]
+        L.or_num_threads.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"], "oracle arrays must be C-contiguous"
+    if a.dtype == np.uint64:
+        return a.ctypes.data_as(_u64p)
+    if a.dtype == np.int64:
+        return a.ctypes.data_as(_i64p)
+    raise TypeError(a.dtype)
+
+
+def _u64(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.uint64))
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(lib().or_num_threads())
+
+
+# --------------------------------------------------------------------------
+# Parameters
+# --------------------------------------------------------------------------
+def is_prime(n: int) -> bool:
+    return bool(lib().or_is_prime(int(n)))
+
+
+def find_primes(N: int, bits: int, L: int) -> list[int]:
+    """The L largest primes below 2^bits with q = 1 mod 2N, descending."""
+    out = np.zeros(L, dtype=np.uint64)
+    got = lib().or_find_primes(N, bits, L, _p(out))
+    if got != L:
+        raise ValueError(f"only {got} primes below 2^{bits} are 1 mod {2 * N}")
+    return [int(v) for v in out]
+
+
+def find_psi(q: int, N: int) -> int:
+    """Smallest primitive 2N-th root of unity mod q."""
+    return int(lib().or_find_psi(int(q), int(N)))
+
+
+@dataclass
+class Params:
+    """RNS BFV parameters: N, L primes of `bits` bits, plaintext modulus t."""
+
+    N: int
+    L: int
+    bits: int
+    t: int
+    q: list = field(default_factory=list)
+    psi: list = field(default_factory=list)
+
+    def __post_init__(self):
+        if not self.q:
+            self.q = find_primes(self.N, self.bits, self.L)
+        if not self.psi:
+            self.psi = [find_psi(q, self.N) for q in self.q]
+        self.Q = math.prod(self.q)
+        self.delta = self.Q // self.t  # BFV scale floor(Q/t) (App. C: delta)
+        self.delta_l = [self.delta % q for q in self.q]
+        self.q_arr = _u64(self.q)
+        self.psi_arr = _u64(self.psi)
+        self.logN = self.N.bit_length() - 1
+
+
+# --------------------------------------------------------------------------
+# Ring products and transforms
+# --------------------------------------------------------------------------
+def negacyclic_mul(a, b, q: int) -> np.ndarray:
+    a, b = _u64(a), _u64(b)
+    c = np.zeros_like(a)
+    lib().or_negacyclic_mul(_p(a), _p(b), _p(c), a.size, int(q))
+    return c
+
+
+def negacyclic_coeff(a, b, k: int, q: int) -> int:
+    a, b = _u64(a), _u64(b)
+    return int(lib().or_negacyclic_coeff(_p(a), _p(b), int(k), a.size, int(q)))
+
+
+def ntt_def(a, q: int, psi: int) -> np.ndarray:
+    a = _u64(a)
+    out = np.zeros_like(a)
+    lib().or_ntt_def(_p(a), _p(out), a.size, int(q), int(psi))
+    return out
+
+
+def intt_def(a, q: int, psi: int) -> np.ndarray:
+    a = _u64(a)
+    out = np.zeros_like(a)
+    lib().or_intt_def(_p(a), _p(out), a.size, int(q), int(psi))
+    return out
+
+
+def ntt_fast(a, q: int, psi: int) -> np.ndarray:
+    a = _u64(a).copy()
+    lib().or_ntt_fast(_p(a), a.size, int(q), int(psi))
+    return a
+
+
+def intt_fast(a, q: int, psi: int) -> np.ndarray:
+    a = _u64(a).copy()
+    lib().or_intt_fast(_p(a), a.size, int(q), int(psi))
+    return a
+
+
+MODE_DEF, MODE_FAST = 0, 1
+
+
+def ntt(polys, prm: Params, mode: int = MODE_FAST, inverse: bool = False) -> np.ndarray:
+    """Forward (or inverse) NTT of every limb of polys [..., L, N] (copy)."""
+    a = _u64(polys).copy()
+    assert a.shape[-1] == prm.N and a.shape[-2] == prm.L
+    n = a.size // (prm.L * prm.N)
+    lib().or_ntt_batch(_p(a), n, prm.L, prm.N, _p(prm.q_arr), _p(prm.psi_arr), int(mode), int(inverse))
+    return a
+
+
+def intt(polys, prm: Params, mode: int = MODE_FAST) -> np.ndarray:
+    return ntt(polys, prm, mode, inverse=True)
+
+
+# --------------------------------------------------------------------------
+# Convolution geometry, planner and packing
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Conv:
+    """A conv layer: input C x H x W, M output channels, kh x kw kernel."""
+
+    C: int
+    H: int
+    W: int
+    M: int
+    kh: int
+    kw: int
+    stride: int = 1
+    pad: int = 0
+
+
+@dataclass(frozen=True)
+class Geometry:
+    Cw: int
+    Hw: int
+    Ww: int
+    Hp: int  # padded input height (before any subsampling)
+    Wp: int
+    Ho: int  # output height at the layer's stride
+    Wo: int
+    sub: bool  # 1x1 strided conv: the padded input is subsampled first
+    He: int  # height of the tensor the tiles read (subsampled if sub)
+    We: int
+    R1: int  # stride-1 output rows that must be produced
+    C1: int
+    bh: int  # stride-1 output rows per tile
+    bw: int
+    nsi: int
+    nsj: int
+    S: int
+    CB: int
+    O: int  # coefficient index of output (0, 0) in a product
+
+
+def geometry(cv: Conv, Cw: int, Hw: int, Ww: int) -> Geometry:
+    """Tiling of a conv for the packing descriptor (Cw, Hw, Ww).
+
+    Stride s > 1 with a kernel larger than 1x1 is computed at stride 1 and
+    every s-th output kept; a strided 1x1 conv subsamples the padded input
+    first and then runs at stride 1."""
+    s = cv.stride
+    Hp, Wp = cv.H + 2 * cv.pad, cv.W + 2 * cv.pad
+    Ho, Wo = (Hp - cv.kh) // s + 1, (Wp - cv.kw) // s + 1
+    sub = cv.kh == 1 and cv.kw == 1 and s > 1
+    if sub:
+        He, We, R1, C1 = Ho, Wo, Ho, Wo
+    else:
+        He, We, R1, C1 = Hp, Wp, (Ho - 1) * s + 1, (Wo - 1) * s + 1
+    bh, bw = Hw - cv.kh + 1, Ww - cv.kw + 1
+    nsi, nsj = -(-R1 // bh), -(-C1 // bw)
+    CB = -(-cv.C // Cw)
+    O = (Cw - 1) * Hw * Ww + (cv.kh - 1) * Ww + (cv.kw - 1)
+    return Geometry(Cw, Hw, Ww, Hp, Wp, Ho, Wo, sub, He, We, R1, C1, bh, bw, nsi, nsj, nsi * nsj, CB, O)
+
+
+def layer_cost(cv: Conv, g: Geometry, N: int, L: int, B: int) -> tuple[int, int]:
+    """(HBM bytes, modmuls) of one unfused layer solve for B images: weights
+    read once, every ciphertext word read and written in each of the three
+    steps; NTTs at (N/2) log2 N modmuls per limb-polynomial, MACs at one
+    modmul per word."""
+    in_cts, out_cts = g.CB * g.S, cv.M * g.S
+    ct_bytes = 2 * L * N * 8
+    byts = cv.M * g.CB * L * N * 8 + B * 3 * (in_cts + out_cts) * ct_bytes
+    logN = N.bit_length() - 1
+    mm = B * (in_cts + out_cts) * 2 * L * (N // 2) * logN + B * cv.M * g.CB * g.S * 2 * L * N
+    return byts, mm
+
+
+def plan_conv(cv: Conv, N: int, L: int, B: int = 1) -> Geometry:
+    """Packing descriptor by exhaustive search: every Hw in [kh, He], Ww in
+    [kw, We] with Hw*Ww <= N, Cw = min(C, floor(N/(Hw*Ww))); minimise HBM
+    bytes, then modmuls, then prefer larger Hw, then larger Ww."""
+    g0 = geometry(cv, 1, cv.kh, cv.kw)
+    best, best_key = None, None
+    for Hw in range(cv.kh, g0.He + 1):
+        for Ww in range(cv.kw, g0.We + 1):
+            if Hw * Ww > N:
+                break
+            Cw = min(cv.C, N // (Hw * Ww))
+            g = geometry(cv, Cw, Hw, Ww)
+            byts, mm = layer_cost(cv, g, N, L, B)
+            key = (byts, mm, -Hw, -Ww)
+            if best_key is None or key < best_key:
+                best, best_key = g, key
+    if best is None:
+        raise ValueError("no packing fits N")
+    return best
+
+
+def padded_input(x: np.ndarray, cv: Conv, g: Geometry) -> np.ndarray:
+    """Zero-padded input, subsampled for a strided 1x1 conv: [C][He][We]."""
+    C, H, W = x.shape
+    xp = np.zeros((C, g.Hp, g.Wp), dtype=np.int64)
+    xp[:, cv.pad:cv.pad + H, cv.pad:cv.pad + W] = x
+    if g.sub:
+        xp = np.ascontiguousarray(xp[:, ::cv.stride, ::cv.stride])
+    return xp
+
+
+def pack_input(x: np.ndarray, cv: Conv, g: Geometry, t: int, N: int) -> np.ndarray:
+    """Client-side coefficient encoding of one input tensor x[C][H][W]:
+    polys [CB][S][N] with coefficient cc*Hw*Ww + i*Ww + j of block cb, tile
+    (si, sj) equal to the padded input at channel cb*Cw+cc, row si*bh+i,
+    column sj*bw+j, reduced mod t into [0, t); zero outside the tensor."""
+    xp = padded_input(x, cv, g)
+    HW = g.Hw * g.Ww
+    out = np.zeros((g.CB, g.S, N), dtype=np.uint64)
+    for cb in range(g.CB):
+        for si in range(g.nsi):
+            for sj in range(g.nsj):
+                s = si * g.nsj + sj
+                for cc in range(g.Cw):
+                    c = cb * g.Cw + cc
+                    if c >= cv.C:
+                        break
+                    r0, c0 = si * g.bh, sj * g.bw
+                    blk = xp[c, r0:r0 + g.Hw, c0:c0 + g.Ww]  # clipped at the tensor edge
+                    for i in range(blk.shape[0]):
+                        base = cc * HW + i * g.Ww
+                        out[cb, s, base:base + blk.shape[1]] = np.mod(blk[i], t).astype(np.uint64)
+    return out
+
+
+def pack_weights(K: np.ndarray, cv: Conv, g: Geometry, prm: Params) -> np.ndarray:
+    """Server-side kernel encoding, coefficient form: wc [M][CB][L][N] with
+    coefficient O - cc*Hw*Ww - l*Ww - l' of (m, cb) equal to K[m][cb*Cw+cc][l][l'],
+    a signed integer lifted into [0, q_l)."""
+    M, C, kh, kw = K.shape
+    HW = g.Hw * g.Ww
+    out = np.zeros((M, g.CB, prm.L, prm.N), dtype=np.uint64)
+    for m in range(M):
+        for c in range(C):
+            cb, cc = divmod(c, g.Cw)
+            for i in range(kh):
+                for j in range(kw):
+                    idx = g.O - cc * HW - i * g.Ww - j
+                    v = int(K[m, c, i, j])
+                    for l, q in enumerate(prm.q):
+                        out[m, cb, l, idx] = v % q
+    return out
+
+
+def encode_weights(K: np.ndarray, cv: Conv, g: Geometry, prm: Params, mode: int = MODE_FAST) -> np.ndarray:
+    """NTT preprocessing of the weights (Sec. 6.2): pack, then forward NTT of
+    every limb.  W [M][CB][L][N] in NTT form."""
+    return ntt(pack_weights(K, cv, g, prm), prm, mode)
+
+
+def conv_mac(in_ntt, w_ntt, B: int, g: Geometry, M: int, prm: Params) -> np.ndarray:
+    """out[b][m][s][c][l][k] = sum_cb in[b][cb][s][c][l][k] * w[m][cb][l][k] mod q_l."""
+    in_ntt, w_ntt = _u64(in_ntt), _u64(w_ntt)
+    assert in_ntt.size == B * g.CB * g.S * 2 * prm.L * prm.N
+    assert w_ntt.size == M * g.CB * prm.L * prm.N
+    out = np.zeros((B, M, g.S, 2, prm.L, prm.N), dtype=np.uint64)
+    lib().or_conv_mac(_p(in_ntt), _p(w_ntt), _p(out), B, g.CB, g.S, M, prm.L, prm.N, _p(prm.q_arr))
+    return out
+
+
+def conv_layer_ntt(in_ct, w_ntt, B: int, g: Geometry, M: int, prm: Params, mode: int = MODE_FAST) -> np.ndarray:
+    """The paper's online flow (Sec. 6.2): NTT every input ciphertext, MAC in
+    the NTT domain, inverse NTT of the results.  Coefficient form in and out."""
+    x = ntt(in_ct, prm, mode)
+    y = conv_mac(x, w_ntt, B, g, M, prm)
+    return intt(y, prm, mode)
+
+
+def conv_layer_def(in_ct, wc, B: int, g: Geometry, M: int, prm: Params) -> np.ndarray:
+    """The same layer by its plain definition: schoolbook negacyclic products
+    of every input ciphertext with the coefficient-form kernel polynomials,
+    summed over channel blocks.  O(N^2) per product."""
+    in_ct, wc = _u64(in_ct), _u64(wc)
+    out = np.zeros((B, M, g.S, 2, prm.L, prm.N), dtype=np.uint64)
+    lib().or_conv_layer_def(_p(in_ct), _p(wc), _p(out), B, g.CB, g.S, M, prm.L, prm.N, _p(prm.q_arr))
+    return out
+
+
+def conv_layer_coeff(in_ct, wc, g: Geometry, prm: Params, b, m, s, c, l, k) -> int:
+    """One output word of the layer by definition, O(CB*N)."""
+    in_ct, wc = _u64(in_ct), _u64(wc)
+    return int(lib().or_conv_layer_coeff(_p(in_ct), _p(wc), g.CB, g.S, prm.L, prm.N, _p(prm.q_arr),
+                                         b, m, s, c, l, k))
+
+
+# --------------------------------------------------------------------------
+# BFV client side (App. C); the server path never sees the key
+# --------------------------------------------------------------------------
+def bfv_encrypt(msgs, sk, a, e, prm: Params, mode: int = MODE_FAST) -> np.ndarray:
+    """Symmetric-key encryption of n messages (msgs [n][N] in [0, t)) with
+    secret key sk [N] (ternary), uniform a [n][L][N] and error e [n][N]:
+    ct[i][0] = a_i, ct[i][1] = a_i*sk + delta*m_i + e_i per limb.
+    Returns ct [n][2][L][N]."""
+    msgs = _u64(msgs)
+    n = msgs.shape[0]
+    a = _u64(a).reshape(n, prm.L, prm.N)
+    e = np.ascontiguousarray(np.asarray(e, dtype=np.int64).reshape(n, prm.N))
+    sk = np.ascontiguousarray(np.asarray(sk, dtype=np.int64))
+    ct = np.zeros((n, 2, prm.L, prm.N), dtype=np.uint64)
+    dl = _u64(prm.delta_l)
+    lib().or_bfv_encrypt(n, prm.L, prm.N, _p(prm.q_arr), _p(prm.psi_arr), _p(sk), _p(a), _p(e), _p(msgs),
+                         _p(dl), _p(ct), int(mode))
+    return ct
+
+
+def bfv_phase(ct, sk, prm: Params, mode: int = MODE_FAST) -> np.ndarray:
+    """v_l = b_l - a_l*sk mod q_l for ct [n][2][L][N] -> [n][L][N]."""
+    ct = _u64(ct)
+    n = ct.size // (2 * prm.L * prm.N)
+    sk = np.ascontiguousarray(np.asarray(sk, dtype=np.int64))
+    v = np.zeros((n, prm.L, prm.N), dtype=np.uint64)
+    lib().or_bfv_phase(n, prm.L, prm.N, _p(prm.q_arr), _p(prm.psi_arr), _p(sk), _p(ct), _p(v), int(mode))
+    return v
+
+
+def crt(v: np.ndarray, prm: Params) -> np.ndarray:
+    """Chinese remaindering of residues v[..., L] into [0, Q) (object array of
+    Python ints)."""
+    acc = np.zeros(v.shape[:-1], dtype=object)
+    for l, q in enumerate(prm.q):
+        Ql = prm.Q // q
+        c = Ql * pow(Ql % q, -1, q)
+        acc = acc + v[..., l].astype(object) * c
+    return acc % prm.Q
+
+
+def bfv_decode(v: np.ndarray, prm: Params, with_noise: bool = False):
+    """Phase residues v[..., L] -> messages centred in [-t/2, t/2):
+    m = floor((t*V + floor(Q/2)) / Q) mod t (round half up).  With
+    with_noise, also the largest |V - delta*m mod Q| (centred) in bits."""
+    V = crt(v, prm)
+    t, Q = prm.t, prm.Q
+    m = ((t * V + Q // 2) // Q) % t
+    mc = np.where(m >= t // 2, m - t, m).astype(np.int64)
+    if not with_noise:
+        return mc
+    noise = (V - prm.delta * (m % t)) % Q
+    noise = np.where(noise > Q // 2, Q - noise, noise)
+    mx = max([int(z) for z in noise.ravel()] + [0])
+    return mc, (mx.bit_length() if mx else 0)
+
+
+def bfv_decrypt(ct, sk, prm: Params, coeffs=None, mode: int = MODE_FAST, with_noise: bool = False):
+    """Decrypt ct [n][2][L][N]; decode only the coefficient indexes in
+    `coeffs` if given.  Returns centred messages [n][len(coeffs) or N]."""
+    v = bfv_phase(ct, sk, prm, mode)  # [n][L][N]
+    v = np.moveaxis(v, -2, -1)  # [n][N][L]
+    if coeffs is not None:
+        v = v[:, np.asarray(coeffs), :]
+    return bfv_decode(v, prm, with_noise)
+
+
+# --------------------------------------------------------------------------
+# Output decoding and the plaintext reference
+# --------------------------------------------------------------------------
+def output_slots(g: Geometry) -> np.ndarray:
+    """Coefficient indexes O + i*Ww + j (i < bh, j < bw) that hold results."""
+    i = np.arange(g.bh)[:, None]
+    j = np.arange(g.bw)[None, :]
+    return (g.O + i * g.Ww + j).ravel()
+
+
+def assemble_output(slot_vals: np.ndarray, cv: Conv, g: Geometry) -> np.ndarray:
+    """slot_vals [M][S][bh*bw] (decoded output slots of every tile) ->
+    output tensor [M][Ho][Wo] at the layer's stride."""
+    M = slot_vals.shape[0]
+    full = np.zeros((M, g.nsi * g.bh, g.nsj * g.bw), dtype=np.int64)
+    for si in range(g.nsi):
+        for sj in range(g.nsj):
+            s = si * g.nsj + sj
+            full[:, si * g.bh:(si + 1) * g.bh, sj * g.bw:(sj + 1) * g.bw] = slot_vals[:, s].reshape(M, g.bh, g.bw)
+    if g.sub:
+        return full[:, :g.Ho, :g.Wo]
+    return full[:, :g.R1:cv.stride, :g.C1:cv.stride][:, :g.Ho, :g.Wo]
+
+
+def plain_conv(x: np.ndarray, K: np.ndarray, stride: int, pad: int) -> np.ndarray:
+    """Plaintext integer convolution (cross-correlation, as CNNs use):
+    y[m][i][j] = sum_{c,u,v} K[m][c][u][v] * xpad[c][i*stride+u][j*stride+v],
+    in wrapping int64 (exact whenever the true sum fits, and always exact
+    mod 2^k for k <= 64)."""
+    C, H, W = x.shape
+    M, C2, kh, kw = K.shape
+    assert C == C2
+    xp = np.zeros((C, H + 2 * pad, W + 2 * pad), dtype=np.int64)
+    xp[:, pad:pad + H, pad:pad + W] = x
+    Ho = (H + 2 * pad - kh) // stride + 1
+    Wo = (W + 2 * pad - kw) // stride + 1
+    y = np.zeros((M, Ho, Wo), dtype=np.int64)
+    with np.errstate(over="ignore"):
+        for u in range(kh):
+            for v in range(kw):
+                patch = xp[:, u:u + stride * (Ho - 1) + 1:stride, v:v + stride * (Wo - 1) + 1:stride]
+                y += np.tensordot(K[:, :, u, v].astype(np.int64), patch, axes=([1], [0]))
+    return y
+
+
+def centre_mod(y: np.ndarray, t: int) -> np.ndarray:
+    """y mod t, centred into [-t/2, t/2)."""
+    r = np.mod(y, t)
+    return np.where(r >= t // 2, r - t, r).astype(np.int64)
