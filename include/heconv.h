@@ -1,0 +1,159 @@
+/*
+ * heconv.h -- C ABI of the MI355X (gfx950) homomorphic-convolution library.
+ *
+ * The server side of an HE convolution on RNS BFV ciphertexts, as the paper
+ * describes it (SecONNds, arXiv 2506.11586, Sec. 6.2 "NTT preprocessing"):
+ * weights are encoded and NTT-transformed once; each incoming ciphertext is
+ * NTT-transformed on receipt; every multiply-accumulate runs in the NTT
+ * domain, summed over input-channel blocks; only the final results are
+ * inverse-transformed.  The library never handles key material (Sec. 6.3:
+ * the GPU side computes only on encrypted data).
+ *
+ * Conventions for every entry point:
+ *  - All functions return he_status; nothing throws across the ABI.
+ *  - Pointers named d_* are device pointers (HIP device memory on the
+ *    device that was current when the context was created).  The caller
+ *    owns every buffer; the library owns only its context tables.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *    enqueued asynchronously; errors raised by asynchronous work surface as
+ *    HE_EDEVICE from a later call or from the caller's synchronisation.
+ *  - Ciphertext and plaintext words are uint64 residues.  Inputs must be
+ *    canonical (< q_l of their limb); outputs are always canonical.
+ *  - An RNS polynomial is [L][N] words, limb-major: limb l holds the N
+ *    coefficients (or NTT values) modulo q_l.  A ciphertext is two RNS
+ *    polynomials (a, b) in the paper's order (App. C): component 0 = a,
+ *    component 1 = b.
+ *  - NTT form: entry i of a limb is the evaluation of the polynomial at
+ *    psi_l^(2*brv(i)+1), brv = bit reversal over log2 N bits, psi_l the
+ *    smallest primitive 2N-th root of unity mod q_l (App. C.1).
+ *  - No entry point allocates device memory except he_ctx_create.
+ */
+#ifndef HECONV_H
+#define HECONV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HE_OK = 0,
+  HE_EINVAL = -1,  /* null pointer, zero-sized descriptor field, bad flag */
+  HE_ESHAPE = -2,  /* packing descriptor does not fit N or the layer */
+  HE_EPARAM = -3,  /* unsupported N, q not prime / not 1 mod 2N / too large */
+  HE_ENOMEM = -4,  /* device allocation failed (context creation only) */
+  HE_EDEVICE = -5, /* a HIP call or kernel launch failed */
+  HE_EBUSY = -6    /* reserved */
+} he_status;
+
+/* BFV/RNS parameters.  N: ring degree, a power of two in [2^10, 2^14].
+ * L: number of RNS limbs, 1..8.  q[0..L-1]: distinct primes, q_l = 1 mod 2N,
+ * q_l < 2^61.  t: plaintext modulus (informational; the server-side path
+ * does not depend on it). */
+typedef struct {
+  uint32_t N, L;
+  const uint64_t* q;
+  uint64_t t;
+} he_params;
+
+/* One convolution layer (cross-correlation as in CNNs): input C x H x W,
+ * M output channels, kh x kw kernel, stride, zero padding `pad` on every
+ * side.  (Cw, Hw, Ww) is the packing descriptor: Cw channels of an Hw x Ww
+ * window per ciphertext (Cw*Hw*Ww <= N).  A strided conv with a kernel
+ * larger than 1x1 is evaluated at stride 1 (the client keeps every
+ * stride-th output); a strided 1x1 conv expects the client to subsample the
+ * padded input first.  The packing layout is:
+ *   input poly (channel block cb, tile s): coeff cc*Hw*Ww + i*Ww + j
+ *     = padded input[cb*Cw+cc][si*bh+i][sj*bw+j], bh = Hw-kh+1, bw = Ww-kw+1
+ *   kernel poly (m, cb): coeff O - cc*Hw*Ww - i*Ww - j = K[m][cb*Cw+cc][i][j],
+ *     O = (Cw-1)*Hw*Ww + (kh-1)*Ww + (kw-1)
+ *   output (m, tile s): coeff O + i*Ww + j = stride-1 output at
+ *     (si*bh+i, sj*bw+j), i < bh, j < bw.
+ * The paper gives no formula for this coefficient encoding (Sec. 6.1 and
+ * Sec. 2.3, Cheetah paragraph); this layout is the library's. */
+typedef struct {
+  uint32_t C, H, W, M, kh, kw, stride, pad;
+  uint32_t Cw, Hw, Ww;
+} he_conv_desc;
+
+typedef struct he_ctx he_ctx;
+
+/* Status as text (static string). */
+const char* he_status_str(he_status s);
+
+/* The L largest primes below 2^bits that are 1 mod 2N, in descending order,
+ * written to q_out[0..L-1].  HE_EPARAM if N is not a power of two, bits is
+ * outside [20, 61], or fewer than L such primes exist. */
+he_status he_gen_primes(uint32_t N, uint32_t bits, uint32_t L, uint64_t* q_out);
+
+/* Create a context on the current HIP device: checks the parameters, picks
+ * psi_l (the smallest primitive 2N-th root of unity mod q_l), builds the
+ * twiddle tables (powers of psi in bit-reversed order with their Shoup
+ * quotients, N^-1) and copies them to the device.  *out receives the
+ * context; destroy it with he_ctx_destroy. */
+he_status he_ctx_create(const he_params* prm, he_ctx** out);
+void he_ctx_destroy(he_ctx* ctx);
+
+/* The roots chosen by the context: psi_out[0..L-1]. */
+he_status he_ctx_psi(const he_ctx* ctx, uint64_t* psi_out);
+
+/* Packing descriptor by exhaustive search (the library's planner): every
+ * Hw in [kh, He], Ww in [kw, We] with Hw*Ww <= N (He x We = padded input,
+ * subsampled for a strided 1x1 conv), Cw = min(C, N / (Hw*Ww)); minimise
+ * the unfused HBM bytes M*CB*L*N*8 + batch*3*(in_cts+out_cts)*2*L*N*8, then
+ * the modmul count, then prefer larger Hw, then larger Ww.  Fills io->Cw,
+ * io->Hw, io->Ww.  batch_hint = number of images a launch will carry. */
+he_status he_plan_conv(const he_ctx* ctx, he_conv_desc* io, uint32_t batch_hint);
+
+/* The same planner without a context (host only, no device needed):
+ * N a power of two, L >= 1. */
+he_status he_plan_conv_host(uint32_t N, uint32_t L, he_conv_desc* io, uint32_t batch_hint);
+
+/* The root a context would pick for (q, N): the smallest primitive 2N-th
+ * root of unity mod q (host only).  HE_EPARAM unless q is a prime below
+ * 2^62 with q = 1 mod 2N. */
+he_status he_min_root(uint64_t q, uint32_t N, uint64_t* psi_out);
+
+/* Sizes for a planned layer (per image): CB = ceil(C/Cw) channel blocks,
+ * S spatial tiles, in_cts = CB*S, out_cts = M*S, w_words = M*CB*L*N.  Any
+ * output pointer may be NULL.  HE_ESHAPE if the descriptor is invalid. */
+he_status he_conv_sizes(const he_ctx* ctx, const he_conv_desc* desc, uint32_t* CB, uint32_t* S,
+                        uint64_t* in_cts, uint64_t* out_cts, uint64_t* w_words);
+
+/* Offline step: NTT preprocessing of the weights (Sec. 6.2).  Packs
+ * d_w[M][C][kh][kw] (signed int64, device) into kernel polynomials, lifts
+ * each signed value into [0, q_l), and forward-NTTs every limb.
+ * d_wntt: [M][CB][L][N] uint64, written completely. */
+he_status he_encode_weights(const he_ctx* ctx, const he_conv_desc* desc, const int64_t* d_w, uint64_t* d_wntt,
+                            void* stream);
+
+/* Forward negacyclic NTT, in place, of n RNS polynomials d_polys[n][L][N]
+ * (App. C.1).  n = 0 is a no-op. */
+he_status he_ntt_fwd(const he_ctx* ctx, uint64_t* d_polys, uint64_t n, void* stream);
+
+/* Inverse NTT, in place: d_polys[n][L][N] from NTT form back to
+ * coefficients (including the factor N^-1). */
+he_status he_ntt_inv(const he_ctx* ctx, uint64_t* d_polys, uint64_t n, void* stream);
+
+/* Multiply-accumulate in the NTT domain over channel blocks (Sec. 6.2):
+ *   out[b][m][s][c][l][k] = sum_{cb<CB} in[b][cb][s][c][l][k] * w[m][cb][l][k] mod q_l
+ * d_in_ntt: [B][CB][S][2][L][N], d_wntt: [M][CB][L][N],
+ * d_out_ntt: [B][M][S][2][L][N] (written completely; must not alias the
+ * inputs). */
+he_status he_conv_ntt_mac(const he_ctx* ctx, const he_conv_desc* desc, uint32_t B, const uint64_t* d_in_ntt,
+                          const uint64_t* d_wntt, uint64_t* d_out_ntt, void* stream);
+
+/* The whole online layer: forward NTT of the B*CB*S input ciphertexts in
+ * place (d_in is clobbered: it holds their NTT form afterwards), the MAC,
+ * then the inverse NTT of the B*M*S output ciphertexts.
+ * d_in: [B][CB][S][2][L][N] coefficient form; d_out: [B][M][S][2][L][N]
+ * coefficient form. */
+he_status he_conv_layer(const he_ctx* ctx, const he_conv_desc* desc, uint32_t B, uint64_t* d_in,
+                        const uint64_t* d_wntt, uint64_t* d_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HECONV_H */

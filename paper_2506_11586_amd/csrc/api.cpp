@@ -1,0 +1,349 @@
+// C ABI of the homomorphic-convolution library (declared in include/heconv.h):
+// parameter checks, the library's own prime/root search and twiddle tables,
+// the packing planner, and the entry points that enqueue the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "heconv.h"
+#include "kernels.h"
+
+using heconv::LimbConst;
+using heconv::Tw;
+
+namespace {
+
+typedef unsigned __int128 u128;
+
+uint64_t mmul(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+
+uint64_t mpow(uint64_t b, uint64_t e, uint64_t m) {
+  uint64_t r = 1;
+  b %= m;
+  for (; e; e >>= 1, b = mmul(b, b, m))
+    if (e & 1) r = mmul(r, b, m);
+  return r;
+}
+
+// Miller-Rabin with the seven bases of Jaeschke/Sinclair, exact for all
+// 64-bit inputs.
+bool prime64(uint64_t n) {
+  if (n < 2) return false;
+  for (uint64_t p : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull, 17ull, 19ull, 23ull, 29ull, 31ull, 37ull}) {
+    if (n % p == 0) return n == p;
+  }
+  uint64_t d = n - 1;
+  unsigned s = __builtin_ctzll(d);
+  d >>= s;
+  for (uint64_t a : {2ull, 325ull, 9375ull, 28178ull, 450775ull, 9780504ull, 1795265022ull}) {
+    uint64_t x = mpow(a % n, d, n);
+    if (x == 0 || x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (unsigned r = 1; r < s && comp; r++) {
+      x = mmul(x, x, n);
+      if (x == n - 1) comp = false;
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+unsigned log2u(uint64_t x) { return 63 - __builtin_clzll(x); }
+
+unsigned bitrev(unsigned x, unsigned bits) {
+  unsigned r = 0;
+  for (unsigned i = 0; i < bits; i++, x >>= 1) r = (r << 1) | (x & 1);
+  return r;
+}
+
+// The smallest primitive 2N-th root of unity mod q (q = 1 mod 2N).  A
+// primitive 2N-th root r is c^((q-1)/2N) for some c with r^N = -1; every
+// other is an odd power of r.
+uint64_t min_root(uint64_t q, uint32_t N) {
+  uint64_t r = 0;
+  for (uint64_t c = 2; c < q && !r; c++) {
+    uint64_t cand = mpow(c, (q - 1) / (2ull * N), q);
+    if (mpow(cand, N, q) == q - 1) r = cand;
+  }
+  if (!r) return 0;
+  const uint64_t r2 = mmul(r, r, q);
+  uint64_t best = r;
+  for (uint64_t k = 1, v = r; k < 2ull * N; k += 2, v = mmul(v, r2, q))
+    if (v < best) best = v;
+  return best;
+}
+
+uint64_t shoup(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
+
+}  // namespace
+
+struct he_ctx {
+  int device = 0;
+  uint32_t N = 0, logN = 0, L = 0;
+  uint64_t t = 0;
+  std::vector<uint64_t> q, psi;
+  std::vector<LimbConst> lc;
+  Tw* d_fwd = nullptr;  // [L][N] psi^brv(k) with Shoup quotient
+  Tw* d_inv = nullptr;  // [L][N] psi^-brv(k) with Shoup quotient
+  LimbConst* d_lc = nullptr;
+};
+
+namespace {
+
+// Conv geometry derived from a descriptor (mirrors the header's layout).
+struct Geo {
+  uint32_t He, We, R1, C1, bh, bw, nsi, nsj, S, CB, O;
+  bool sub;
+};
+
+bool geo_of(const he_conv_desc& d, uint32_t N, Geo& g) {
+  if (!d.C || !d.H || !d.W || !d.M || !d.kh || !d.kw || !d.stride) return false;
+  const uint32_t Hp = d.H + 2 * d.pad, Wp = d.W + 2 * d.pad;
+  if (Hp < d.kh || Wp < d.kw) return false;
+  const uint32_t Ho = (Hp - d.kh) / d.stride + 1, Wo = (Wp - d.kw) / d.stride + 1;
+  g.sub = d.kh == 1 && d.kw == 1 && d.stride > 1;
+  if (g.sub) {
+    g.He = Ho, g.We = Wo, g.R1 = Ho, g.C1 = Wo;
+  } else {
+    g.He = Hp, g.We = Wp, g.R1 = (Ho - 1) * d.stride + 1, g.C1 = (Wo - 1) * d.stride + 1;
+  }
+  if (!d.Cw || !d.Hw || !d.Ww) return false;
+  if (d.Cw > d.C || d.Hw < d.kh || d.Ww < d.kw || d.Hw > g.He || d.Ww > g.We) return false;
+  if ((uint64_t)d.Cw * d.Hw * d.Ww > N) return false;
+  g.bh = d.Hw - d.kh + 1, g.bw = d.Ww - d.kw + 1;
+  g.nsi = (g.R1 + g.bh - 1) / g.bh, g.nsj = (g.C1 + g.bw - 1) / g.bw;
+  g.S = g.nsi * g.nsj;
+  g.CB = (d.C + d.Cw - 1) / d.Cw;
+  g.O = (d.Cw - 1) * d.Hw * d.Ww + (d.kh - 1) * d.Ww + (d.kw - 1);
+  return true;
+}
+
+he_status check_ctx(const he_ctx* c) { return c ? HE_OK : HE_EINVAL; }
+
+he_status dev_err(hipError_t e) { return e == hipSuccess ? HE_OK : HE_EDEVICE; }
+
+}  // namespace
+
+extern "C" {
+
+const char* he_status_str(he_status s) {
+  switch (s) {
+    case HE_OK: return "ok";
+    case HE_EINVAL: return "invalid argument";
+    case HE_ESHAPE: return "shape/descriptor mismatch";
+    case HE_EPARAM: return "unsupported parameters";
+    case HE_ENOMEM: return "device allocation failed";
+    case HE_EDEVICE: return "HIP device error";
+    case HE_EBUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+he_status he_gen_primes(uint32_t N, uint32_t bits, uint32_t L, uint64_t* q_out) {
+  if (!q_out || !pow2(N) || N < 2 || bits < 20 || bits > 61 || L == 0) return HE_EPARAM;
+  const uint64_t m = 2ull * N;
+  uint64_t c = ((1ull << bits) - 2) / m * m + 1;  // largest value below 2^bits that is 1 mod 2N
+  uint32_t got = 0;
+  for (; got < L && c > m; c -= m)
+    if (prime64(c)) q_out[got++] = c;
+  return got == L ? HE_OK : HE_EPARAM;
+}
+
+he_status he_ctx_create(const he_params* prm, he_ctx** out) {
+  if (!prm || !out || !prm->q) return HE_EINVAL;
+  *out = nullptr;
+  const uint32_t N = prm->N, L = prm->L;
+  if (!pow2(N) || N < (1u << 10) || N > (1u << 14) || L == 0 || L > 8) return HE_EPARAM;
+  for (uint32_t l = 0; l < L; l++) {
+    const uint64_t q = prm->q[l];
+    if (q >= (1ull << 61) || q % (2ull * N) != 1 || !prime64(q)) return HE_EPARAM;
+    for (uint32_t j = 0; j < l; j++)
+      if (prm->q[j] == q) return HE_EPARAM;
+  }
+  he_ctx* c = new (std::nothrow) he_ctx;
+  if (!c) return HE_ENOMEM;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return HE_EDEVICE;
+  }
+  c->N = N, c->logN = log2u(N), c->L = L, c->t = prm->t;
+  c->q.assign(prm->q, prm->q + L);
+  std::vector<Tw> fwd((size_t)L * N), inv((size_t)L * N);
+  std::vector<uint64_t> pw(N);
+  for (uint32_t l = 0; l < L; l++) {
+    const uint64_t q = c->q[l];
+    const uint64_t psi = min_root(q, N);
+    if (!psi) {
+      delete c;
+      return HE_EPARAM;
+    }
+    c->psi.push_back(psi);
+    const uint64_t psi_inv = mpow(psi, q - 2, q);
+    for (int dir = 0; dir < 2; dir++) {
+      const uint64_t base = dir ? psi_inv : psi;
+      pw[0] = 1;
+      for (uint32_t i = 1; i < N; i++) pw[i] = mmul(pw[i - 1], base, q);
+      Tw* tab = (dir ? inv.data() : fwd.data()) + (size_t)l * N;
+      for (uint32_t k = 0; k < N; k++) {
+        const uint64_t w = pw[bitrev(k, c->logN)];
+        tab[k] = Tw{w, shoup(w, q)};
+      }
+    }
+    LimbConst k{};
+    k.q = q, k.two_q = 2 * q;
+    k.ninv = mpow(N % q, q - 2, q), k.ninv_sh = shoup(k.ninv, q);
+    k.ninv_w = mmul(k.ninv, inv[(size_t)l * N + 1].w, q), k.ninv_w_sh = shoup(k.ninv_w, q);
+    k.r64 = (uint64_t)(((u128)1 << 64) % q), k.r64_sh = shoup(k.r64, q);
+    k.mu64 = (uint64_t)(((u128)1 << 64) / q);
+    c->lc.push_back(k);
+  }
+  const size_t tb = sizeof(Tw) * (size_t)L * N;
+  if (hipMalloc(&c->d_fwd, tb) != hipSuccess || hipMalloc(&c->d_inv, tb) != hipSuccess ||
+      hipMalloc(&c->d_lc, sizeof(LimbConst) * L) != hipSuccess) {
+    he_ctx_destroy(c);
+    return HE_ENOMEM;
+  }
+  if (hipMemcpy(c->d_fwd, fwd.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_inv, inv.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_lc, c->lc.data(), sizeof(LimbConst) * L, hipMemcpyHostToDevice) != hipSuccess) {
+    he_ctx_destroy(c);
+    return HE_EDEVICE;
+  }
+  *out = c;
+  return HE_OK;
+}
+
+void he_ctx_destroy(he_ctx* c) {
+  if (!c) return;
+  if (c->d_fwd) (void)hipFree(c->d_fwd);
+  if (c->d_inv) (void)hipFree(c->d_inv);
+  if (c->d_lc) (void)hipFree(c->d_lc);
+  delete c;
+}
+
+he_status he_ctx_psi(const he_ctx* c, uint64_t* psi_out) {
+  if (check_ctx(c) || !psi_out) return HE_EINVAL;
+  std::memcpy(psi_out, c->psi.data(), sizeof(uint64_t) * c->L);
+  return HE_OK;
+}
+
+he_status he_plan_conv_host(uint32_t N, uint32_t L, he_conv_desc* io, uint32_t batch_hint) {
+  if (!io) return HE_EINVAL;
+  if (!pow2(N) || N < 2 || L == 0) return HE_EPARAM;
+  const unsigned logN = log2u(N);
+  if (!batch_hint) batch_hint = 1;
+  he_conv_desc d = *io;
+  d.Cw = 1, d.Hw = d.kh, d.Ww = d.kw;
+  Geo g0;
+  if (!geo_of(d, N, g0)) return io->C && io->M && io->kh && io->kw && io->stride ? HE_ESHAPE : HE_EINVAL;
+  const u128 LN8 = (u128)L * N * 8, ct = 2 * LN8;
+  const u128 ntt_mm = (u128)L * (N / 2) * logN * 2;  // per ciphertext
+  bool have = false;
+  u128 best_b = 0, best_m = 0;
+  uint32_t bHw = 0, bWw = 0, bCw = 0;
+  for (uint32_t Hw = d.kh; Hw <= g0.He; Hw++) {
+    for (uint32_t Ww = d.kw; Ww <= g0.We; Ww++) {
+      if ((uint64_t)Hw * Ww > N) break;
+      d.Hw = Hw, d.Ww = Ww;
+      d.Cw = std::min<uint64_t>(d.C, N / ((uint64_t)Hw * Ww));
+      Geo g;
+      if (!geo_of(d, N, g)) continue;
+      const u128 in_cts = (u128)g.CB * g.S, out_cts = (u128)d.M * g.S;
+      const u128 bytes = (u128)d.M * g.CB * LN8 + (u128)batch_hint * 3 * (in_cts + out_cts) * ct;
+      const u128 mm = (u128)batch_hint * (in_cts + out_cts) * ntt_mm +
+                      (u128)batch_hint * d.M * g.CB * g.S * 2 * L * N;
+      // strict improvement keeps the earlier (smaller) Hw/Ww on ties of both
+      // costs; ties are then broken towards larger Hw, then larger Ww
+      bool better = !have || bytes < best_b || (bytes == best_b && mm < best_m) ||
+                    (bytes == best_b && mm == best_m && (Hw > bHw || (Hw == bHw && Ww > bWw)));
+      if (better) have = true, best_b = bytes, best_m = mm, bHw = Hw, bWw = Ww, bCw = d.Cw;
+    }
+  }
+  if (!have) return HE_ESHAPE;
+  io->Cw = bCw, io->Hw = bHw, io->Ww = bWw;
+  return HE_OK;
+}
+
+he_status he_plan_conv(const he_ctx* c, he_conv_desc* io, uint32_t batch_hint) {
+  if (check_ctx(c)) return HE_EINVAL;
+  return he_plan_conv_host(c->N, c->L, io, batch_hint);
+}
+
+he_status he_min_root(uint64_t q, uint32_t N, uint64_t* psi_out) {
+  if (!psi_out || !pow2(N) || N < 2 || q % (2ull * N) != 1 || q >= (1ull << 62) || !prime64(q)) return HE_EPARAM;
+  *psi_out = min_root(q, N);
+  return *psi_out ? HE_OK : HE_EPARAM;
+}
+
+he_status he_conv_sizes(const he_ctx* c, const he_conv_desc* d, uint32_t* CB, uint32_t* S, uint64_t* in_cts,
+                        uint64_t* out_cts, uint64_t* w_words) {
+  if (check_ctx(c) || !d) return HE_EINVAL;
+  Geo g;
+  if (!geo_of(*d, c->N, g)) return HE_ESHAPE;
+  if (CB) *CB = g.CB;
+  if (S) *S = g.S;
+  if (in_cts) *in_cts = (uint64_t)g.CB * g.S;
+  if (out_cts) *out_cts = (uint64_t)d->M * g.S;
+  if (w_words) *w_words = (uint64_t)d->M * g.CB * c->L * c->N;
+  return HE_OK;
+}
+
+he_status he_encode_weights(const he_ctx* c, const he_conv_desc* d, const int64_t* d_w, uint64_t* d_wntt,
+                            void* stream) {
+  if (check_ctx(c) || !d || !d_w || !d_wntt) return HE_EINVAL;
+  Geo g;
+  if (!geo_of(*d, c->N, g)) return HE_ESHAPE;
+  heconv::PackGeom pg{d->M, d->C, d->kh, d->kw, d->Cw, d->Hw, d->Ww, g.CB, c->L, c->N, g.O};
+  hipStream_t st = (hipStream_t)stream;
+  he_status s = dev_err(heconv::pack_weights_launch(pg, d_w, d_wntt, c->d_lc, st));
+  if (s) return s;
+  return dev_err(heconv::ntt_launch(false, c->logN, d_wntt, (uint64_t)d->M * g.CB, c->L, c->d_fwd, c->d_lc, st));
+}
+
+he_status he_ntt_fwd(const he_ctx* c, uint64_t* d_polys, uint64_t n, void* stream) {
+  if (check_ctx(c)) return HE_EINVAL;
+  if (n == 0) return HE_OK;
+  if (!d_polys) return HE_EINVAL;
+  return dev_err(heconv::ntt_launch(false, c->logN, d_polys, n, c->L, c->d_fwd, c->d_lc, (hipStream_t)stream));
+}
+
+he_status he_ntt_inv(const he_ctx* c, uint64_t* d_polys, uint64_t n, void* stream) {
+  if (check_ctx(c)) return HE_EINVAL;
+  if (n == 0) return HE_OK;
+  if (!d_polys) return HE_EINVAL;
+  return dev_err(heconv::ntt_launch(true, c->logN, d_polys, n, c->L, c->d_inv, c->d_lc, (hipStream_t)stream));
+}
+
+he_status he_conv_ntt_mac(const he_ctx* c, const he_conv_desc* d, uint32_t B, const uint64_t* d_in_ntt,
+                          const uint64_t* d_wntt, uint64_t* d_out_ntt, void* stream) {
+  if (check_ctx(c) || !d) return HE_EINVAL;
+  Geo g;
+  if (!geo_of(*d, c->N, g)) return HE_ESHAPE;
+  if (B == 0) return HE_OK;
+  if (!d_in_ntt || !d_wntt || !d_out_ntt) return HE_EINVAL;
+  if ((uint64_t)B * g.S * 2 > 0xffffffffull) return HE_ESHAPE;
+  return dev_err(heconv::mac_launch(d_in_ntt, d_wntt, d_out_ntt, B, g.CB, g.S, d->M, c->L, c->N, c->d_lc,
+                                    (hipStream_t)stream));
+}
+
+he_status he_conv_layer(const he_ctx* c, const he_conv_desc* d, uint32_t B, uint64_t* d_in, const uint64_t* d_wntt,
+                        uint64_t* d_out, void* stream) {
+  if (check_ctx(c) || !d) return HE_EINVAL;
+  Geo g;
+  if (!geo_of(*d, c->N, g)) return HE_ESHAPE;
+  if (B == 0) return HE_OK;
+  if (!d_in || !d_wntt || !d_out) return HE_EINVAL;
+  he_status s = he_ntt_fwd(c, d_in, (uint64_t)B * g.CB * g.S * 2, stream);
+  if (s) return s;
+  s = he_conv_ntt_mac(c, d, B, d_in, d_wntt, d_out, stream);
+  if (s) return s;
+  return he_ntt_inv(c, d_out, (uint64_t)B * d->M * g.S * 2, stream);
+}
+
+}  // extern "C"

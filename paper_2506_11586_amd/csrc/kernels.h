@@ -1,0 +1,28 @@
+// Internal launcher declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "modarith.h"
+
+namespace heconv {
+
+// Forward (inverse = false) or inverse NTT, in place, of n_rns_polys RNS
+// polynomials [n][L][N], N = 2^logN, logN in [10, 14].
+hipError_t ntt_launch(bool inverse, uint32_t logN, uint64_t* polys, uint64_t n_rns_polys, uint32_t L, const Tw* tw,
+                      const LimbConst* lc, hipStream_t st);
+
+// Geometry of a planned conv as the kernels need it.
+struct PackGeom {
+  uint32_t M, C, kh, kw, Cw, Hw, Ww, CB, L, N, O;
+};
+
+// Kernel polynomials in coefficient form: out[M][CB][L][N], lifted mod q_l.
+hipError_t pack_weights_launch(const PackGeom& g, const int64_t* w, uint64_t* out, const LimbConst* lc,
+                               hipStream_t st);
+
+// out[b][m][s][c][l][k] = sum_cb in[b][cb][s][c][l][k] * w[m][cb][l][k] mod q_l.
+hipError_t mac_launch(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t B, uint32_t CB, uint32_t S,
+                      uint32_t M, uint32_t L, uint32_t N, const LimbConst* lc, hipStream_t st);
+
+}  // namespace heconv

@@ -1,0 +1,178 @@
+// Weight packing and the channel-block multiply-accumulate (NTT domain).
+#include "kernels.h"
+
+namespace heconv {
+
+// ---------------------------------------------------------------------------
+// Kernel-polynomial packing (offline).  Each thread writes one coefficient
+// k of (m, cb, l): with d = O - k, the coefficient holds K[m][cb*Cw+cc][i][j]
+// when d = cc*Hw*Ww + i*Ww + j with cc < Cw, i < kh, j < kw and the channel
+// exists, and 0 otherwise.  Signed values are lifted into [0, q_l).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void pack_weights_kernel(PackGeom g, const int64_t* __restrict__ w,
+                                                           uint64_t* __restrict__ out,
+                                                           const LimbConst* __restrict__ lcs) {
+  const uint64_t total = (uint64_t)g.M * g.CB * g.L * g.N;
+  const uint32_t HW = g.Hw * g.Ww;
+  for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = (uint32_t)(idx % g.N);
+    uint64_t r = idx / g.N;
+    const uint32_t l = (uint32_t)(r % g.L);
+    r /= g.L;
+    const uint32_t cb = (uint32_t)(r % g.CB);
+    const uint32_t m = (uint32_t)(r / g.CB);
+    uint64_t v = 0;
+    if (k <= g.O) {
+      const uint32_t d = g.O - k;
+      const uint32_t cc = d / HW, rem = d % HW;
+      const uint32_t i = rem / g.Ww, j = rem % g.Ww;
+      const uint32_t c = cb * g.Cw + cc;
+      if (cc < g.Cw && c < g.C && i < g.kh && j < g.kw) {
+        const int64_t s = w[(((uint64_t)m * g.C + c) * g.kh + i) * g.kw + j];
+        const uint64_t q = lcs[l].q;
+        if (s >= 0) {
+          v = (uint64_t)s % q;
+        } else {
+          const uint64_t a = (uint64_t)0 - (uint64_t)s;  // |s|, exact also for INT64_MIN
+          const uint64_t am = a % q;
+          v = am ? q - am : 0;
+        }
+      }
+    }
+    out[idx] = v;
+  }
+}
+
+hipError_t pack_weights_launch(const PackGeom& g, const int64_t* w, uint64_t* out, const LimbConst* lc,
+                               hipStream_t st) {
+  const uint64_t total = (uint64_t)g.M * g.CB * g.L * g.N;
+  uint64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(pack_weights_kernel, dim3((uint32_t)blocks), dim3(256), 0, st, g, w, out, lc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// MAC over channel blocks.  Every NTT point (l, k) is an independent small
+// product Out[(b,s,c), m] = sum_cb In[(b,s,c), cb] * W[cb, m] mod q_l.  A
+// thread owns one k for a tile of MT output channels x RT rows (b, s, c)
+// and accumulates the 128-bit products exactly in registers, reducing once
+// per output (and every 32 terms, so the sum never overflows 128 bits with
+// q < 2^61).  Consecutive lanes take consecutive k: every load and store is
+// a coalesced 512-byte wave access.
+// ---------------------------------------------------------------------------
+constexpr int MAC_THREADS = 256;
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Remap so that
+// consecutive tile ids land on one XCD: the tiles of one k-chunk (which
+// read the same input words) then share that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
+  const uint32_t full = nblocks / 8 * 8;
+  if (bid >= full) return bid;
+  const uint32_t per = full / 8;
+  return (bid % 8) * per + bid / 8;
+}
+
+template <int MT, int RT>
+__global__ __launch_bounds__(MAC_THREADS) void mac_kernel(const uint64_t* __restrict__ in,
+                                                          const uint64_t* __restrict__ w,
+                                                          uint64_t* __restrict__ out, uint32_t CB, uint32_t S,
+                                                          uint32_t M, uint32_t L, uint32_t N, uint32_t rows,
+                                                          uint32_t n_mt, uint32_t n_rt,
+                                                          const LimbConst* __restrict__ lcs) {
+  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t per_chunk = n_mt * n_rt;
+  const uint32_t kc = tile / per_chunk;
+  const uint32_t mt = (tile % per_chunk) / n_rt;
+  const uint32_t rt = tile % n_rt;
+  const uint32_t chunks_per_limb = N / MAC_THREADS;
+  const uint32_t l = kc / chunks_per_limb;
+  const uint32_t k = (kc % chunks_per_limb) * MAC_THREADS + threadIdx.x;
+  const LimbConst c = lcs[l];
+  const uint64_t LN = (uint64_t)L * N;
+
+  // row r = (b*S + s)*2 + comp; input address of (r, cb) and output of (r, m)
+  uint64_t in_off[RT], out_off[RT];
+  bool rv[RT];
+#pragma unroll
+  for (int i = 0; i < RT; i++) {
+    const uint32_t r = rt * RT + i;
+    rv[i] = r < rows;
+    const uint32_t rr = rv[i] ? r : 0;
+    const uint32_t comp = rr & 1, bs = rr >> 1;
+    const uint32_t b = bs / S, s = bs % S;
+    in_off[i] = ((((uint64_t)b * CB) * S + s) * 2 + comp) * LN + (uint64_t)l * N + k;
+    out_off[i] = ((((uint64_t)b * M) * S + s) * 2 + comp) * LN + (uint64_t)l * N + k;
+  }
+  const uint64_t in_cb_stride = (uint64_t)S * 2 * LN;  // cb -> cb+1 in the input
+  const uint64_t out_m_stride = (uint64_t)S * 2 * LN;  // m -> m+1 in the output
+  bool mv[MT];
+  uint64_t w_off[MT];
+#pragma unroll
+  for (int j = 0; j < MT; j++) {
+    const uint32_t m = mt * MT + j;
+    mv[j] = m < M;
+    w_off[j] = ((uint64_t)(mv[j] ? m : 0) * CB) * LN + (uint64_t)l * N + k;
+  }
+
+  uint64_t hi[MT][RT], lo[MT][RT];
+#pragma unroll
+  for (int j = 0; j < MT; j++)
+#pragma unroll
+    for (int i = 0; i < RT; i++) hi[j][i] = lo[j][i] = 0;
+
+  for (uint32_t cb0 = 0; cb0 < CB; cb0 += 32) {
+    const uint32_t cb1 = cb0 + 32 < CB ? cb0 + 32 : CB;
+    for (uint32_t cb = cb0; cb < cb1; cb++) {
+      uint64_t xv[RT], wv[MT];
+#pragma unroll
+      for (int i = 0; i < RT; i++) xv[i] = rv[i] ? in[in_off[i] + cb * in_cb_stride] : 0;
+#pragma unroll
+      for (int j = 0; j < MT; j++) wv[j] = mv[j] ? w[w_off[j] + (uint64_t)cb * LN] : 0;
+#pragma unroll
+      for (int j = 0; j < MT; j++)
+#pragma unroll
+        for (int i = 0; i < RT; i++) {
+          uint64_t ph, pl;
+          mul_wide(xv[i], wv[j], ph, pl);
+          lo[j][i] += pl;
+          hi[j][i] += ph + (lo[j][i] < pl ? 1 : 0);
+        }
+    }
+    if (cb1 < CB) {  // fold the 128-bit sums before they can overflow
+#pragma unroll
+      for (int j = 0; j < MT; j++)
+#pragma unroll
+        for (int i = 0; i < RT; i++) {
+          lo[j][i] = reduce128(hi[j][i], lo[j][i], c);
+          hi[j][i] = 0;
+        }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < MT; j++)
+#pragma unroll
+    for (int i = 0; i < RT; i++)
+      if (mv[j] && rv[i]) out[out_off[i] + (uint64_t)(mt * MT + j) * out_m_stride] = reduce128(hi[j][i], lo[j][i], c);
+}
+
+template <int MT, int RT>
+static hipError_t mac_go(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t CB, uint32_t S, uint32_t M,
+                         uint32_t L, uint32_t N, uint32_t rows, const LimbConst* lc, hipStream_t st) {
+  const uint32_t n_mt = (M + MT - 1) / MT, n_rt = (rows + RT - 1) / RT;
+  const uint64_t blocks = (uint64_t)L * (N / MAC_THREADS) * n_mt * n_rt;
+  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((mac_kernel<MT, RT>), dim3((uint32_t)blocks), dim3(MAC_THREADS), 0, st, in, w, out, CB, S, M,
+                     L, N, rows, n_mt, n_rt, lc);
+  return hipGetLastError();
+}
+
+hipError_t mac_launch(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t B, uint32_t CB, uint32_t S,
+                      uint32_t M, uint32_t L, uint32_t N, const LimbConst* lc, hipStream_t st) {
+  const uint32_t rows = B * S * 2;
+  if (rows >= 4) return mac_go<4, 4>(in, w, out, CB, S, M, L, N, rows, lc, st);
+  return mac_go<8, 2>(in, w, out, CB, S, M, L, N, rows, lc, st);
+}
+
+}  // namespace heconv

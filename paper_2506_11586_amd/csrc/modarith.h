@@ -1,0 +1,54 @@
+// Device-side 64-bit modular arithmetic for primes q < 2^61 (gfx950).
+//
+// Shoup multiplication by a fixed operand: for w < q and w' = floor(w*2^64/q),
+// any x < 2^64 gives r = x*w - umulhi(x, w')*q (mod 2^64) with r in [0, 2q)
+// (Harvey, "Faster arithmetic for number-theoretic transforms", 2014).  Only
+// the high half of x*w' and the low halves of x*w and hi*q are needed.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace heconv {
+
+// Per-limb constants kept on the device.
+struct LimbConst {
+  uint64_t q, two_q;
+  uint64_t ninv, ninv_sh;      // N^-1 mod q and its Shoup quotient
+  uint64_t ninv_w, ninv_w_sh;  // N^-1 * (last inverse twiddle) and quotient
+  uint64_t r64, r64_sh;        // 2^64 mod q and its Shoup quotient
+  uint64_t mu64;               // floor(2^64 / q): Shoup quotient of w = 1
+};
+
+// A twiddle with its Shoup quotient, stored side by side (one 16-byte load).
+struct Tw {
+  uint64_t w, wsh;
+};
+
+__device__ __forceinline__ uint64_t mul_shoup_lazy(uint64_t x, uint64_t w, uint64_t wsh, uint64_t q) {
+  uint64_t hi = __umul64hi(x, wsh);
+  return x * w - hi * q;  // in [0, 2q)
+}
+
+__device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
+
+// x < 2^64 reduced into [0, 2q) (Shoup with w = 1).
+__device__ __forceinline__ uint64_t reduce64_lazy(uint64_t x, uint64_t mu64, uint64_t q) {
+  return x - __umul64hi(x, mu64) * q;
+}
+
+// Full 64 x 64 -> 128-bit product as (hi, lo).
+__device__ __forceinline__ void mul_wide(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
+  lo = a * b;
+  hi = __umul64hi(a, b);
+}
+
+// 128-bit value (hi, lo) reduced mod q into [0, q): hi*2^64 = hi*(2^64 mod q).
+__device__ __forceinline__ uint64_t reduce128(uint64_t hi, uint64_t lo, const LimbConst& c) {
+  uint64_t a = mul_shoup_lazy(hi, c.r64, c.r64_sh, c.q);  // [0, 2q)
+  uint64_t b = reduce64_lazy(lo, c.mu64, c.q);            // [0, 2q)
+  uint64_t s = a + b;                                     // [0, 4q) < 2^63
+  s = csub(s, c.two_q);
+  return csub(s, c.q);
+}
+
+}  // namespace heconv

@@ -1,0 +1,226 @@
+"""ctypes binding of libheconv.so (include/heconv.h), argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; torch is used for
+device buffers and streams.  Device tensors are int64 (or uint64) torch
+tensors whose words are the residues; they are passed as raw pointers.
+The module fails loudly if the built library is missing: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libheconv.so")
+
+HE_OK, HE_EINVAL, HE_ESHAPE, HE_EPARAM, HE_ENOMEM, HE_EDEVICE, HE_EBUSY = 0, -1, -2, -3, -4, -5, -6
+
+
+class HeError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {_lib_handle().he_status_str(status).decode()} ({status})")
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_uint32), ("L", ctypes.c_uint32), ("q", ctypes.POINTER(ctypes.c_uint64)),
+                ("t", ctypes.c_uint64)]
+
+
+class ConvDesc(ctypes.Structure):
+    """he_conv_desc: C, H, W, M, kh, kw, stride, pad, Cw, Hw, Ww."""
+
+    _fields_ = [(n, ctypes.c_uint32) for n in ("C", "H", "W", "M", "kh", "kw", "stride", "pad", "Cw", "Hw", "Ww")]
+
+    def shape(self):
+        return (self.C, self.H, self.W, self.M, self.kh, self.kw, self.stride, self.pad)
+
+    def packing(self):
+        return (self.Cw, self.Hw, self.Ww)
+
+    def __repr__(self):
+        return "ConvDesc(" + ", ".join(f"{n}={getattr(self, n)}" for n, _ in self._fields_) + ")"
+
+
+_LIB = None
+
+
+def _lib_handle():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, u32, u64, vp = ctypes.POINTER, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
+        i32 = ctypes.c_int
+        L.he_status_str.argtypes = [i32]
+        L.he_status_str.restype = ctypes.c_char_p
+        L.he_gen_primes.argtypes = [u32, u32, u32, P(u64)]
+        L.he_ctx_create.argtypes = [P(_Params), P(vp)]
+        L.he_ctx_destroy.argtypes = [vp]
+        L.he_ctx_destroy.restype = None
+        L.he_ctx_psi.argtypes = [vp, P(u64)]
+        L.he_plan_conv.argtypes = [vp, P(ConvDesc), u32]
+        L.he_plan_conv_host.argtypes = [u32, u32, P(ConvDesc), u32]
+        L.he_min_root.argtypes = [u64, u32, P(u64)]
+        L.he_conv_sizes.argtypes = [vp, P(ConvDesc), P(u32), P(u32), P(u64), P(u64), P(u64)]
+        L.he_encode_weights.argtypes = [vp, P(ConvDesc), vp, vp, vp]
+        L.he_ntt_fwd.argtypes = [vp, vp, u64, vp]
+        L.he_ntt_inv.argtypes = [vp, vp, u64, vp]
+        L.he_conv_ntt_mac.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
+        L.he_conv_layer.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
+        for name in ("he_gen_primes", "he_ctx_create", "he_ctx_psi", "he_plan_conv", "he_plan_conv_host", "he_min_root", "he_conv_sizes",
+                     "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer"):
+            getattr(L, name).restype = i32
+        _LIB = L
+    return _LIB
+
+
+def lib():
+    """The loaded ctypes library (raises ImportError if it is not built)."""
+    return _lib_handle()
+
+
+def _check(status: int, what: str):
+    if status != HE_OK:
+        raise HeError(status, what)
+
+
+def gen_primes(N: int, bits: int, L: int) -> list[int]:
+    out = (ctypes.c_uint64 * L)()
+    _check(lib().he_gen_primes(N, bits, L, out), "he_gen_primes")
+    return [int(v) for v in out]
+
+
+def plan_host(N: int, L: int, shape, batch: int = 1) -> ConvDesc:
+    """The library's planner without a context (host only)."""
+    d = ConvDesc(*[int(v) for v in shape], 0, 0, 0)
+    _check(lib().he_plan_conv_host(int(N), int(L), ctypes.byref(d), int(batch)), "he_plan_conv_host")
+    return d
+
+
+def min_root(q: int, N: int) -> int:
+    """The library's choice of psi for (q, N) (host only)."""
+    out = ctypes.c_uint64()
+    _check(lib().he_min_root(int(q), int(N), ctypes.byref(out)), "he_min_root")
+    return int(out.value)
+
+
+def _ptr(t, words: int | None = None, what: str = "buffer") -> int:
+    """Raw device pointer of a contiguous 64-bit-word CUDA tensor."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: must be a device tensor")
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise TypeError(f"{what}: dtype must be int64/uint64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    if words is not None and t.numel() < words:
+        raise ValueError(f"{what}: needs {words} words, has {t.numel()}")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+@dataclass
+class Sizes:
+    CB: int
+    S: int
+    in_cts: int
+    out_cts: int
+    w_words: int
+
+
+class Context:
+    """he_ctx on the current device: parameters, roots and twiddle tables."""
+
+    def __init__(self, N: int, q: list[int], t: int = 2 ** 37):
+        self.N, self.L, self.q, self.t = int(N), len(q), [int(v) for v in q], int(t)
+        self._qarr = (ctypes.c_uint64 * self.L)(*self.q)
+        prm = _Params(self.N, self.L, self._qarr, self.t)
+        h = ctypes.c_void_p()
+        _check(lib().he_ctx_create(ctypes.byref(prm), ctypes.byref(h)), "he_ctx_create")
+        self._h = h
+        psi = (ctypes.c_uint64 * self.L)()
+        _check(lib().he_ctx_psi(self._h, psi), "he_ctx_psi")
+        self.psi = [int(v) for v in psi]
+
+    @classmethod
+    def from_bits(cls, N: int, L: int, bits: int, t: int = 2 ** 37) -> "Context":
+        return cls(N, gen_primes(N, bits, L), t)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().he_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- planning ----------------------------------------------------------
+    def plan(self, shape, batch: int = 1, packing=None) -> ConvDesc:
+        """Descriptor for a layer shape (C, H, W, M, kh, kw, stride, pad);
+        the planner fills the packing unless `packing` = (Cw, Hw, Ww)."""
+        d = ConvDesc(*[int(v) for v in shape], 0, 0, 0)
+        if packing is None:
+            _check(lib().he_plan_conv(self._h, ctypes.byref(d), int(batch)), "he_plan_conv")
+        else:
+            d.Cw, d.Hw, d.Ww = (int(v) for v in packing)
+        self.sizes(d)  # validates
+        return d
+
+    def sizes(self, d: ConvDesc) -> Sizes:
+        CB, S = ctypes.c_uint32(), ctypes.c_uint32()
+        i, o, w = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().he_conv_sizes(self._h, ctypes.byref(d), ctypes.byref(CB), ctypes.byref(S), ctypes.byref(i),
+                                   ctypes.byref(o), ctypes.byref(w)), "he_conv_sizes")
+        return Sizes(CB.value, S.value, i.value, o.value, w.value)
+
+    # -- the hot path ------------------------------------------------------
+    def encode_weights(self, d: ConvDesc, w_dev, wntt_dev, stream=None):
+        s = self.sizes(d)
+        nw = d.M * d.C * d.kh * d.kw
+        _check(lib().he_encode_weights(self._h, ctypes.byref(d), _ptr(w_dev, nw, "weights"),
+                                       _ptr(wntt_dev, s.w_words, "wntt"), _stream(stream)), "he_encode_weights")
+
+    def ntt_fwd(self, polys_dev, n: int | None = None, stream=None):
+        n = polys_dev.numel() // (self.L * self.N) if n is None else int(n)
+        _check(lib().he_ntt_fwd(self._h, _ptr(polys_dev, n * self.L * self.N, "polys"), n, _stream(stream)),
+               "he_ntt_fwd")
+
+    def ntt_inv(self, polys_dev, n: int | None = None, stream=None):
+        n = polys_dev.numel() // (self.L * self.N) if n is None else int(n)
+        _check(lib().he_ntt_inv(self._h, _ptr(polys_dev, n * self.L * self.N, "polys"), n, _stream(stream)),
+               "he_ntt_inv")
+
+    def conv_ntt_mac(self, d: ConvDesc, B: int, in_dev, wntt_dev, out_dev, stream=None):
+        s = self.sizes(d)
+        ct = 2 * self.L * self.N
+        _check(lib().he_conv_ntt_mac(self._h, ctypes.byref(d), int(B), _ptr(in_dev, B * s.in_cts * ct, "in"),
+                                     _ptr(wntt_dev, s.w_words, "wntt"), _ptr(out_dev, B * s.out_cts * ct, "out"),
+                                     _stream(stream)), "he_conv_ntt_mac")
+
+    def conv_layer(self, d: ConvDesc, B: int, in_dev, wntt_dev, out_dev, stream=None):
+        s = self.sizes(d)
+        ct = 2 * self.L * self.N
+        _check(lib().he_conv_layer(self._h, ctypes.byref(d), int(B), _ptr(in_dev, B * s.in_cts * ct, "in"),
+                                   _ptr(wntt_dev, s.w_words, "wntt"), _ptr(out_dev, B * s.out_cts * ct, "out"),
+                                   _stream(stream)), "he_conv_layer")

@@ -1,0 +1,187 @@
+"""GPU parity: every entry point of the C ABI against the CPU oracle.
+
+Bit-exact on every word (integer arithmetic mod q_l).  Inputs are seeded:
+uniform residues (a ciphertext is indistinguishable from uniform words) and,
+for the layer tests, real encryptions made by the oracle's client side, so
+the decrypted output can be compared with the plaintext integer conv."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import Stream
+from tests import workload as wl
+from tests.gpu_util import empty_words, require_gpu, to_dev, to_host
+from tests.libload import ensure_built
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = [(1024, 2, 50), (2048, 2, 60), (4096, 2, 50), (8192, 3, 60), (16384, 2, 60)]
+_cache = {}
+
+
+def ctx_and_prm(N, L, bits):
+    key = (N, L, bits)
+    if key not in _cache:
+        require_gpu()
+        ensure_built()
+        from paper_2506_11586_amd import heconv
+        prm = oracle.Params(N, L, bits, 2 ** 37)
+        ctx = heconv.Context(N, heconv.gen_primes(N, bits, L))
+        _cache[key] = (ctx, prm)
+    return _cache[key]
+
+
+def rand_polys(seed, n, prm):
+    return synth.uniform_mod(Stream(seed, synth.UNIFORM), (n, prm.L, prm.N), prm.q)
+
+
+@pytest.mark.parametrize("N,L,bits", PARAMS)
+def test_context_matches_oracle(N, L, bits):
+    ctx, prm = ctx_and_prm(N, L, bits)
+    assert ctx.q == prm.q and ctx.psi == prm.psi
+
+
+@pytest.mark.parametrize("N,L,bits", PARAMS)
+def test_ntt_forward_and_inverse(N, L, bits):
+    ctx, prm = ctx_and_prm(N, L, bits)
+    x = rand_polys(N + L, 3, prm)
+    x[2] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)  # all q-1: lazy-range edge
+    x[1, 0, :5] = [0, 1, 2, 3, 0]
+    want = oracle.ntt(x, prm)
+    d = to_dev(x)
+    ctx.ntt_fwd(d, 3)
+    got = to_host(d).reshape(x.shape)
+    assert np.array_equal(got, want)
+    ctx.ntt_inv(d, 3)
+    assert np.array_equal(to_host(d).reshape(x.shape), x)
+    # inverse of an independent NTT-domain input
+    y = rand_polys(N + L + 1, 2, prm)
+    d2 = to_dev(y)
+    ctx.ntt_inv(d2, 2)
+    assert np.array_equal(to_host(d2).reshape(y.shape), oracle.intt(y, prm))
+
+
+def test_ntt_zero_count_is_noop():
+    ctx, prm = ctx_and_prm(4096, 2, 50)
+    x = rand_polys(5, 1, prm)
+    d = to_dev(x)
+    ctx.ntt_fwd(d, 0)
+    ctx.ntt_inv(d, 0)
+    assert np.array_equal(to_host(d).reshape(x.shape), x)
+
+
+ENCODE_CASES = [
+    ((4, 16, 16, 4, 3, 3, 1, 1), (4096, 2, 50), None),
+    ((64, 56, 56, 64, 3, 3, 1, 1), (8192, 3, 60), None),
+    ((3, 23, 23, 5, 7, 7, 2, 3), (4096, 2, 50), None),
+    ((10, 9, 9, 3, 1, 1, 2, 0), (4096, 2, 50), (3, 5, 4)),
+]
+
+
+@pytest.mark.parametrize("shape,params,packing", ENCODE_CASES)
+def test_encode_weights(shape, params, packing):
+    ctx, prm = ctx_and_prm(*params)
+    cv = oracle.Conv(*shape)
+    d = ctx.plan(shape, packing=packing)
+    g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+    K = Stream(shape[0] * 7 + shape[3], synth.WEIGHT).ints(cv.M * cv.C * cv.kh * cv.kw, -2 ** 12, 2 ** 12)
+    K = K.reshape(cv.M, cv.C, cv.kh, cv.kw)
+    K.flat[0], K.flat[-1] = -(2 ** 63), 2 ** 63 - 1  # lifting extremes
+    K.flat[1] = -1
+    want = oracle.encode_weights(K, cv, g, prm)
+    s = ctx.sizes(d)
+    out = empty_words(s.w_words)
+    ctx.encode_weights(d, to_dev(K), out)
+    assert np.array_equal(to_host(out).reshape(want.shape), want)
+
+
+MAC_CASES = [  # (shape, params, packing, B)
+    ((4, 16, 16, 4, 3, 3, 1, 1), (4096, 2, 50), None, 1),
+    ((64, 56, 56, 64, 3, 3, 1, 1), (8192, 3, 60), None, 1),
+    ((5, 12, 12, 5, 3, 3, 1, 1), (4096, 2, 50), (1, 6, 9), 3),  # ragged M, odd row count
+    ((70, 6, 6, 3, 1, 1, 1, 0), (1024, 2, 50), (1, 6, 6), 2),  # CB = 70 > 32: 128-bit fold
+]
+
+
+@pytest.mark.parametrize("shape,params,packing,B", MAC_CASES)
+def test_conv_ntt_mac(shape, params, packing, B):
+    ctx, prm = ctx_and_prm(*params)
+    cv = oracle.Conv(*shape)
+    d = ctx.plan(shape, packing=packing)
+    g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+    x = rand_polys(11, B * g.CB * g.S * 2, prm)
+    w = rand_polys(12, cv.M * g.CB, prm)
+    if B == 2:  # all q-1: largest products and carries
+        x[:] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)
+        w[:] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)
+    want = oracle.conv_mac(x, w, B, g, cv.M, prm)
+    out = empty_words(want.size)
+    ctx.conv_ntt_mac(d, B, to_dev(x), to_dev(w), out)
+    assert np.array_equal(to_host(out).reshape(want.shape), want)
+
+
+def run_layer(cfg_id):
+    cfg = synth.CONFIGS[cfg_id]
+    shape = cfg["layers"][0]
+    ctx, prm = ctx_and_prm(cfg["N"], cfg["L"], cfg["bits"])
+    cv = wl.conv_of(shape)
+    d = ctx.plan(shape)
+    g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+    assert g == oracle.plan_conv(cv, prm.N, prm.L)
+    x, K = wl.draw_layer(cfg, shape)
+    sk = wl.secret_key(cfg["seed"], prm.N)
+    ct = wl.encrypt_input(x, cv, g, prm, cfg["seed"], sk)[None]
+    s = ctx.sizes(d)
+    wntt = empty_words(s.w_words)
+    ctx.encode_weights(d, to_dev(K), wntt)
+    d_in = to_dev(ct)
+    out = empty_words(s.out_cts * 2 * prm.L * prm.N)
+    ctx.conv_layer(d, 1, d_in, wntt, out)
+    got = to_host(out).reshape(1, cv.M, g.S, 2, prm.L, prm.N)
+    return cfg, cv, g, prm, x, K, sk, ct, got, to_host(d_in).reshape(ct.shape)
+
+
+def test_layer_cfg1_bit_exact_and_decrypts():
+    """4->4 3x3 @16x16, N=4096: every output word equals the layer by
+    definition (schoolbook products); decrypted slots = integer conv."""
+    cfg, cv, g, prm, x, K, sk, ct, got, in_after = run_layer(1)
+    wc = oracle.pack_weights(K, cv, g, prm)
+    assert np.array_equal(got, oracle.conv_layer_def(ct, wc, 1, g, cv.M, prm))
+    assert np.array_equal(in_after, oracle.ntt(ct, prm))  # d_in holds the NTT form afterwards
+    y = wl.decrypt_output(got[0], cv, g, prm, sk)
+    assert np.array_equal(y, oracle.plain_conv(x, K, 1, 1))
+
+
+def test_layer_cfg2_bit_exact_and_decrypts():
+    """64->64 3x3 @56x56, N=8192, L=3: every word equals the oracle's NTT
+    flow; sampled words equal the definition; decrypted slots = conv."""
+    cfg, cv, g, prm, x, K, sk, ct, got, _ = run_layer(2)
+    wc = oracle.pack_weights(K, cv, g, prm)
+    want = oracle.conv_layer_ntt(ct, oracle.ntt(wc, prm), 1, g, cv.M, prm)
+    assert np.array_equal(got, want)
+    rng = Stream(99, 7)
+    for _ in range(8):
+        m, s, c, l, k = (int(rng.below(1, v)[0]) for v in (cv.M, g.S, 2, prm.L, prm.N))
+        assert int(got[0, m, s, c, l, k]) == oracle.conv_layer_coeff(ct, wc, g, prm, 0, m, s, c, l, k)
+    y = wl.decrypt_output(got[0], cv, g, prm, sk)
+    assert np.array_equal(y, oracle.plain_conv(x, K, 1, 1))
+
+
+def test_error_statuses():
+    require_gpu()
+    ensure_built()
+    from paper_2506_11586_amd import heconv
+    with pytest.raises(heconv.HeError) as e:
+        heconv.Context(4096, [1125899906826241 + 8192])  # not prime
+    assert e.value.status == heconv.HE_EPARAM
+    with pytest.raises(heconv.HeError) as e:
+        heconv.Context(512, heconv.gen_primes(512, 50, 1))  # N below the supported range
+    assert e.value.status == heconv.HE_EPARAM
+    ctx, prm = ctx_and_prm(4096, 2, 50)
+    with pytest.raises(heconv.HeError) as e:
+        ctx.plan((4, 16, 16, 4, 3, 3, 1, 1), packing=(4, 40, 40))  # 4*40*40 > N
+    assert e.value.status == heconv.HE_ESHAPE
+    d = ctx.plan((4, 16, 16, 4, 3, 3, 1, 1))
+    st = heconv.lib().he_conv_layer(ctx.handle, heconv.ctypes.byref(d), 1, None, None, None, None)
+    assert st == heconv.HE_EINVAL

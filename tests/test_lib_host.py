@@ -1,0 +1,77 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every function include/heconv.h declares, and its host logic (prime
+search, root choice, planner) agrees with the oracle's independent code."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+import synth
+from tests.libload import ensure_built
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "heconv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(he_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    path = ensure_built()
+    lib = ctypes.CDLL(path)
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings():
+    ensure_built()
+    from paper_2506_11586_amd import heconv
+    for s in range(-6, 1):
+        assert heconv.lib().he_status_str(s).decode()
+
+
+@pytest.mark.parametrize("N,bits,L", [(4096, 50, 2), (8192, 60, 3), (1024, 40, 4), (16384, 61, 2)])
+def test_primes_and_roots_match_oracle(N, bits, L):
+    ensure_built()
+    from paper_2506_11586_amd import heconv
+    qs = heconv.gen_primes(N, bits, L)
+    assert qs == oracle.find_primes(N, bits, L)
+    for q in qs:
+        assert heconv.min_root(q, N) == oracle.find_psi(q, N)
+
+
+def test_bad_parameters_rejected():
+    ensure_built()
+    from paper_2506_11586_amd import heconv
+    with pytest.raises(heconv.HeError):
+        heconv.gen_primes(1000, 50, 2)  # N not a power of two
+    with pytest.raises(heconv.HeError):
+        heconv.min_root(1125899906826241 + 2, 4096)  # not 1 mod 2N
+    with pytest.raises(heconv.HeError):
+        heconv.plan_host(4096, 2, (4, 16, 16, 4, 0, 3, 1, 1))  # zero kernel height
+
+
+def all_shapes():
+    shapes = set()
+    for cfg in synth.CONFIGS.values():
+        for s in cfg["layers"]:
+            shapes.add((cfg["N"], cfg["L"], s))
+    return sorted(shapes)
+
+
+def test_planner_matches_oracle_on_every_workload_shape():
+    """Same descriptor from the library's planner and the oracle's, for every
+    layer of every workload, at batch 1 and 16."""
+    ensure_built()
+    from paper_2506_11586_amd import heconv
+    for N, L, s in all_shapes():
+        for B in (1, 16):
+            d = heconv.plan_host(N, L, s, B)
+            g = oracle.plan_conv(oracle.Conv(*s), N, L, B)
+            assert (d.Cw, d.Hw, d.Ww) == (g.Cw, g.Hw, g.Ww), (s, B)
