@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM counter scaling)")
     return ap.parse_args()
 
 
@@ -196,6 +198,14 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+
+    if args.copy_probe:
+        src = torch.ones(32 << 20, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_probe_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"], result["bit_exact"] = cpu_baseline(args, cfg, ctx, d, sz, x_host, K_host, gpu_out)

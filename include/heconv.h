@@ -95,6 +95,23 @@ he_status he_gen_primes(uint32_t N, uint32_t bits, uint32_t L, uint64_t* q_out);
 he_status he_ctx_create(const he_params* prm, he_ctx** out);
 void he_ctx_destroy(he_ctx* ctx);
 
+/* Launch-shape choices of a context (they change speed, never results).
+ * NTT: 2^ntt_loge_small words per thread (one workgroup of N/2^loge
+ * threads per limb polynomial) when a call transforms fewer than
+ * ntt_small_below limb polynomials, else 2^ntt_loge_large; loge is 3 or 4
+ * (3 is used only for N <= 2^13).  MAC: each thread accumulates mac_mt
+ * output channels x mac_rt ciphertext rows for one NTT point; (0, 0) picks
+ * by shape; supported pairs: (4,4) (8,2) (2,4) (4,2) (8,4) (2,8) (4,8) (1,8).
+ * Defaults: {3, 4, 512, 0, 0}. */
+typedef struct {
+  uint32_t ntt_loge_small, ntt_loge_large, ntt_small_below;
+  uint32_t mac_mt, mac_rt;
+} he_tuning;
+
+he_status he_ctx_get_tuning(const he_ctx* ctx, he_tuning* out);
+/* HE_EINVAL for an unsupported value; the context is then unchanged. */
+he_status he_ctx_set_tuning(he_ctx* ctx, const he_tuning* tuning);
+
 /* The roots chosen by the context: psi_out[0..L-1]. */
 he_status he_ctx_psi(const he_ctx* ctx, uint64_t* psi_out);
 

@@ -92,6 +92,7 @@ struct he_ctx {
   Tw* d_fwd = nullptr;  // [L][N] psi^brv(k) with Shoup quotient
   Tw* d_inv = nullptr;  // [L][N] psi^-brv(k) with Shoup quotient
   LimbConst* d_lc = nullptr;
+  he_tuning tune{3, 4, 512, 0, 0};
 };
 
 namespace {
@@ -125,6 +126,10 @@ bool geo_of(const he_conv_desc& d, uint32_t N, Geo& g) {
 }
 
 he_status check_ctx(const he_ctx* c) { return c ? HE_OK : HE_EINVAL; }
+
+uint32_t ntt_loge(const he_ctx* c, uint64_t n_rns_polys) {
+  return n_rns_polys * c->L < c->tune.ntt_small_below ? c->tune.ntt_loge_small : c->tune.ntt_loge_large;
+}
 
 he_status dev_err(hipError_t e) { return e == hipSuccess ? HE_OK : HE_EDEVICE; }
 
@@ -233,6 +238,24 @@ he_status he_ctx_psi(const he_ctx* c, uint64_t* psi_out) {
   return HE_OK;
 }
 
+he_status he_ctx_get_tuning(const he_ctx* c, he_tuning* out) {
+  if (check_ctx(c) || !out) return HE_EINVAL;
+  *out = c->tune;
+  return HE_OK;
+}
+
+he_status he_ctx_set_tuning(he_ctx* c, const he_tuning* t) {
+  if (check_ctx(c) || !t) return HE_EINVAL;
+  auto loge_ok = [](uint32_t v) { return v == 3 || v == 4; };
+  if (!loge_ok(t->ntt_loge_small) || !loge_ok(t->ntt_loge_large)) return HE_EINVAL;
+  static const uint32_t tiles[][2] = {{0, 0}, {4, 4}, {8, 2}, {2, 4}, {4, 2}, {8, 4}, {2, 8}, {4, 8}, {1, 8}};
+  bool ok = false;
+  for (auto& p : tiles) ok |= (p[0] == t->mac_mt && p[1] == t->mac_rt);
+  if (!ok) return HE_EINVAL;
+  c->tune = *t;
+  return HE_OK;
+}
+
 he_status he_plan_conv_host(uint32_t N, uint32_t L, he_conv_desc* io, uint32_t batch_hint) {
   if (!io) return HE_EINVAL;
   if (!pow2(N) || N < 2 || L == 0) return HE_EPARAM;
@@ -303,21 +326,22 @@ he_status he_encode_weights(const he_ctx* c, const he_conv_desc* d, const int64_
   hipStream_t st = (hipStream_t)stream;
   he_status s = dev_err(heconv::pack_weights_launch(pg, d_w, d_wntt, c->d_lc, st));
   if (s) return s;
-  return dev_err(heconv::ntt_launch(false, c->logN, d_wntt, (uint64_t)d->M * g.CB, c->L, c->d_fwd, c->d_lc, st));
+  return dev_err(heconv::ntt_launch(false, c->logN, ntt_loge(c, (uint64_t)d->M * g.CB), d_wntt,
+                                    (uint64_t)d->M * g.CB, c->L, c->d_fwd, c->d_lc, st));
 }
 
 he_status he_ntt_fwd(const he_ctx* c, uint64_t* d_polys, uint64_t n, void* stream) {
   if (check_ctx(c)) return HE_EINVAL;
   if (n == 0) return HE_OK;
   if (!d_polys) return HE_EINVAL;
-  return dev_err(heconv::ntt_launch(false, c->logN, d_polys, n, c->L, c->d_fwd, c->d_lc, (hipStream_t)stream));
+  return dev_err(heconv::ntt_launch(false, c->logN, ntt_loge(c, n), d_polys, n, c->L, c->d_fwd, c->d_lc, (hipStream_t)stream));
 }
 
 he_status he_ntt_inv(const he_ctx* c, uint64_t* d_polys, uint64_t n, void* stream) {
   if (check_ctx(c)) return HE_EINVAL;
   if (n == 0) return HE_OK;
   if (!d_polys) return HE_EINVAL;
-  return dev_err(heconv::ntt_launch(true, c->logN, d_polys, n, c->L, c->d_inv, c->d_lc, (hipStream_t)stream));
+  return dev_err(heconv::ntt_launch(true, c->logN, ntt_loge(c, n), d_polys, n, c->L, c->d_inv, c->d_lc, (hipStream_t)stream));
 }
 
 he_status he_conv_ntt_mac(const he_ctx* c, const he_conv_desc* d, uint32_t B, const uint64_t* d_in_ntt,
@@ -329,7 +353,7 @@ he_status he_conv_ntt_mac(const he_ctx* c, const he_conv_desc* d, uint32_t B, co
   if (!d_in_ntt || !d_wntt || !d_out_ntt) return HE_EINVAL;
   if ((uint64_t)B * g.S * 2 > 0xffffffffull) return HE_ESHAPE;
   return dev_err(heconv::mac_launch(d_in_ntt, d_wntt, d_out_ntt, B, g.CB, g.S, d->M, c->L, c->N, c->d_lc,
-                                    (hipStream_t)stream));
+                                    c->tune.mac_mt, c->tune.mac_rt, (hipStream_t)stream));
 }
 
 he_status he_conv_layer(const he_ctx* c, const he_conv_desc* d, uint32_t B, uint64_t* d_in, const uint64_t* d_wntt,

@@ -8,9 +8,10 @@
 namespace heconv {
 
 // Forward (inverse = false) or inverse NTT, in place, of n_rns_polys RNS
-// polynomials [n][L][N], N = 2^logN, logN in [10, 14].
-hipError_t ntt_launch(bool inverse, uint32_t logN, uint64_t* polys, uint64_t n_rns_polys, uint32_t L, const Tw* tw,
-                      const LimbConst* lc, hipStream_t st);
+// polynomials [n][L][N], N = 2^logN, logN in [10, 14]; 2^loge words per
+// thread (loge 3 or 4; 3 needs logN <= 13, else 4 is used).
+hipError_t ntt_launch(bool inverse, uint32_t logN, uint32_t loge, uint64_t* polys, uint64_t n_rns_polys, uint32_t L,
+                      const Tw* tw, const LimbConst* lc, hipStream_t st);
 
 // Geometry of a planned conv as the kernels need it.
 struct PackGeom {
@@ -22,7 +23,9 @@ hipError_t pack_weights_launch(const PackGeom& g, const int64_t* w, uint64_t* ou
                                hipStream_t st);
 
 // out[b][m][s][c][l][k] = sum_cb in[b][cb][s][c][l][k] * w[m][cb][l][k] mod q_l.
+// (mt, rt): output channels x rows per thread; (0, 0) picks by shape.
 hipError_t mac_launch(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t B, uint32_t CB, uint32_t S,
-                      uint32_t M, uint32_t L, uint32_t N, const LimbConst* lc, hipStream_t st);
+                      uint32_t M, uint32_t L, uint32_t N, const LimbConst* lc, uint32_t mt, uint32_t rt,
+                      hipStream_t st);
 
 }  // namespace heconv

@@ -93,7 +93,8 @@ __global__ __launch_bounds__(MAC_THREADS) void mac_kernel(const uint64_t* __rest
   const uint64_t LN = (uint64_t)L * N;
 
   // row r = (b*S + s)*2 + comp; input address of (r, cb) and output of (r, m)
-  uint64_t in_off[RT], out_off[RT];
+  const uint64_t* ip[RT];
+  uint64_t out_off[RT];
   bool rv[RT];
 #pragma unroll
   for (int i = 0; i < RT; i++) {
@@ -102,18 +103,18 @@ __global__ __launch_bounds__(MAC_THREADS) void mac_kernel(const uint64_t* __rest
     const uint32_t rr = rv[i] ? r : 0;
     const uint32_t comp = rr & 1, bs = rr >> 1;
     const uint32_t b = bs / S, s = bs % S;
-    in_off[i] = ((((uint64_t)b * CB) * S + s) * 2 + comp) * LN + (uint64_t)l * N + k;
+    ip[i] = in + ((((uint64_t)b * CB) * S + s) * 2 + comp) * LN + (uint64_t)l * N + k;
     out_off[i] = ((((uint64_t)b * M) * S + s) * 2 + comp) * LN + (uint64_t)l * N + k;
   }
   const uint64_t in_cb_stride = (uint64_t)S * 2 * LN;  // cb -> cb+1 in the input
   const uint64_t out_m_stride = (uint64_t)S * 2 * LN;  // m -> m+1 in the output
   bool mv[MT];
-  uint64_t w_off[MT];
+  const uint64_t* wp[MT];
 #pragma unroll
   for (int j = 0; j < MT; j++) {
     const uint32_t m = mt * MT + j;
     mv[j] = m < M;
-    w_off[j] = ((uint64_t)(mv[j] ? m : 0) * CB) * LN + (uint64_t)l * N + k;
+    wp[j] = w + ((uint64_t)(mv[j] ? m : 0) * CB) * LN + (uint64_t)l * N + k;
   }
 
   uint64_t hi[MT][RT], lo[MT][RT];
@@ -122,25 +123,30 @@ __global__ __launch_bounds__(MAC_THREADS) void mac_kernel(const uint64_t* __rest
 #pragma unroll
     for (int i = 0; i < RT; i++) hi[j][i] = lo[j][i] = 0;
 
-  for (uint32_t cb0 = 0; cb0 < CB; cb0 += 32) {
-    const uint32_t cb1 = cb0 + 32 < CB ? cb0 + 32 : CB;
-    for (uint32_t cb = cb0; cb < cb1; cb++) {
-      uint64_t xv[RT], wv[MT];
+  // software pipeline: the loads of channel block cb+1 are issued before the
+  // products of block cb
+  uint64_t xv[RT], wv[MT];
 #pragma unroll
-      for (int i = 0; i < RT; i++) xv[i] = rv[i] ? in[in_off[i] + cb * in_cb_stride] : 0;
+  for (int i = 0; i < RT; i++) xv[i] = rv[i] ? ip[i][0] : 0;
 #pragma unroll
-      for (int j = 0; j < MT; j++) wv[j] = mv[j] ? w[w_off[j] + (uint64_t)cb * LN] : 0;
+  for (int j = 0; j < MT; j++) wv[j] = mv[j] ? wp[j][0] : 0;
+  for (uint32_t cb = 0; cb < CB; cb++) {
+    uint64_t xn[RT], wn[MT];
+    const bool more = cb + 1 < CB;
 #pragma unroll
-      for (int j = 0; j < MT; j++)
+    for (int i = 0; i < RT; i++) xn[i] = (more && rv[i]) ? ip[i][(uint64_t)(cb + 1) * in_cb_stride] : 0;
 #pragma unroll
-        for (int i = 0; i < RT; i++) {
-          uint64_t ph, pl;
-          mul_wide(xv[i], wv[j], ph, pl);
-          lo[j][i] += pl;
-          hi[j][i] += ph + (lo[j][i] < pl ? 1 : 0);
-        }
-    }
-    if (cb1 < CB) {  // fold the 128-bit sums before they can overflow
+    for (int j = 0; j < MT; j++) wn[j] = (more && mv[j]) ? wp[j][(uint64_t)(cb + 1) * LN] : 0;
+#pragma unroll
+    for (int j = 0; j < MT; j++)
+#pragma unroll
+      for (int i = 0; i < RT; i++) {
+        uint64_t ph, pl;
+        mul_wide(xv[i], wv[j], ph, pl);
+        lo[j][i] += pl;
+        hi[j][i] += ph + (lo[j][i] < pl ? 1 : 0);
+      }
+    if ((cb & 31) == 31 && more) {  // fold the 128-bit sums before they can overflow
 #pragma unroll
       for (int j = 0; j < MT; j++)
 #pragma unroll
@@ -149,6 +155,10 @@ __global__ __launch_bounds__(MAC_THREADS) void mac_kernel(const uint64_t* __rest
           hi[j][i] = 0;
         }
     }
+#pragma unroll
+    for (int i = 0; i < RT; i++) xv[i] = xn[i];
+#pragma unroll
+    for (int j = 0; j < MT; j++) wv[j] = wn[j];
   }
 #pragma unroll
   for (int j = 0; j < MT; j++)
@@ -169,10 +179,25 @@ static hipError_t mac_go(const uint64_t* in, const uint64_t* w, uint64_t* out, u
 }
 
 hipError_t mac_launch(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t B, uint32_t CB, uint32_t S,
-                      uint32_t M, uint32_t L, uint32_t N, const LimbConst* lc, hipStream_t st) {
+                      uint32_t M, uint32_t L, uint32_t N, const LimbConst* lc, uint32_t mt, uint32_t rt,
+                      hipStream_t st) {
   const uint32_t rows = B * S * 2;
-  if (rows >= 4) return mac_go<4, 4>(in, w, out, CB, S, M, L, N, rows, lc, st);
-  return mac_go<8, 2>(in, w, out, CB, S, M, L, N, rows, lc, st);
+  if (mt == 0 || rt == 0) {  // default tile by shape
+    if (rows >= 4) mt = 4, rt = 4;
+    else mt = 8, rt = 2;
+  }
+#define HECONV_MAC_TILE(A, Bt) \
+  if (mt == A && rt == Bt) return mac_go<A, Bt>(in, w, out, CB, S, M, L, N, rows, lc, st);
+  HECONV_MAC_TILE(4, 4)
+  HECONV_MAC_TILE(8, 2)
+  HECONV_MAC_TILE(2, 4)
+  HECONV_MAC_TILE(4, 2)
+  HECONV_MAC_TILE(8, 4)
+  HECONV_MAC_TILE(2, 8)
+  HECONV_MAC_TILE(4, 8)
+  HECONV_MAC_TILE(1, 8)
+#undef HECONV_MAC_TILE
+  return hipErrorInvalidValue;
 }
 
 }  // namespace heconv

@@ -24,6 +24,16 @@ class HeError(RuntimeError):
         super().__init__(f"{what}: {_lib_handle().he_status_str(status).decode()} ({status})")
 
 
+class Tuning(ctypes.Structure):
+    """he_tuning: launch-shape choices (speed only, never results)."""
+
+    _fields_ = [(n, ctypes.c_uint32) for n in ("ntt_loge_small", "ntt_loge_large", "ntt_small_below",
+                                               "mac_mt", "mac_rt")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_uint32), ("L", ctypes.c_uint32), ("q", ctypes.POINTER(ctypes.c_uint64)),
                 ("t", ctypes.c_uint64)]
@@ -62,6 +72,8 @@ def _lib_handle():
         L.he_ctx_destroy.argtypes = [vp]
         L.he_ctx_destroy.restype = None
         L.he_ctx_psi.argtypes = [vp, P(u64)]
+        L.he_ctx_get_tuning.argtypes = [vp, P(Tuning)]
+        L.he_ctx_set_tuning.argtypes = [vp, P(Tuning)]
         L.he_plan_conv.argtypes = [vp, P(ConvDesc), u32]
         L.he_plan_conv_host.argtypes = [u32, u32, P(ConvDesc), u32]
         L.he_min_root.argtypes = [u64, u32, P(u64)]
@@ -71,7 +83,7 @@ def _lib_handle():
         L.he_ntt_inv.argtypes = [vp, vp, u64, vp]
         L.he_conv_ntt_mac.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
         L.he_conv_layer.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
-        for name in ("he_gen_primes", "he_ctx_create", "he_ctx_psi", "he_plan_conv", "he_plan_conv_host", "he_min_root", "he_conv_sizes",
+        for name in ("he_gen_primes", "he_ctx_create", "he_ctx_psi", "he_ctx_get_tuning", "he_ctx_set_tuning", "he_plan_conv", "he_plan_conv_host", "he_min_root", "he_conv_sizes",
                      "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer"):
             getattr(L, name).restype = i32
         _LIB = L
@@ -174,6 +186,20 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    # -- launch-shape tuning ----------------------------------------------
+    def get_tuning(self) -> Tuning:
+        t = Tuning()
+        _check(lib().he_ctx_get_tuning(self._h, ctypes.byref(t)), "he_ctx_get_tuning")
+        return t
+
+    def set_tuning(self, **kw) -> Tuning:
+        """Change named fields of the tuning (others keep their value)."""
+        t = self.get_tuning()
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _check(lib().he_ctx_set_tuning(self._h, ctypes.byref(t)), "he_ctx_set_tuning")
+        return t
 
     # -- planning ----------------------------------------------------------
     def plan(self, shape, batch: int = 1, packing=None) -> ConvDesc:

@@ -42,9 +42,12 @@ def test_context_matches_oracle(N, L, bits):
     assert ctx.q == prm.q and ctx.psi == prm.psi
 
 
+@pytest.mark.parametrize("loge", [3, 4])
 @pytest.mark.parametrize("N,L,bits", PARAMS)
-def test_ntt_forward_and_inverse(N, L, bits):
+def test_ntt_forward_and_inverse(N, L, bits, loge):
+    """Both launch shapes (8 or 16 words per thread) against the oracle."""
     ctx, prm = ctx_and_prm(N, L, bits)
+    ctx.set_tuning(ntt_loge_small=loge, ntt_loge_large=loge)
     x = rand_polys(N + L, 3, prm)
     x[2] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)  # all q-1: lazy-range edge
     x[1, 0, :5] = [0, 1, 2, 3, 0]
@@ -60,6 +63,7 @@ def test_ntt_forward_and_inverse(N, L, bits):
     d2 = to_dev(y)
     ctx.ntt_inv(d2, 2)
     assert np.array_equal(to_host(d2).reshape(y.shape), oracle.intt(y, prm))
+    ctx.set_tuning(ntt_loge_small=3, ntt_loge_large=4)
 
 
 def test_ntt_zero_count_is_noop():
@@ -104,8 +108,12 @@ MAC_CASES = [  # (shape, params, packing, B)
 ]
 
 
+MAC_TILES = [(0, 0), (4, 4), (8, 2), (2, 4), (4, 2), (8, 4), (2, 8), (4, 8), (1, 8)]
+
+
 @pytest.mark.parametrize("shape,params,packing,B", MAC_CASES)
 def test_conv_ntt_mac(shape, params, packing, B):
+    """Every supported MAC tile against the oracle."""
     ctx, prm = ctx_and_prm(*params)
     cv = oracle.Conv(*shape)
     d = ctx.plan(shape, packing=packing)
@@ -116,9 +124,14 @@ def test_conv_ntt_mac(shape, params, packing, B):
         x[:] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)
         w[:] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)
     want = oracle.conv_mac(x, w, B, g, cv.M, prm)
-    out = empty_words(want.size)
-    ctx.conv_ntt_mac(d, B, to_dev(x), to_dev(w), out)
-    assert np.array_equal(to_host(out).reshape(want.shape), want)
+    dx, dw = to_dev(x), to_dev(w)
+    for mt, rt in MAC_TILES:
+        ctx.set_tuning(mac_mt=mt, mac_rt=rt)
+        out = empty_words(want.size)
+        out.fill_(-1)
+        ctx.conv_ntt_mac(d, B, dx, dw, out)
+        assert np.array_equal(to_host(out).reshape(want.shape), want), (mt, rt)
+    ctx.set_tuning(mac_mt=0, mac_rt=0)
 
 
 def run_layer(cfg_id):
@@ -185,3 +198,9 @@ def test_error_statuses():
     d = ctx.plan((4, 16, 16, 4, 3, 3, 1, 1))
     st = heconv.lib().he_conv_layer(ctx.handle, heconv.ctypes.byref(d), 1, None, None, None, None)
     assert st == heconv.HE_EINVAL
+    before = ctx.get_tuning().as_dict()
+    for bad in (dict(ntt_loge_small=5), dict(mac_mt=3, mac_rt=3)):
+        with pytest.raises(heconv.HeError) as e:
+            ctx.set_tuning(**bad)
+        assert e.value.status == heconv.HE_EINVAL
+    assert ctx.get_tuning().as_dict() == before
