@@ -49,7 +49,7 @@ typedef enum {
 
 /* BFV/RNS parameters.  N: ring degree, a power of two in [2^10, 2^14].
  * L: number of RNS limbs, 1..8.  q[0..L-1]: distinct primes, q_l = 1 mod 2N,
- * q_l < 2^61.  t: plaintext modulus (informational; the server-side path
+ * 2^30 < q_l < 2^60 (the MAC splits residues into 30-bit halves).  t: plaintext modulus (informational; the server-side path
  * does not depend on it). */
 typedef struct {
   uint32_t N, L;
@@ -84,7 +84,7 @@ const char* he_status_str(he_status s);
 
 /* The L largest primes below 2^bits that are 1 mod 2N, in descending order,
  * written to q_out[0..L-1].  HE_EPARAM if N is not a power of two, bits is
- * outside [20, 61], or fewer than L such primes exist. */
+ * outside [20, 60], or fewer than L such primes exist. */
 he_status he_gen_primes(uint32_t N, uint32_t bits, uint32_t L, uint64_t* q_out);
 
 /* Create a context on the current HIP device: checks the parameters, picks
@@ -101,7 +101,7 @@ void he_ctx_destroy(he_ctx* ctx);
  * ntt_small_below limb polynomials, else 2^ntt_loge_large; loge is 3 or 4
  * (3 is used only for N <= 2^13).  MAC: each thread accumulates mac_mt
  * output channels x mac_rt ciphertext rows for one NTT point; (0, 0) picks
- * by shape; supported pairs: (4,4) (8,2) (2,4) (4,2) (8,4) (2,8) (4,8) (1,8).
+ * by shape; supported pairs: (4,4) (4,2) (2,4) (8,2) (2,8) (8,1) (1,8) (2,2).
  * Defaults: {3, 4, 512, 0, 0}. */
 typedef struct {
   uint32_t ntt_loge_small, ntt_loge_large, ntt_small_below;

@@ -151,7 +151,7 @@ const char* he_status_str(he_status s) {
 }
 
 he_status he_gen_primes(uint32_t N, uint32_t bits, uint32_t L, uint64_t* q_out) {
-  if (!q_out || !pow2(N) || N < 2 || bits < 20 || bits > 61 || L == 0) return HE_EPARAM;
+  if (!q_out || !pow2(N) || N < 2 || bits < 20 || bits > 60 || L == 0) return HE_EPARAM;
   const uint64_t m = 2ull * N;
   uint64_t c = ((1ull << bits) - 2) / m * m + 1;  // largest value below 2^bits that is 1 mod 2N
   uint32_t got = 0;
@@ -167,7 +167,7 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
   if (!pow2(N) || N < (1u << 10) || N > (1u << 14) || L == 0 || L > 8) return HE_EPARAM;
   for (uint32_t l = 0; l < L; l++) {
     const uint64_t q = prm->q[l];
-    if (q >= (1ull << 61) || q % (2ull * N) != 1 || !prime64(q)) return HE_EPARAM;
+    if (q >= (1ull << 60) || q % (2ull * N) != 1 || !prime64(q)) return HE_EPARAM;
     for (uint32_t j = 0; j < l; j++)
       if (prm->q[j] == q) return HE_EPARAM;
   }
@@ -206,6 +206,8 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
     k.ninv_w = mmul(k.ninv, inv[(size_t)l * N + 1].w, q), k.ninv_w_sh = shoup(k.ninv_w, q);
     k.r64 = (uint64_t)(((u128)1 << 64) % q), k.r64_sh = shoup(k.r64, q);
     k.mu64 = (uint64_t)(((u128)1 << 64) / q);
+    k.c30 = (uint64_t)(((u128)1 << 30) % q), k.c30_sh = shoup(k.c30, q);
+    k.c60 = (uint64_t)(((u128)1 << 60) % q), k.c60_sh = shoup(k.c60, q);
     c->lc.push_back(k);
   }
   const size_t tb = sizeof(Tw) * (size_t)L * N;
@@ -248,7 +250,7 @@ he_status he_ctx_set_tuning(he_ctx* c, const he_tuning* t) {
   if (check_ctx(c) || !t) return HE_EINVAL;
   auto loge_ok = [](uint32_t v) { return v == 3 || v == 4; };
   if (!loge_ok(t->ntt_loge_small) || !loge_ok(t->ntt_loge_large)) return HE_EINVAL;
-  static const uint32_t tiles[][2] = {{0, 0}, {4, 4}, {8, 2}, {2, 4}, {4, 2}, {8, 4}, {2, 8}, {4, 8}, {1, 8}};
+  static const uint32_t tiles[][2] = {{0, 0}, {4, 4}, {4, 2}, {2, 4}, {8, 2}, {2, 8}, {8, 1}, {1, 8}, {2, 2}};
   bool ok = false;
   for (auto& p : tiles) ok |= (p[0] == t->mac_mt && p[1] == t->mac_rt);
   if (!ok) return HE_EINVAL;

@@ -56,22 +56,47 @@ hipError_t pack_weights_launch(const PackGeom& g, const int64_t* w, uint64_t* ou
 // ---------------------------------------------------------------------------
 // MAC over channel blocks.  Every NTT point (l, k) is an independent small
 // product Out[(b,s,c), m] = sum_cb In[(b,s,c), cb] * W[cb, m] mod q_l.  A
-// thread owns one k for a tile of MT output channels x RT rows (b, s, c)
-// and accumulates the 128-bit products exactly in registers, reducing once
-// per output (and every 32 terms, so the sum never overflows 128 bits with
-// q < 2^61).  Consecutive lanes take consecutive k: every load and store is
-// a coalesced 512-byte wave access.
+// thread owns one k for a tile of MT output channels x RT rows (b, s, c).
+// Each operand is split into 30-bit halves and the four partial products
+// are accumulated exactly in 64-bit registers (16 channel blocks per
+// accumulator), then folded mod q once per 16 blocks.  Consecutive lanes
+// take consecutive k: every load and store is a coalesced 512-byte wave
+// access.
 // ---------------------------------------------------------------------------
 constexpr int MAC_THREADS = 256;
+constexpr uint32_t MAC_CHUNK = 16;
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Remap so that
 // consecutive tile ids land on one XCD: the tiles of one k-chunk (which
-// read the same input words) then share that XCD's L2.
+// read the same input and weight words) then share that XCD's L2.
 __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
   const uint32_t full = nblocks / 8 * 8;
   if (bid >= full) return bid;
   const uint32_t per = full / 8;
   return (bid % 8) * per + bid / 8;
+}
+
+constexpr int MAC_DEPTH = 4;
+
+// One channel block: the four 30-bit partial products of every (m, row).
+template <int MT, int RT>
+__device__ __forceinline__ void mac_step(const uint64_t (&xr)[RT], const uint64_t (&wr)[MT], uint64_t (&a00)[MT][RT],
+                                         uint64_t (&a01)[MT][RT], uint64_t (&a10)[MT][RT],
+                                         uint64_t (&a11)[MT][RT]) {
+  Half30 xs[RT], ws[MT];
+#pragma unroll
+  for (int i = 0; i < RT; i++) xs[i] = split30(xr[i]);
+#pragma unroll
+  for (int j = 0; j < MT; j++) ws[j] = split30(wr[j]);
+#pragma unroll
+  for (int j = 0; j < MT; j++)
+#pragma unroll
+    for (int i = 0; i < RT; i++) {
+      a00[j][i] += (uint64_t)xs[i].lo * ws[j].lo;
+      a01[j][i] += (uint64_t)xs[i].lo * ws[j].hi;
+      a10[j][i] += (uint64_t)xs[i].hi * ws[j].lo;
+      a11[j][i] += (uint64_t)xs[i].hi * ws[j].hi;
+    }
 }
 
 template <int MT, int RT>
@@ -117,54 +142,55 @@ __global__ __launch_bounds__(MAC_THREADS) void mac_kernel(const uint64_t* __rest
     wp[j] = w + ((uint64_t)(mv[j] ? m : 0) * CB) * LN + (uint64_t)l * N + k;
   }
 
-  uint64_t hi[MT][RT], lo[MT][RT];
+  uint64_t res[MT][RT];
 #pragma unroll
   for (int j = 0; j < MT; j++)
 #pragma unroll
-    for (int i = 0; i < RT; i++) hi[j][i] = lo[j][i] = 0;
+    for (int i = 0; i < RT; i++) res[j][i] = 0;
 
-  // software pipeline: the loads of channel block cb+1 are issued before the
-  // products of block cb
-  uint64_t xv[RT], wv[MT];
-#pragma unroll
-  for (int i = 0; i < RT; i++) xv[i] = rv[i] ? ip[i][0] : 0;
-#pragma unroll
-  for (int j = 0; j < MT; j++) wv[j] = mv[j] ? wp[j][0] : 0;
-  for (uint32_t cb = 0; cb < CB; cb++) {
-    uint64_t xn[RT], wn[MT];
-    const bool more = cb + 1 < CB;
-#pragma unroll
-    for (int i = 0; i < RT; i++) xn[i] = (more && rv[i]) ? ip[i][(uint64_t)(cb + 1) * in_cb_stride] : 0;
-#pragma unroll
-    for (int j = 0; j < MT; j++) wn[j] = (more && mv[j]) ? wp[j][(uint64_t)(cb + 1) * LN] : 0;
+  // Rows and channels past the end read row 0 / channel 0 (valid memory);
+  // their sums are never stored, so every load is unconditional.
+  for (uint32_t cb0 = 0; cb0 < CB; cb0 += MAC_CHUNK) {
+    const uint32_t cb1 = cb0 + MAC_CHUNK < CB ? cb0 + MAC_CHUNK : CB;
+    uint64_t a00[MT][RT], a01[MT][RT], a10[MT][RT], a11[MT][RT];
 #pragma unroll
     for (int j = 0; j < MT; j++)
 #pragma unroll
-      for (int i = 0; i < RT; i++) {
-        uint64_t ph, pl;
-        mul_wide(xv[i], wv[j], ph, pl);
-        lo[j][i] += pl;
-        hi[j][i] += ph + (lo[j][i] < pl ? 1 : 0);
+      for (int i = 0; i < RT; i++) a00[j][i] = a01[j][i] = a10[j][i] = a11[j][i] = 0;
+    uint32_t cb = cb0;
+    // MAC_DEPTH channel blocks per step: all their loads are issued before
+    // the first product, so that many loads per thread are in flight
+    for (; cb + MAC_DEPTH <= cb1; cb += MAC_DEPTH) {
+      uint64_t xr[MAC_DEPTH][RT], wr[MAC_DEPTH][MT];
+#pragma unroll
+      for (int d = 0; d < MAC_DEPTH; d++) {
+#pragma unroll
+        for (int i = 0; i < RT; i++) xr[d][i] = ip[i][(uint64_t)(cb + d) * in_cb_stride];
+#pragma unroll
+        for (int j = 0; j < MT; j++) wr[d][j] = wp[j][(uint64_t)(cb + d) * LN];
       }
-    if ((cb & 31) == 31 && more) {  // fold the 128-bit sums before they can overflow
 #pragma unroll
-      for (int j = 0; j < MT; j++)
+      for (int d = 0; d < MAC_DEPTH; d++) mac_step<MT, RT>(xr[d], wr[d], a00, a01, a10, a11);
+    }
+    for (; cb < cb1; cb++) {
+      uint64_t xr[RT], wr[MT];
 #pragma unroll
-        for (int i = 0; i < RT; i++) {
-          lo[j][i] = reduce128(hi[j][i], lo[j][i], c);
-          hi[j][i] = 0;
-        }
+      for (int i = 0; i < RT; i++) xr[i] = ip[i][(uint64_t)cb * in_cb_stride];
+#pragma unroll
+      for (int j = 0; j < MT; j++) wr[j] = wp[j][(uint64_t)cb * LN];
+      mac_step<MT, RT>(xr, wr, a00, a01, a10, a11);
     }
 #pragma unroll
-    for (int i = 0; i < RT; i++) xv[i] = xn[i];
+    for (int j = 0; j < MT; j++)
 #pragma unroll
-    for (int j = 0; j < MT; j++) wv[j] = wn[j];
+      for (int i = 0; i < RT; i++)
+        res[j][i] = csub(res[j][i] + fold30(a00[j][i], a01[j][i], a10[j][i], a11[j][i], c), c.q);
   }
 #pragma unroll
   for (int j = 0; j < MT; j++)
 #pragma unroll
     for (int i = 0; i < RT; i++)
-      if (mv[j] && rv[i]) out[out_off[i] + (uint64_t)(mt * MT + j) * out_m_stride] = reduce128(hi[j][i], lo[j][i], c);
+      if (mv[j] && rv[i]) out[out_off[i] + (uint64_t)(mt * MT + j) * out_m_stride] = res[j][i];
 }
 
 template <int MT, int RT>
@@ -183,19 +209,19 @@ hipError_t mac_launch(const uint64_t* in, const uint64_t* w, uint64_t* out, uint
                       hipStream_t st) {
   const uint32_t rows = B * S * 2;
   if (mt == 0 || rt == 0) {  // default tile by shape
-    if (rows >= 4) mt = 4, rt = 4;
-    else mt = 8, rt = 2;
+    if (rows >= 4 && M >= 4) mt = 4, rt = 4;
+    else mt = 2, rt = 2;
   }
 #define HECONV_MAC_TILE(A, Bt) \
   if (mt == A && rt == Bt) return mac_go<A, Bt>(in, w, out, CB, S, M, L, N, rows, lc, st);
   HECONV_MAC_TILE(4, 4)
-  HECONV_MAC_TILE(8, 2)
-  HECONV_MAC_TILE(2, 4)
   HECONV_MAC_TILE(4, 2)
-  HECONV_MAC_TILE(8, 4)
+  HECONV_MAC_TILE(2, 4)
+  HECONV_MAC_TILE(8, 2)
   HECONV_MAC_TILE(2, 8)
-  HECONV_MAC_TILE(4, 8)
+  HECONV_MAC_TILE(8, 1)
   HECONV_MAC_TILE(1, 8)
+  HECONV_MAC_TILE(2, 2)
 #undef HECONV_MAC_TILE
   return hipErrorInvalidValue;
 }

@@ -1,4 +1,4 @@
-// Device-side 64-bit modular arithmetic for primes q < 2^61 (gfx950).
+// Device-side 64-bit modular arithmetic for primes q < 2^60 (gfx950).
 //
 // Shoup multiplication by a fixed operand: for w < q and w' = floor(w*2^64/q),
 // any x < 2^64 gives r = x*w - umulhi(x, w')*q (mod 2^64) with r in [0, 2q)
@@ -17,6 +17,8 @@ struct LimbConst {
   uint64_t ninv_w, ninv_w_sh;  // N^-1 * (last inverse twiddle) and quotient
   uint64_t r64, r64_sh;        // 2^64 mod q and its Shoup quotient
   uint64_t mu64;               // floor(2^64 / q): Shoup quotient of w = 1
+  uint64_t c30, c30_sh;        // 2^30 mod q and its Shoup quotient
+  uint64_t c60, c60_sh;        // 2^60 mod q and its Shoup quotient
 };
 
 // A twiddle with its Shoup quotient, stored side by side (one 16-byte load).
@@ -47,6 +49,30 @@ __device__ __forceinline__ uint64_t reduce128(uint64_t hi, uint64_t lo, const Li
   uint64_t a = mul_shoup_lazy(hi, c.r64, c.r64_sh, c.q);  // [0, 2q)
   uint64_t b = reduce64_lazy(lo, c.mu64, c.q);            // [0, 2q)
   uint64_t s = a + b;                                     // [0, 4q) < 2^63
+  s = csub(s, c.two_q);
+  return csub(s, c.q);
+}
+
+// Residues below 2^60 split into 30-bit halves: x = hi*2^30 + lo.  Products
+// of halves are below 2^60, so 16 of them fit one 64-bit accumulator and
+// v_mad_u64_u32 accumulates them with no carry handling.
+struct Half30 {
+  uint32_t lo, hi;
+};
+
+__device__ __forceinline__ Half30 split30(uint64_t x) {
+  return Half30{(uint32_t)x & 0x3fffffffu, (uint32_t)(x >> 30)};
+}
+
+// Exact sum of products in four accumulators: a00 + (a01 + a10)*2^30 +
+// a11*2^60, reduced into [0, q).
+__device__ __forceinline__ uint64_t fold30(uint64_t a00, uint64_t a01, uint64_t a10, uint64_t a11,
+                                           const LimbConst& c) {
+  uint64_t s = reduce64_lazy(a00, c.mu64, c.q);         // [0, 2q)
+  s += mul_shoup_lazy(a01, c.c30, c.c30_sh, c.q);       // [0, 4q)
+  s += mul_shoup_lazy(a10, c.c30, c.c30_sh, c.q);       // [0, 6q)
+  s += mul_shoup_lazy(a11, c.c60, c.c60_sh, c.q);       // [0, 8q) < 2^63
+  s = csub(s, 4 * c.q);
   s = csub(s, c.two_q);
   return csub(s, c.q);
 }

@@ -108,7 +108,7 @@ MAC_CASES = [  # (shape, params, packing, B)
 ]
 
 
-MAC_TILES = [(0, 0), (4, 4), (8, 2), (2, 4), (4, 2), (8, 4), (2, 8), (4, 8), (1, 8)]
+MAC_TILES = [(0, 0), (4, 4), (4, 2), (2, 4), (8, 2), (2, 8), (8, 1), (1, 8), (2, 2)]
 
 
 @pytest.mark.parametrize("shape,params,packing,B", MAC_CASES)
