@@ -1,0 +1,54 @@
+// Internal: the context object and conv geometry shared by the library's
+// host translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "heconv.h"
+#include "modarith.h"
+
+struct he_ctx {
+  int device = 0;
+  uint32_t N = 0, logN = 0, L = 0;
+  uint64_t t = 0;
+  std::vector<uint64_t> q, psi;
+  std::vector<heconv::LimbConst> lc;
+  heconv::Tw* d_fwd = nullptr;  // [L][N] psi^brv(k) with Shoup quotient
+  heconv::Tw* d_inv = nullptr;  // [L][N] psi^-brv(k) with Shoup quotient
+  heconv::LimbConst* d_lc = nullptr;
+  he_tuning tune{3, 4, 512, 0, 0};
+};
+
+namespace heconv {
+
+// Conv geometry derived from a descriptor (mirrors the header's layout).
+struct Geo {
+  uint32_t He, We, R1, C1, bh, bw, nsi, nsj, S, CB, O;
+  bool sub;
+};
+
+inline bool geo_of(const he_conv_desc& d, uint32_t N, Geo& g) {
+  if (!d.C || !d.H || !d.W || !d.M || !d.kh || !d.kw || !d.stride) return false;
+  const uint32_t Hp = d.H + 2 * d.pad, Wp = d.W + 2 * d.pad;
+  if (Hp < d.kh || Wp < d.kw) return false;
+  const uint32_t Ho = (Hp - d.kh) / d.stride + 1, Wo = (Wp - d.kw) / d.stride + 1;
+  g.sub = d.kh == 1 && d.kw == 1 && d.stride > 1;
+  if (g.sub) {
+    g.He = Ho, g.We = Wo, g.R1 = Ho, g.C1 = Wo;
+  } else {
+    g.He = Hp, g.We = Wp, g.R1 = (Ho - 1) * d.stride + 1, g.C1 = (Wo - 1) * d.stride + 1;
+  }
+  if (!d.Cw || !d.Hw || !d.Ww) return false;
+  if (d.Cw > d.C || d.Hw < d.kh || d.Ww < d.kw || d.Hw > g.He || d.Ww > g.We) return false;
+  if ((uint64_t)d.Cw * d.Hw * d.Ww > N) return false;
+  g.bh = d.Hw - d.kh + 1, g.bw = d.Ww - d.kw + 1;
+  g.nsi = (g.R1 + g.bh - 1) / g.bh, g.nsj = (g.C1 + g.bw - 1) / g.bw;
+  g.S = g.nsi * g.nsj;
+  g.CB = (d.C + d.Cw - 1) / d.Cw;
+  g.O = (d.Cw - 1) * d.Hw * d.Ww + (d.kh - 1) * d.Ww + (d.kw - 1);
+  return true;
+}
+
+}  // namespace heconv

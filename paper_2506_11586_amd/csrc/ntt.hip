@@ -1,184 +1,32 @@
-// Fused negacyclic NTT / inverse NTT for gfx950: one workgroup per limb
-// polynomial, E = 2^LOGE coefficients per thread in registers, radix-E
-// passes (LOGE butterfly stages each) with an LDS transpose between passes.
-//
-// Forward (Cooley-Tukey, natural order in, bit-reversed order out): the
-// butterfly on bit b pairs j and j + 2^b with twiddle psi^brv(2^(n-1-b) +
-// (j >> (b+1))), n = log2 N; stages run from bit n-1 down to bit 0.  The
-// inverse (Gentleman-Sande) uses the same index with psi^-1 and runs from
-// bit 0 up; its last stage also applies N^-1.  Lazy reduction after Harvey:
-// forward values stay in [0, 4q), inverse values in [0, 2q), and every
-// stored word is canonical.
-//
-// Thread/element mapping of a pass over bits [lo, lo+LOGE): register k of
-// thread t holds element j = (t mod 2^lo) | k << lo | (t >> lo) << (lo+LOGE).
-// The top pass (lo = n-LOGE) is j = t + k*N/E: global loads and stores use
-// it, so every wave access is a contiguous 512-byte run.  The forward
-// transform ends on lo = 0 and goes through LDS once more to store in the
-// top mapping; the inverse loads in the top mapping and goes through LDS to
-// start at lo = 0.  When n is not a multiple of LOGE the leftover bits are
-// done by a partial pass at lo = 0.
+// Standalone NTT / inverse NTT kernels: one workgroup per limb polynomial.
+// The transform itself is in ntt_impl.h.
 #include "kernels.h"
+#include "ntt_impl.h"
 
 namespace heconv {
-
-__device__ __forceinline__ int lds_pad(int j) { return j + (j >> 4); }
-
-template <int LOGE, int LO>
-__device__ __forceinline__ int elem_index(int tid, int k) {
-  const int low = tid & ((1 << LO) - 1);
-  const int high = tid >> LO;
-  return low | (k << LO) | (high << (LO + LOGE));
-}
-
-// Forward stages u in [U0, LOGE) of the pass at bit offset LO.
-template <int LOGN, int LOGE, int LO, int U0>
-__device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LOGE], int tid, const Tw* __restrict__ tw, uint64_t q,
-                                         uint64_t q2) {
-  const int high = tid >> LO;
-#pragma unroll
-  for (int u = U0; u < LOGE; u++) {
-    const int s = LOGN - LOGE - LO + u;  // stage index: butterflies on bit LO+LOGE-1-u
-    const int half = 1 << (LOGE - 1 - u);
-#pragma unroll
-    for (int g = 0; g < (1 << u); g++) {
-      const Tw t = tw[(1 << s) + (high << u) + g];
-#pragma unroll
-      for (int e = 0; e < half; e++) {
-        const int k0 = g * 2 * half + e, k1 = k0 + half;
-        uint64_t X = csub(x[k0], q2);
-        uint64_t T = mul_shoup_lazy(x[k1], t.w, t.wsh, q);
-        x[k0] = X + T;
-        x[k1] = X - T + q2;
-      }
-    }
-  }
-}
-
-// Inverse stages u from LOGE-1 down to U0 of the pass at LO.  With LAST, the
-// stage on the top bit (u = 0 of the pass at n-LOGE) also applies N^-1 and
-// leaves canonical values.
-template <int LOGN, int LOGE, int LO, int U0, bool LAST>
-__device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LOGE], int tid, const Tw* __restrict__ tw,
-                                         const LimbConst& c) {
-  const int high = tid >> LO;
-  const uint64_t q = c.q, q2 = c.two_q;
-#pragma unroll
-  for (int u = LOGE - 1; u >= U0; u--) {
-    const int s = LOGN - LOGE - LO + u;
-    const int half = 1 << (LOGE - 1 - u);
-    if (LAST && u == 0) {
-#pragma unroll
-      for (int e = 0; e < half; e++) {
-        const int k0 = e, k1 = e + half;
-        uint64_t X = x[k0], Y = x[k1];
-        x[k0] = csub(mul_shoup_lazy(X + Y, c.ninv, c.ninv_sh, q), q);
-        x[k1] = csub(mul_shoup_lazy(X - Y + q2, c.ninv_w, c.ninv_w_sh, q), q);
-      }
-      continue;
-    }
-#pragma unroll
-    for (int g = 0; g < (1 << u); g++) {
-      const Tw t = tw[(1 << s) + (high << u) + g];
-#pragma unroll
-      for (int e = 0; e < half; e++) {
-        const int k0 = g * 2 * half + e, k1 = k0 + half;
-        uint64_t X = x[k0], Y = x[k1];
-        x[k0] = csub(X + Y, q2);
-        x[k1] = mul_shoup_lazy(X - Y + q2, t.w, t.wsh, q);
-      }
-    }
-  }
-}
-
-// Move the thread's registers from the mapping at FROM to the mapping at TO
-// through LDS.  The leading barrier keeps the previous exchange's readers
-// ahead of this exchange's writers.
-template <int LOGE, int FROM, int TO>
-__device__ __forceinline__ void exchange(uint64_t* lds, uint64_t (&x)[1 << LOGE], int tid) {
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < (1 << LOGE); k++) lds[lds_pad(elem_index<LOGE, FROM>(tid, k))] = x[k];
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < (1 << LOGE); k++) x[k] = lds[lds_pad(elem_index<LOGE, TO>(tid, k))];
-}
-
-// Forward full passes at LO = LOGN-LOGE*(P+1), then the partial pass.
-template <int LOGN, int LOGE, int P>
-__device__ __forceinline__ void fwd_rest(uint64_t (&x)[1 << LOGE], uint64_t* lds, int tid,
-                                         const Tw* __restrict__ tw, uint64_t q, uint64_t q2) {
-  constexpr int NFULL = LOGN / LOGE, REM = LOGN % LOGE;
-  if constexpr (P < NFULL) {
-    constexpr int LO = LOGN - LOGE * (P + 1);
-    if constexpr (P > 0) exchange<LOGE, LO + LOGE, LO>(lds, x, tid);
-    fwd_pass<LOGN, LOGE, LO, 0>(x, tid, tw, q, q2);
-    fwd_rest<LOGN, LOGE, P + 1>(x, lds, tid, tw, q, q2);
-  } else if constexpr (REM > 0) {
-    exchange<LOGE, LOGN - LOGE * NFULL, 0>(lds, x, tid);
-    fwd_pass<LOGN, LOGE, 0, LOGE - REM>(x, tid, tw, q, q2);
-  }
-}
 
 template <int LOGN, int LOGE>
 __global__ __launch_bounds__((1 << LOGN) >> LOGE) void ntt_fwd_kernel(uint64_t* __restrict__ polys, uint32_t L,
                                                                        const Tw* __restrict__ tw_all,
                                                                        const LimbConst* __restrict__ lcs) {
-  constexpr int N = 1 << LOGN, E = 1 << LOGE, T = N / E, TOP = LOGN - LOGE;
+  constexpr int N = 1 << LOGN;
   __shared__ uint64_t lds[N + N / 16];
-  const int tid = threadIdx.x;
   const uint32_t p = blockIdx.x;
   const uint32_t l = p % L;
-  uint64_t* a = polys + (size_t)p * N;
-  const Tw* tw = tw_all + (size_t)l * N;
-  const uint64_t q = lcs[l].q, q2 = lcs[l].two_q;
-  uint64_t x[E];
-#pragma unroll
-  for (int k = 0; k < E; k++) x[k] = a[tid + k * T];
-  fwd_rest<LOGN, LOGE, 0>(x, lds, tid, tw, q, q2);
-#pragma unroll
-  for (int k = 0; k < E; k++) x[k] = csub(csub(x[k], q2), q);
-  exchange<LOGE, 0, TOP>(lds, x, tid);  // back to j = tid + k*T for a coalesced store
-#pragma unroll
-  for (int k = 0; k < E; k++) a[tid + k * T] = x[k];
-}
-
-// Inverse full passes at LO = REM + LOGE*P (the partial pass at LO = 0, if
-// any, has already run).
-template <int LOGN, int LOGE, int P>
-__device__ __forceinline__ void inv_rest(uint64_t (&x)[1 << LOGE], uint64_t* lds, int tid,
-                                         const Tw* __restrict__ tw, const LimbConst& c) {
-  constexpr int NFULL = LOGN / LOGE, REM = LOGN % LOGE;
-  if constexpr (P < NFULL) {
-    constexpr int LO = REM + LOGE * P;
-    constexpr int PREV = (P == 0) ? 0 : REM + LOGE * (P - 1);
-    if constexpr (P > 0 || REM > 0) exchange<LOGE, PREV, LO>(lds, x, tid);
-    inv_pass<LOGN, LOGE, LO, 0, (P == NFULL - 1)>(x, tid, tw, c);
-    inv_rest<LOGN, LOGE, P + 1>(x, lds, tid, tw, c);
-  }
+  ntt_fwd_poly<LOGN, LOGE>(polys + (size_t)p * N, tw_all + (size_t)l * N, lcs[l].q, lcs[l].two_q, lds,
+                           threadIdx.x);
 }
 
 template <int LOGN, int LOGE>
 __global__ __launch_bounds__((1 << LOGN) >> LOGE) void ntt_inv_kernel(uint64_t* __restrict__ polys, uint32_t L,
                                                                        const Tw* __restrict__ tw_all,
                                                                        const LimbConst* __restrict__ lcs) {
-  constexpr int N = 1 << LOGN, E = 1 << LOGE, T = N / E, TOP = LOGN - LOGE, REM = LOGN % LOGE;
+  constexpr int N = 1 << LOGN;
   __shared__ uint64_t lds[N + N / 16];
-  const int tid = threadIdx.x;
   const uint32_t p = blockIdx.x;
   const uint32_t l = p % L;
-  uint64_t* a = polys + (size_t)p * N;
-  const Tw* tw = tw_all + (size_t)l * N;
   const LimbConst c = lcs[l];
-  uint64_t x[E];
-#pragma unroll
-  for (int k = 0; k < E; k++) x[k] = a[tid + k * T];  // coalesced, top mapping
-  exchange<LOGE, TOP, 0>(lds, x, tid);
-  if constexpr (REM > 0) inv_pass<LOGN, LOGE, 0, LOGE - REM, false>(x, tid, tw, c);
-  inv_rest<LOGN, LOGE, 0>(x, lds, tid, tw, c);
-  // the last pass ran at LO = n-LOGE: element j = tid + k*T, canonical
-#pragma unroll
-  for (int k = 0; k < E; k++) a[tid + k * T] = x[k];
+  ntt_inv_poly<LOGN, LOGE>(polys + (size_t)p * N, tw_all + (size_t)l * N, c, lds, threadIdx.x);
 }
 
 template <int LOGN, int LOGE>

@@ -54,6 +54,13 @@ class ConvDesc(ctypes.Structure):
         return "ConvDesc(" + ", ".join(f"{n}={getattr(self, n)}" for n, _ in self._fields_) + ")"
 
 
+class _Job(ctypes.Structure):
+    _fields_ = [("desc", ConvDesc), ("B", ctypes.c_uint32), ("d_in", ctypes.c_void_p), ("d_wntt", ctypes.c_void_p),
+                ("d_out", ctypes.c_void_p)]
+
+
+SCHED_PIPELINED, SCHED_PHASED = 0, 1
+
 _LIB = None
 
 
@@ -83,6 +90,17 @@ def _lib_handle():
         L.he_ntt_inv.argtypes = [vp, vp, u64, vp]
         L.he_conv_ntt_mac.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
         L.he_conv_layer.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
+        L.he_batch_create.argtypes = [vp, P(_Job), u32, u32, P(vp)]
+        L.he_batch_launch.argtypes = [vp, vp, i32]
+        L.he_batch_status.argtypes = [vp, vp]
+        L.he_batch_info.argtypes = [vp, P(u64), P(u32)]
+        L.he_batch_set_spin_limit.argtypes = [vp, u32]
+        L.he_batch_counters.argtypes = [vp, vp, P(u32), u32]
+        L.he_batch_destroy.argtypes = [vp]
+        L.he_batch_destroy.restype = None
+        for name in ("he_batch_create", "he_batch_launch", "he_batch_status", "he_batch_info",
+                     "he_batch_set_spin_limit", "he_batch_counters"):
+            getattr(L, name).restype = i32
         for name in ("he_gen_primes", "he_ctx_create", "he_ctx_psi", "he_ctx_get_tuning", "he_ctx_set_tuning", "he_plan_conv", "he_plan_conv_host", "he_min_root", "he_conv_sizes",
                      "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer"):
             getattr(L, name).restype = i32
@@ -250,3 +268,56 @@ class Context:
         _check(lib().he_conv_layer(self._h, ctypes.byref(d), int(B), _ptr(in_dev, B * s.in_cts * ct, "in"),
                                    _ptr(wntt_dev, s.w_words, "wntt"), _ptr(out_dev, B * s.out_cts * ct, "out"),
                                    _stream(stream)), "he_conv_layer")
+
+
+class Batch:
+    """he_batch: many layer solves in one persistent launch.
+
+    jobs: list of (desc, B, d_in, d_wntt, d_out) with device tensors; the
+    tensors are kept referenced for the batch's lifetime."""
+
+    def __init__(self, ctx: Context, jobs, schedule: int = SCHED_PIPELINED):
+        self.ctx = ctx
+        self.n_jobs = len(jobs)
+        self._keep = []
+        arr = (_Job * len(jobs))()
+        ct = 2 * ctx.L * ctx.N
+        for i, (d, B, din, dw, dout) in enumerate(jobs):
+            s = ctx.sizes(d)
+            arr[i] = _Job(d, int(B), _ptr(din, B * s.in_cts * ct, "in"), _ptr(dw, s.w_words, "wntt"),
+                          _ptr(dout, B * s.out_cts * ct, "out"))
+            self._keep += [din, dw, dout]
+        h = ctypes.c_void_p()
+        _check(lib().he_batch_create(ctx.handle, arr, len(jobs), int(schedule), ctypes.byref(h)), "he_batch_create")
+        self._h = h
+        n, g = ctypes.c_uint64(), ctypes.c_uint32()
+        _check(lib().he_batch_info(self._h, ctypes.byref(n), ctypes.byref(g)), "he_batch_info")
+        self.n_items, self.n_workgroups = n.value, g.value
+
+    def launch(self, stream=None, graph: bool = True):
+        _check(lib().he_batch_launch(self._h, _stream(stream), int(bool(graph))), "he_batch_launch")
+
+    def status(self, stream=None):
+        _check(lib().he_batch_status(self._h, _stream(stream)), "he_batch_status")
+
+    def counters(self, stream=None):
+        """(dispensed, error, seen, target, [(fwd_done, mac_done) per job])."""
+        n = 4 + 2 * self.n_jobs
+        out = (ctypes.c_uint32 * n)()
+        _check(lib().he_batch_counters(self._h, _stream(stream), out, n), "he_batch_counters")
+        v = list(out)
+        return v[0], v[1], v[2], v[3], [(v[4 + 2 * j], v[5 + 2 * j]) for j in range(self.n_jobs)]
+
+    def set_spin_limit(self, limit: int):
+        _check(lib().he_batch_set_spin_limit(self._h, int(limit)), "he_batch_set_spin_limit")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().he_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
