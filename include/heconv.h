@@ -170,12 +170,16 @@ he_status he_conv_layer(const he_ctx* ctx, const he_conv_desc* desc, uint32_t B,
                         const uint64_t* d_wntt, uint64_t* d_out, void* stream);
 
 /* ------------------------------------------------------------------------
- * Batch executor: many layer solves of uneven shape in one persistent launch.
+ * Batch executor: many layer solves of uneven shape in one launch.
  * Each job is one he_conv_layer call's worth of work (same buffers, same
- * result); a batch runs all of them in one persistent kernel that takes work
- * items (forward NTT of a limb polynomial, a MAC tile, inverse NTT of a limb
- * polynomial) from a device work list, so that the transforms of some jobs
- * overlap the MACs of others.  Results equal he_conv_layer's for every job.
+ * result).  A batch runs the forward NTT of every job's input limb
+ * polynomials as one grid, every job's MAC tiles as one grid and every
+ * job's inverse NTTs as one grid (one workgroup per item), so small layers
+ * no longer leave the GPU half empty.  With HE_SCHED_TWO_CHAINS the jobs are
+ * split into two chains (balanced by weight bytes) on two streams, so the
+ * MAC of one chain can overlap the transforms of the other.  With
+ * use_graph the kernels of all chains are captured once into a hipGraph and
+ * replayed with a single hipGraphLaunch.
  * ------------------------------------------------------------------------ */
 typedef struct {
   he_conv_desc desc;      /* planned descriptor (Cw, Hw, Ww filled) */
@@ -188,41 +192,30 @@ typedef struct {
 typedef struct he_batch he_batch;
 
 enum {
-  HE_SCHED_PIPELINED = 0, /* forward NTTs of job s next to MACs of s-1 and inverse NTTs of s-2 */
-  HE_SCHED_PHASED = 1     /* all forward NTTs, then all MACs, then all inverse NTTs */
+  HE_SCHED_ONE_CHAIN = 1, /* one stream: all forward NTTs, all MACs, all inverse NTTs */
+  HE_SCHED_TWO_CHAINS = 2 /* two chains of jobs on two streams */
 };
 
-/* Validate the jobs, build the work list in the given schedule and copy it
- * and the job table to the device (the batch's only allocations).  The
- * buffers named by the jobs must stay allocated while the batch is used;
- * jobs must not share output buffers or input buffers.  HE_ESHAPE for an
- * invalid descriptor or more than 2^32 work items. */
+/* Validate the jobs, build the work lists and copy them and the job table
+ * to the device (the batch's only allocations, besides two streams and two
+ * events for HE_SCHED_TWO_CHAINS).  The buffers named by the jobs must stay
+ * allocated while the batch is used; jobs must not share input or output
+ * buffers.  HE_EINVAL for an unknown schedule (value 0 named a persistent
+ * single-kernel executor, which is disabled).  HE_ESHAPE for an invalid
+ * descriptor or more than 2^31 items in one grid. */
 he_status he_batch_create(const he_ctx* ctx, const he_job* jobs, uint32_t n_jobs, uint32_t schedule,
                           he_batch** out);
 
-/* Enqueue one execution of the whole batch on `stream`: a counter-reset
- * kernel, then the persistent kernel.  With use_graph != 0 the two are
- * captured once into a hipGraph (on first use) and replayed with
- * hipGraphLaunch.  Executions of one batch must not overlap. */
+/* Enqueue one execution of the whole batch on `stream` (use_graph = 0: the
+ * kernels directly; else one hipGraphLaunch of the graph captured on first
+ * use).  Executions of one batch must not overlap. */
 he_status he_batch_launch(he_batch* b, void* stream, int use_graph);
 
-/* Synchronise `stream` and report the last execution: HE_OK, or HE_EDEVICE
- * if a dependency wait ran past its spin bound (results then invalid). */
+/* Synchronise `stream`; HE_EDEVICE if the device reported an error. */
 he_status he_batch_status(he_batch* b, void* stream);
 
-/* Counters of the last execution (synchronises `stream`): out[0] items
- * dispensed, out[1] error flag, out[2] / out[3] count seen / target of the
- * first wait that timed out, then per job j: out[4+2j] forward-NTT items
- * done, out[5+2j] MAC items done.  n >= 4 + 2*n_jobs. */
-he_status he_batch_counters(he_batch* b, void* stream, uint32_t* out, uint32_t n);
-
-/* Work items in the list and workgroups of the persistent launch. */
-he_status he_batch_info(const he_batch* b, uint64_t* n_items, uint32_t* n_workgroups);
-
-/* Bound on the polling iterations of one dependency wait (default 2^20;
- * each wait is also bounded by about one second of wall-clock time).
- * HE_EBUSY once the batch has been captured into a graph. */
-he_status he_batch_set_spin_limit(he_batch* b, uint32_t limit);
+/* Work items over all grids, and chains used. */
+he_status he_batch_info(const he_batch* b, uint64_t* n_items, uint32_t* n_chains);
 
 void he_batch_destroy(he_batch* b);
 

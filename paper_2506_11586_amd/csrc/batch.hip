@@ -1,149 +1,117 @@
-// Batch executor: one persistent kernel drains a work list that mixes the
-// three steps of many layer solves of uneven shape.
-//
-// Work items, in list order: FWD (forward NTT of one input limb
-// polynomial of a job), MAC (one MAC tile of a job), INV (inverse NTT of one
-// output limb polynomial).  Workgroups take items in list order from an
-// atomic head counter.  A job's MAC items wait until all its FWD items are
-// done, its INV items until all its MAC items are done; the host builds the
-// list so that every item's prerequisites come earlier in it, and every
-// earlier item has been taken by a running workgroup that never waits on a
-// later one, so the waits always end.  Each wait is nevertheless bounded: on
-// timeout the workgroup raises an error flag and carries on.
-//
-// Completion signals use agent-scope release fences (and the waiter an
-// agent-scope acquire fence), which on gfx950 write back / invalidate the
-// per-XCD L2 so that data written on one XCD is seen on another.
+// Batch executor kernels: the three steps of many layer solves of uneven
+// shape, each as one grid over a work list (one workgroup per item):
+// forward NTT of every input limb polynomial of every job, every MAC tile of
+// every job, inverse NTT of every output limb polynomial.  Kernel
+// boundaries order the steps; no workgroup waits on another.
 #include "batch.h"
 #include "mac_impl.h"
 #include "ntt_impl.h"
 
 namespace heconv {
 
-// Wall-clock bound of one dependency wait, in ticks of the 100 MHz
-// s_memrealtime counter (1 s).
-constexpr uint64_t WAIT_TICKS = 100000000ull;
-
-// A wait ends when the count is reached; when spin_limit polls or
-// WAIT_TICKS have passed (it then raises the error flag and records the
-// count it saw and the target); or as soon as any other wait has raised the
-// flag -- so a failed launch drains in about a second instead of hanging.
-// Counters live on separate 256-byte lines (CTR_STRIDE words apart).
-__device__ __forceinline__ void wait_count(uint32_t* cnt, uint32_t target, uint32_t* err, uint32_t spin_limit,
-                                           int tid) {
-  if (tid == 0) {
-    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    for (uint32_t spins = 0;; spins++) {
-      const uint32_t v = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (v >= target) break;
-      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-      if (spins + 1 >= spin_limit || __builtin_amdgcn_s_memrealtime() - t0 > WAIT_TICKS) {
-        if (__hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-          __hip_atomic_store(err + 1, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(err + 2, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        break;
-      }
-      __builtin_amdgcn_s_sleep(8);
-    }
-  }
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-__device__ __forceinline__ void signal_count(uint32_t* cnt, int tid) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (tid == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Counter words (CTR_STRIDE apart): [0] head, [1] error flag (+1 count seen,
-// +2 target of the first timed-out wait), [2 + 2j] FWD items of job j done,
-// [3 + 2j] MAC items of job j done.
-template <int LOGN, int MT, int RT>
-__global__ __launch_bounds__((1 << LOGN) / 16, 4) void batch_kernel(const BatchItem* __restrict__ items,
-                                                                     uint32_t n_items,
-                                                                     const BatchJob* __restrict__ jobs,
-                                                                     uint32_t* ctr, const Tw* __restrict__ twf,
-                                                                     const Tw* __restrict__ twi,
-                                                                     const LimbConst* __restrict__ lcs, uint32_t L,
-                                                                     uint32_t spin_limit) {
-  constexpr int N = 1 << LOGN, T = N / 16;
+template <int LOGN, int LOGE>
+__global__ __launch_bounds__((1 << LOGN) >> LOGE) void batch_fwd_kernel(const BatchItem* __restrict__ items,
+                                                                         const BatchJob* __restrict__ jobs,
+                                                                         const Tw* __restrict__ tw,
+                                                                         const LimbConst* __restrict__ lcs,
+                                                                         uint32_t L) {
+  constexpr int N = 1 << LOGN;
   __shared__ uint64_t lds[N + N / 16];
-  __shared__ uint32_t s_it;
-  const int tid = threadIdx.x;
-  uint32_t* head = ctr;
-  uint32_t* err = ctr + CTR_STRIDE;
-  for (;;) {
-    if (tid == 0) s_it = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const uint32_t it = s_it;
-    __syncthreads();
-    if (it >= n_items) break;
-    const BatchItem item = items[it];
-    const uint32_t j = item.jt >> 2, type = item.jt & 3u;
-    const BatchJob jd = jobs[j];
-    if (type == ITEM_FWD) {
-      const uint32_t l = item.idx % L;
-      ntt_fwd_poly<LOGN, 4>(jd.in + (size_t)item.idx * N, twf + (size_t)l * N, lcs[l].q, lcs[l].two_q, lds, tid);
-      signal_count(ctr + (2 + 2 * j) * CTR_STRIDE, tid);
-    } else if (type == ITEM_MAC) {
-      wait_count(ctr + (2 + 2 * j) * CTR_STRIDE, jd.n_fwd, err, spin_limit, tid);
-      const uint32_t per_chunk = jd.n_mt * jd.n_rt;
-      const uint32_t kc = item.idx / per_chunk;
-      const uint32_t mt = (item.idx % per_chunk) / jd.n_rt;
-      const uint32_t rt = item.idx % jd.n_rt;
-      const LimbConst c = lcs[kc / (N / T)];
-      mac_tile<MT, RT, T>(jd.in, jd.w, jd.out, jd.CB, jd.S, jd.M, L, N, jd.rows, kc, mt, rt, c, tid);
-      signal_count(ctr + (3 + 2 * j) * CTR_STRIDE, tid);
-    } else {
-      wait_count(ctr + (3 + 2 * j) * CTR_STRIDE, jd.n_mac, err, spin_limit, tid);
-      const uint32_t l = item.idx % L;
-      const LimbConst c = lcs[l];
-      ntt_inv_poly<LOGN, 4>(jd.out + (size_t)item.idx * N, twi + (size_t)l * N, c, lds, tid);
+  const BatchItem it = items[blockIdx.x];
+  gword* in = as_global(jobs[it.job].in);
+  const uint32_t l = it.idx % L;
+  ntt_fwd_poly<LOGN, LOGE>(in + (size_t)it.idx * N, tw + (size_t)l * N, lcs[l].q, lcs[l].two_q, lds, threadIdx.x);
+}
+
+template <int LOGN, int LOGE>
+__global__ __launch_bounds__((1 << LOGN) >> LOGE) void batch_inv_kernel(const BatchItem* __restrict__ items,
+                                                                         const BatchJob* __restrict__ jobs,
+                                                                         const Tw* __restrict__ tw,
+                                                                         const LimbConst* __restrict__ lcs,
+                                                                         uint32_t L) {
+  constexpr int N = 1 << LOGN;
+  __shared__ uint64_t lds[N + N / 16];
+  const BatchItem it = items[blockIdx.x];
+  gword* out = as_global(jobs[it.job].out);
+  const uint32_t l = it.idx % L;
+  const LimbConst c = lcs[l];
+  ntt_inv_poly<LOGN, LOGE>(out + (size_t)it.idx * N, tw + (size_t)l * N, c, lds, threadIdx.x);
+}
+
+// MAC items are listed job by job, tile index k-chunk-major, so the XCD remap
+// keeps the tiles of one k-chunk (which share input and weight words) on one
+// XCD's L2.
+template <int MT, int RT>
+__global__ __launch_bounds__(BATCH_MAC_THREADS) void batch_mac_kernel(const BatchItem* __restrict__ items,
+                                                                       const BatchJob* __restrict__ jobs,
+                                                                       const LimbConst* __restrict__ lcs,
+                                                                       uint32_t L, uint32_t N) {
+  const BatchItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+  const BatchJob jd = jobs[it.job];
+  const uint32_t per_chunk = jd.n_mt * jd.n_rt;
+  const uint32_t kc = it.idx / per_chunk;
+  const uint32_t mt = (it.idx % per_chunk) / jd.n_rt;
+  const uint32_t rt = it.idx % jd.n_rt;
+  const LimbConst c = lcs[kc / (N / BATCH_MAC_THREADS)];
+  mac_tile<MT, RT, BATCH_MAC_THREADS>(as_global(jd.in), as_global(jd.w), as_global(jd.out), jd.CB, jd.S, jd.M, L, N,
+                                      jd.rows, kc, mt, rt, c, threadIdx.x);
+}
+
+template <int LOGN, int LOGE>
+static void launch_ntt_phase(bool inverse, const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
+  constexpr uint32_t T = (1u << LOGN) >> LOGE;
+  if (inverse)
+    hipLaunchKernelGGL((batch_inv_kernel<LOGN, LOGE>), dim3(p.n), dim3(T), 0, st, p.items, a.jobs, a.twi, a.lcs, a.L);
+  else
+    hipLaunchKernelGGL((batch_fwd_kernel<LOGN, LOGE>), dim3(p.n), dim3(T), 0, st, p.items, a.jobs, a.twf, a.lcs, a.L);
+}
+
+template <int LOGN>
+static hipError_t ntt_phase(bool inverse, uint32_t loge, const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
+  if constexpr (LOGN <= 13) {
+    if (loge == 3) {
+      launch_ntt_phase<LOGN, 3>(inverse, p, a, st);
+      return hipGetLastError();
     }
   }
-}
-
-__global__ void batch_reset_kernel(uint32_t* ctr, uint32_t n) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) ctr[i] = 0;
-}
-
-template <int LOGN>
-static const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&batch_kernel<LOGN, BATCH_MT, BATCH_RT>);
-}
-
-hipError_t batch_occupancy(uint32_t logN, int* blocks_per_cu) {
-  const void* f = nullptr;
-  switch (logN) {
-    case 10: f = kernel_ptr<10>(); break;
-    case 11: f = kernel_ptr<11>(); break;
-    case 12: f = kernel_ptr<12>(); break;
-    case 13: f = kernel_ptr<13>(); break;
-    case 14: f = kernel_ptr<14>(); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, (1 << logN) / 16, 0);
-}
-
-template <int LOGN>
-static void launch_batch(const BatchLaunch& a, hipStream_t st) {
-  hipLaunchKernelGGL((batch_kernel<LOGN, BATCH_MT, BATCH_RT>), dim3(a.grid), dim3((1 << LOGN) / 16), 0, st, a.items,
-                     a.n_items, a.jobs, a.ctr, a.twf, a.twi, a.lcs, a.L, a.spin_limit);
-}
-
-hipError_t batch_launch(uint32_t logN, const BatchLaunch& a, hipStream_t st) {
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, st, a.ctr, a.n_ctr);
-  switch (logN) {
-    case 10: launch_batch<10>(a, st); break;
-    case 11: launch_batch<11>(a, st); break;
-    case 12: launch_batch<12>(a, st); break;
-    case 13: launch_batch<13>(a, st); break;
-    case 14: launch_batch<14>(a, st); break;
-    default: return hipErrorInvalidValue;
-  }
+  launch_ntt_phase<LOGN, 4>(inverse, p, a, st);
   return hipGetLastError();
+}
+
+static hipError_t ntt_phase_n(bool inverse, uint32_t logN, uint32_t loge, const BatchPhase& p, const BatchArgs& a,
+                              hipStream_t st) {
+  if (p.n == 0) return hipSuccess;
+  switch (logN) {
+    case 10: return ntt_phase<10>(inverse, loge, p, a, st);
+    case 11: return ntt_phase<11>(inverse, loge, p, a, st);
+    case 12: return ntt_phase<12>(inverse, loge, p, a, st);
+    case 13: return ntt_phase<13>(inverse, loge, p, a, st);
+    case 14: return ntt_phase<14>(inverse, loge, p, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static hipError_t mac_phase(const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
+  if (p.n == 0) return hipSuccess;
+  if (a.mac_mt == 4 && a.mac_rt == 4) {
+    hipLaunchKernelGGL((batch_mac_kernel<4, 4>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs, a.lcs,
+                       a.L, a.N);
+    return hipGetLastError();
+  }
+  if (a.mac_mt == 2 && a.mac_rt == 2) {
+    hipLaunchKernelGGL((batch_mac_kernel<2, 2>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs, a.lcs,
+                       a.L, a.N);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t batch_chain(const BatchChain& ch, const BatchArgs& a, hipStream_t st) {
+  hipError_t e = ntt_phase_n(false, a.logN, ch.fwd.n < 512 ? a.loge_small : a.loge_large, ch.fwd, a, st);
+  if (e != hipSuccess) return e;
+  e = mac_phase(ch.mac, a, st);
+  if (e != hipSuccess) return e;
+  return ntt_phase_n(true, a.logN, ch.inv.n < 512 ? a.loge_small : a.loge_large, ch.inv, a, st);
 }
 
 }  // namespace heconv

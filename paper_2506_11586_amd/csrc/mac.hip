@@ -73,7 +73,7 @@ __global__ __launch_bounds__(MAC_THREADS) void mac_kernel(const uint64_t* __rest
   const uint32_t mt = (tile % per_chunk) / n_rt;
   const uint32_t rt = tile % n_rt;
   const LimbConst c = lcs[kc / (N / MAC_THREADS)];
-  mac_tile<MT, RT, MAC_THREADS>(in, w, out, CB, S, M, L, N, rows, kc, mt, rt, c, threadIdx.x);
+  mac_tile<MT, RT, MAC_THREADS>(as_global(in), as_global(w), as_global(out), CB, S, M, L, N, rows, kc, mt, rt, c, threadIdx.x);
 }
 
 template <int MT, int RT>

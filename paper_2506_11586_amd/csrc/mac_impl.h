@@ -54,8 +54,7 @@ __device__ __forceinline__ void mac_step(const uint64_t (&xr)[RT], const uint64_
 // kc / (N/THREADS)), output channels mt*MT.., rows rt*RT.., for the calling
 // workgroup of THREADS threads.  c = constants of that limb.
 template <int MT, int RT, int THREADS>
-__device__ __forceinline__ void mac_tile(const uint64_t* __restrict__ in, const uint64_t* __restrict__ w,
-                                         uint64_t* __restrict__ out, uint32_t CB, uint32_t S, uint32_t M, uint32_t L,
+__device__ __forceinline__ void mac_tile(cgword* __restrict__ in, cgword* __restrict__ w, gword* __restrict__ out, uint32_t CB, uint32_t S, uint32_t M, uint32_t L,
                                          uint32_t N, uint32_t rows, uint32_t kc, uint32_t mt, uint32_t rt,
                                          const LimbConst& c, int tid) {
   const uint32_t chunks_per_limb = N / THREADS;
@@ -64,7 +63,7 @@ __device__ __forceinline__ void mac_tile(const uint64_t* __restrict__ in, const 
   const uint64_t LN = (uint64_t)L * N;
 
   // row r = (b*S + s)*2 + comp; input address of (r, cb) and output of (r, m)
-  const uint64_t* ip[RT];
+  cgword* ip[RT];
   uint64_t out_off[RT];
   bool rv[RT];
 #pragma unroll
@@ -80,7 +79,7 @@ __device__ __forceinline__ void mac_tile(const uint64_t* __restrict__ in, const 
   const uint64_t in_cb_stride = (uint64_t)S * 2 * LN;  // cb -> cb+1 in the input
   const uint64_t out_m_stride = (uint64_t)S * 2 * LN;  // m -> m+1 in the output
   bool mv[MT];
-  const uint64_t* wp[MT];
+  cgword* wp[MT];
 #pragma unroll
   for (int j = 0; j < MT; j++) {
     const uint32_t m = mt * MT + j;

@@ -21,6 +21,18 @@ struct LimbConst {
   uint64_t c60, c60_sh;        // 2^60 mod q and its Shoup quotient
 };
 
+// Device buffers are passed to the transform and MAC bodies as pointers in
+// the global address space: a pointer loaded from memory (a job table) is
+// otherwise generic to the compiler, whose loads and stores would then be
+// flat ones with 64-bit per-lane addresses.
+typedef __attribute__((address_space(1))) uint64_t gword;
+typedef const __attribute__((address_space(1))) uint64_t cgword;
+
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // A twiddle with its Shoup quotient, stored side by side (one 16-byte load).
 struct Tw {
   uint64_t w, wsh;

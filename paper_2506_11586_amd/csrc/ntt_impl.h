@@ -140,7 +140,7 @@ __device__ __forceinline__ void inv_rest(uint64_t (&x)[1 << LOGE], uint64_t* lds
 // Forward transform of one limb polynomial a[N] (in place) by the calling
 // workgroup of N/2^LOGE threads.
 template <int LOGN, int LOGE>
-__device__ __forceinline__ void ntt_fwd_poly(uint64_t* __restrict__ a, const Tw* __restrict__ tw, uint64_t q,
+__device__ __forceinline__ void ntt_fwd_poly(gword* __restrict__ a, const Tw* __restrict__ tw, uint64_t q,
                                              uint64_t q2, uint64_t* lds, int tid) {
   constexpr int N = 1 << LOGN, E = 1 << LOGE, T = N / E, TOP = LOGN - LOGE;
   uint64_t x[E];
@@ -156,7 +156,7 @@ __device__ __forceinline__ void ntt_fwd_poly(uint64_t* __restrict__ a, const Tw*
 
 // Inverse transform of one limb polynomial a[N] (in place).
 template <int LOGN, int LOGE>
-__device__ __forceinline__ void ntt_inv_poly(uint64_t* __restrict__ a, const Tw* __restrict__ tw, const LimbConst& c,
+__device__ __forceinline__ void ntt_inv_poly(gword* __restrict__ a, const Tw* __restrict__ tw, const LimbConst& c,
                                              uint64_t* lds, int tid) {
   constexpr int N = 1 << LOGN, E = 1 << LOGE, T = N / E, TOP = LOGN - LOGE, REM = LOGN % LOGE;
   uint64_t x[E];

@@ -59,7 +59,7 @@ class _Job(ctypes.Structure):
                 ("d_out", ctypes.c_void_p)]
 
 
-SCHED_PIPELINED, SCHED_PHASED = 0, 1
+SCHED_ONE_CHAIN, SCHED_TWO_CHAINS = 1, 2
 
 _LIB = None
 
@@ -94,12 +94,9 @@ def _lib_handle():
         L.he_batch_launch.argtypes = [vp, vp, i32]
         L.he_batch_status.argtypes = [vp, vp]
         L.he_batch_info.argtypes = [vp, P(u64), P(u32)]
-        L.he_batch_set_spin_limit.argtypes = [vp, u32]
-        L.he_batch_counters.argtypes = [vp, vp, P(u32), u32]
         L.he_batch_destroy.argtypes = [vp]
         L.he_batch_destroy.restype = None
-        for name in ("he_batch_create", "he_batch_launch", "he_batch_status", "he_batch_info",
-                     "he_batch_set_spin_limit", "he_batch_counters"):
+        for name in ("he_batch_create", "he_batch_launch", "he_batch_status", "he_batch_info"):
             getattr(L, name).restype = i32
         for name in ("he_gen_primes", "he_ctx_create", "he_ctx_psi", "he_ctx_get_tuning", "he_ctx_set_tuning", "he_plan_conv", "he_plan_conv_host", "he_min_root", "he_conv_sizes",
                      "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer"):
@@ -271,12 +268,13 @@ class Context:
 
 
 class Batch:
-    """he_batch: many layer solves in one persistent launch.
+    """he_batch: many layer solves in one launch (three grids per chain,
+    optionally one hipGraph).
 
     jobs: list of (desc, B, d_in, d_wntt, d_out) with device tensors; the
     tensors are kept referenced for the batch's lifetime."""
 
-    def __init__(self, ctx: Context, jobs, schedule: int = SCHED_PIPELINED):
+    def __init__(self, ctx: Context, jobs, schedule: int = SCHED_ONE_CHAIN):
         self.ctx = ctx
         self.n_jobs = len(jobs)
         self._keep = []
@@ -290,26 +288,15 @@ class Batch:
         h = ctypes.c_void_p()
         _check(lib().he_batch_create(ctx.handle, arr, len(jobs), int(schedule), ctypes.byref(h)), "he_batch_create")
         self._h = h
-        n, g = ctypes.c_uint64(), ctypes.c_uint32()
-        _check(lib().he_batch_info(self._h, ctypes.byref(n), ctypes.byref(g)), "he_batch_info")
-        self.n_items, self.n_workgroups = n.value, g.value
+        n, c = ctypes.c_uint64(), ctypes.c_uint32()
+        _check(lib().he_batch_info(self._h, ctypes.byref(n), ctypes.byref(c)), "he_batch_info")
+        self.n_items, self.n_chains = n.value, c.value
 
     def launch(self, stream=None, graph: bool = True):
         _check(lib().he_batch_launch(self._h, _stream(stream), int(bool(graph))), "he_batch_launch")
 
     def status(self, stream=None):
         _check(lib().he_batch_status(self._h, _stream(stream)), "he_batch_status")
-
-    def counters(self, stream=None):
-        """(dispensed, error, seen, target, [(fwd_done, mac_done) per job])."""
-        n = 4 + 2 * self.n_jobs
-        out = (ctypes.c_uint32 * n)()
-        _check(lib().he_batch_counters(self._h, _stream(stream), out, n), "he_batch_counters")
-        v = list(out)
-        return v[0], v[1], v[2], v[3], [(v[4 + 2 * j], v[5 + 2 * j]) for j in range(self.n_jobs)]
-
-    def set_spin_limit(self, limit: int):
-        _check(lib().he_batch_set_spin_limit(self._h, int(limit)), "he_batch_set_spin_limit")
 
     def close(self):
         if getattr(self, "_h", None):
