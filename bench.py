@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched fire-module CNN section")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM counter scaling)")
     return ap.parse_args()
@@ -199,6 +203,11 @@ def main():
         "roofline": roofline,
     }
 
+    if not args.no_batched:
+        result["batched"] = run_batched(torch, heconv)
+    if not args.no_serving:
+        result["serving"] = run_serving(torch, heconv, args)
+
     if args.copy_probe:
         src = torch.ones(32 << 20, dtype=torch.int64, device="cuda")
         dst = torch.empty_like(src)
@@ -211,6 +220,126 @@ def main():
         result["cpu_baseline"], result["bit_exact"] = cpu_baseline(args, cfg, ctx, d, sz, x_host, K_host, gpu_out)
     print(json.dumps(result), flush=True)
     ctx.close()
+
+
+def _timed(torch, fn, reps, warm=2):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def run_batched(torch, heconv):
+    """Fire-module CNN (26 convs at 224 input, B=1, N=8192, L=3): the 26 layer
+    solves one after another through he_conv_layer (plain) vs one batch (two
+    chains of three grids, one hipGraph launch).  Outputs compared word for
+    word."""
+    cfg = synth.CONFIGS[3]
+    N, L, bits = cfg["N"], cfg["L"], cfg["bits"]
+    ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), 2 ** synth.T_BITS)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64).copy()).cuda()
+    jobs, pristine, macs = [], [], 0
+    for i, shape in enumerate(cfg["layers"]):
+        C, H, W, M, kh, kw, stride, pad = shape
+        d = ctx.plan(shape)
+        s = ctx.sizes(d)
+        K = Stream(cfg["seed"] * 1000 + i, synth.WEIGHT).ints(M * C * kh * kw, *cfg["w_range"])
+        wntt = torch.empty(s.w_words, dtype=torch.int64, device="cuda")
+        ctx.encode_weights(d, dev(K), wntt)
+        x = synth.uniform_mod(Stream(cfg["seed"] * 1000 + i, synth.UNIFORM), (s.in_cts * 2, L, N), ctx.q)
+        pristine.append(dev(x))
+        jobs.append((d, 1, pristine[-1].clone(), wntt, torch.empty(s.out_cts * 2 * L * N, dtype=torch.int64,
+                                                                         device="cuda")))
+        macs += M * s.CB * s.S
+    plain_out = [torch.empty_like(j[4]) for j in jobs]
+    # correctness: batch outputs == plain outputs on the same inputs
+    for j, p, o in zip(jobs, pristine, plain_out):
+        ctx.conv_layer(j[0], 1, p.clone(), j[3], o)
+    b = heconv.Batch(ctx, jobs, schedule=heconv.SCHED_TWO_CHAINS)
+    b.launch(graph=True)
+    b.status()
+    exact = all(torch.equal(j[4], o) for j, o in zip(jobs, plain_out))
+    del plain_out
+
+    def plain():
+        for j in jobs:
+            ctx.conv_layer(j[0], 1, j[2], j[3], j[4])
+
+    t_plain = _timed(torch, plain, 10)
+    t_batch = _timed(torch, lambda: b.launch(graph=True), 10)
+    n = len(jobs)
+    b.close()
+    ctx.close()
+    return {"workload": cfg["name"], "layers": n, "ctpt_macs_per_pass": macs,
+            "plain_ms": t_plain, "batched_ms": t_batch,
+            "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_batch * 1e3,
+            "plain_ctpt_macs_per_s": macs / t_plain * 1e3, "batched_ctpt_macs_per_s": macs / t_batch * 1e3,
+            "speedup": t_plain / t_batch, "bit_exact_vs_plain": bool(exact),
+            "batched_form": "two chains of three grids (forward NTTs, MAC tiles, inverse NTTs), one hipGraph"}
+
+
+def run_serving(torch, heconv, args):
+    """Open-loop Poisson arrivals over the 28 single-layer shapes of the three
+    workloads above (the small layer keeps N=4096, L=2), weights resident,
+    HBM budget 200 GB, four streams; then the same requests closed-loop
+    (saturation), served vs one at a time on one stream."""
+    from paper_2506_11586_amd import serving
+
+    shapes = [(1, synth.CONFIGS[1]["layers"][0]), (2, synth.CONFIGS[2]["layers"][0])] + \
+             [(3, s) for s in synth.CONFIGS[3]["layers"]]
+    ctxs, layers = {}, []
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64).copy()).cuda()
+    for i, (c, shape) in enumerate(shapes):
+        cfg = synth.CONFIGS[c]
+        key = (cfg["N"], cfg["L"], cfg["bits"])
+        if key not in ctxs:
+            ctxs[key] = heconv.Context(cfg["N"], heconv.gen_primes(cfg["N"], cfg["bits"], cfg["L"]))
+        ctx = ctxs[key]
+        C, H, W, M, kh, kw, stride, pad = shape
+        K = Stream(5000 + i, synth.WEIGHT).ints(M * C * kh * kw, *cfg["w_range"])
+        layers.append(serving.make_layer(ctx, shape, dev(K)))
+    # a pool of two distinct seeded inputs per layer, reused round-robin
+    pool = []
+    for i, lay in enumerate(layers):
+        rows = lay.in_words // lay.ctx.N
+        pool.append([torch.from_numpy(synth.uniform_mod(Stream(6000 + 2 * i + v, synth.UNIFORM),
+                                                        (rows // lay.ctx.L, lay.ctx.L, lay.ctx.N),
+                                                        lay.ctx.q).view(np.int64).ravel().copy()).pin_memory()
+                     for v in range(2)])
+    n = args.serve_requests
+    mix = Stream(5, synth.MIX).below(n, len(layers)).astype(int)
+    times = serving.poisson_arrivals(args.serve_rate, n, Stream(5, synth.ARRIVAL).uniform_f64(n))
+
+    def requests():
+        return [serving.Request(i, int(mix[i]), float(times[i]), pool[mix[i]][i % 2]) for i in range(n)]
+
+    server = serving.Server(layers, n_streams=4, hbm_budget=200e9)
+    server.run(requests()[:32], closed_loop=True)  # warm-up: slots, code paths
+    op = server.run(requests())
+    cl = server.run(requests(), closed_loop=True)
+    one = serving.Server(layers, n_streams=1, hbm_budget=200e9)
+    one.run(requests()[:32], closed_loop=True)
+    seq = one.run(requests(), closed_loop=True)
+    macs = {i: lay.desc.M * lay.sizes.CB * lay.sizes.S for i, lay in enumerate(layers)}
+    tot_macs = sum(macs[int(m)] for m in mix)
+    out = {"workload": f"Poisson {args.serve_rate:g} req/s, {n} single-layer requests over {len(layers)} shapes",
+           "open_loop": {"layers_per_s": op.layers_per_s, "p50_ms": op.p50_ms, "p99_ms": op.p99_ms,
+                         "mean_ms": op.mean_ms, "max_inflight": op.max_inflight, "wall_s": op.wall_s},
+           "closed_loop_served": {"layers_per_s": cl.layers_per_s, "ctpt_macs_per_s": tot_macs / cl.wall_s,
+                                  "p50_ms": cl.p50_ms, "p99_ms": cl.p99_ms, "max_inflight": cl.max_inflight},
+           "closed_loop_plain_one_stream": {"layers_per_s": seq.layers_per_s, "ctpt_macs_per_s": tot_macs / seq.wall_s},
+           "served_vs_plain": cl.layers_per_s / seq.layers_per_s,
+           "hbm_budget_GB": 200, "resident_weights_GB": server.resident / 1e9,
+           "latency": "arrival -> device completion (H2D copy of the input included; results stay in HBM)"}
+    for c in ctxs.values():
+        c.close()
+    return out
 
 
 def cpu_baseline(args, cfg, ctx, d, sz, x_host, K_host, gpu_out):

@@ -1,0 +1,94 @@
+"""GPU: the request server -- every result is the same alone and in the mix
+(bit-exact), requests overlap on the device, and the HBM budget holds."""
+import numpy as np
+import pytest
+
+import synth
+from synth import Stream
+from tests.gpu_util import empty_words, require_gpu, to_dev, to_host
+from tests.libload import ensure_built
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # (N, L, bits, shape)
+    (4096, 2, 50, (4, 16, 16, 4, 3, 3, 1, 1)),
+    (4096, 2, 50, (8, 11, 9, 5, 3, 3, 2, 1)),
+    (8192, 3, 60, (64, 56, 56, 64, 3, 3, 1, 1)),
+    (8192, 3, 60, (16, 55, 55, 64, 1, 1, 1, 0)),
+    (8192, 3, 60, (48, 13, 13, 192, 3, 3, 1, 1)),
+]
+
+
+def build_server(n_streams, budget):
+    import torch
+    from paper_2506_11586_amd import heconv, serving
+    ctxs, layers = {}, []
+    for i, (N, L, bits, shape) in enumerate(SHAPES):
+        if (N, L) not in ctxs:
+            ctxs[(N, L)] = heconv.Context(N, heconv.gen_primes(N, bits, L))
+        ctx = ctxs[(N, L)]
+        C, M, kh, kw = shape[0], shape[3], shape[4], shape[5]
+        K = Stream(700 + i, synth.WEIGHT).ints(M * C * kh * kw, -2 ** 12, 2 ** 12)
+        layers.append(serving.make_layer(ctx, shape, to_dev(K)))
+    torch.cuda.synchronize()
+    return serving.Server(layers, n_streams=n_streams, hbm_budget=budget), layers
+
+
+def make_requests(layers, n, rate, seed):
+    import torch
+    from paper_2506_11586_amd import serving
+    mix = Stream(seed, synth.MIX).below(n, len(layers)).astype(int)
+    times = serving.poisson_arrivals(rate, n, Stream(seed, synth.ARRIVAL).uniform_f64(n))
+    reqs = []
+    for i in range(n):
+        lay = layers[mix[i]]
+        words = synth.uniform_mod(Stream(seed * 1000 + i, synth.UNIFORM),
+                                  (lay.in_words // lay.ctx.N // lay.ctx.L, lay.ctx.L, lay.ctx.N), lay.ctx.q)
+        host = torch.from_numpy(words.view(np.int64).ravel().copy()).pin_memory()
+        reqs.append(serving.Request(i, int(mix[i]), float(times[i]), host))
+    return reqs
+
+
+def test_alone_equals_in_the_mix():
+    require_gpu()
+    ensure_built()
+    server, layers = build_server(n_streams=4, budget=200e9)
+    reqs = make_requests(layers, 40, rate=5000.0, seed=41)
+    # alone: each request by itself, default stream, fresh buffers
+    alone = []
+    for r in reqs:
+        lay = layers[r.layer]
+        d_in = r.host_in.cuda()
+        d_out = empty_words(lay.out_words)
+        lay.ctx.conv_layer(lay.desc, 1, d_in, lay.wntt, d_out)
+        alone.append(to_host(d_out).copy())
+    # in the mix: open loop at 5000 req/s over 4 streams
+    st = server.run(reqs, keep_outputs=True)
+    assert st.n == len(reqs) and st.max_inflight > 1
+    for r, a in zip(reqs, alone):
+        assert np.array_equal(to_host(r.slot[1]), a), r.rid
+    assert server.used <= 200e9
+
+
+def test_budget_limits_admission():
+    """With a budget that fits the weights and one slot pair of the largest
+    layer only, requests queue for slots, never exceed the budget, and still
+    all complete with the same results."""
+    require_gpu()
+    ensure_built()
+    server, layers = build_server(n_streams=4, budget=200e9)
+    biggest = max((l.in_words + l.out_words) * 8 for l in layers)
+    server.budget = server.resident + biggest
+    reqs = make_requests(layers, 12, rate=1e5, seed=43)
+    st = server.run(reqs, closed_loop=True)
+    assert st.n == 12 and server.used <= server.budget
+    assert all(np.isfinite(r.t_done) for r in reqs)
+
+
+def test_budget_too_small_for_weights():
+    require_gpu()
+    ensure_built()
+    from paper_2506_11586_amd import serving
+    _, layers = build_server(n_streams=1, budget=200e9)
+    with pytest.raises(MemoryError):
+        serving.Server(layers, hbm_budget=1e6)
