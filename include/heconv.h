@@ -102,10 +102,15 @@ void he_ctx_destroy(he_ctx* ctx);
  * (3 is used only for N <= 2^13).  MAC: each thread accumulates mac_mt
  * output channels x mac_rt ciphertext rows for one NTT point; (0, 0) picks
  * by shape; supported pairs: (4,4) (4,2) (2,4) (8,2) (2,8) (8,1) (1,8) (2,2).
- * Defaults: {3, 4, 512, 0, 0}. */
+ * layer_fused: 1 = he_conv_layer runs the MAC and the inverse NTT as one
+ * kernel (he_conv_mac_intt), 0 = as two (he_conv_ntt_mac, he_ntt_inv).
+ * Defaults: {3, 4, 512, 0, 0, 0} (the fused kernel gives up the MAC's
+ * register tiling, so it moves several times more data through L2 and is
+ * slower on the 64->64 3x3 layer: 153 us against 106 us for the pair). */
 typedef struct {
   uint32_t ntt_loge_small, ntt_loge_large, ntt_small_below;
   uint32_t mac_mt, mac_rt;
+  uint32_t layer_fused;
 } he_tuning;
 
 he_status he_ctx_get_tuning(const he_ctx* ctx, he_tuning* out);
@@ -160,6 +165,14 @@ he_status he_ntt_inv(const he_ctx* ctx, uint64_t* d_polys, uint64_t n, void* str
  * inputs). */
 he_status he_conv_ntt_mac(const he_ctx* ctx, const he_conv_desc* desc, uint32_t B, const uint64_t* d_in_ntt,
                           const uint64_t* d_wntt, uint64_t* d_out_ntt, void* stream);
+
+/* The MAC and the inverse NTT in one kernel: from NTT-form inputs
+ * d_in_ntt [B][CB][S][2][L][N] and weights to coefficient-form outputs
+ * d_out [B][M][S][2][L][N] -- the same words as he_conv_ntt_mac followed by
+ * he_ntt_inv, without the NTT-form output passing through HBM (Sec. 6.2: all
+ * MACs in the NTT domain, only final results transformed back). */
+he_status he_conv_mac_intt(const he_ctx* ctx, const he_conv_desc* desc, uint32_t B, const uint64_t* d_in_ntt,
+                           const uint64_t* d_wntt, uint64_t* d_out, void* stream);
 
 /* The whole online layer: forward NTT of the B*CB*S input ciphertexts in
  * place (d_in is clobbered: it holds their NTT form afterwards), the MAC,

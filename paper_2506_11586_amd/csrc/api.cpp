@@ -216,7 +216,7 @@ he_status he_ctx_set_tuning(he_ctx* c, const he_tuning* t) {
   static const uint32_t tiles[][2] = {{0, 0}, {4, 4}, {4, 2}, {2, 4}, {8, 2}, {2, 8}, {8, 1}, {1, 8}, {2, 2}};
   bool ok = false;
   for (auto& p : tiles) ok |= (p[0] == t->mac_mt && p[1] == t->mac_rt);
-  if (!ok) return HE_EINVAL;
+  if (!ok || t->layer_fused > 1) return HE_EINVAL;
   c->tune = *t;
   return HE_OK;
 }
@@ -321,6 +321,17 @@ he_status he_conv_ntt_mac(const he_ctx* c, const he_conv_desc* d, uint32_t B, co
                                     c->tune.mac_mt, c->tune.mac_rt, (hipStream_t)stream));
 }
 
+he_status he_conv_mac_intt(const he_ctx* c, const he_conv_desc* d, uint32_t B, const uint64_t* d_in_ntt,
+                           const uint64_t* d_wntt, uint64_t* d_out, void* stream) {
+  if (check_ctx(c) || !d) return HE_EINVAL;
+  Geo g;
+  if (!geo_of(*d, c->N, g)) return HE_ESHAPE;
+  if (B == 0) return HE_OK;
+  if (!d_in_ntt || !d_wntt || !d_out) return HE_EINVAL;
+  return dev_err(heconv::mac_intt_launch(c->logN, d_in_ntt, d_wntt, d_out, B, g.CB, g.S, d->M, c->L, c->d_inv,
+                                         c->d_lc, (hipStream_t)stream));
+}
+
 he_status he_conv_layer(const he_ctx* c, const he_conv_desc* d, uint32_t B, uint64_t* d_in, const uint64_t* d_wntt,
                         uint64_t* d_out, void* stream) {
   if (check_ctx(c) || !d) return HE_EINVAL;
@@ -330,6 +341,7 @@ he_status he_conv_layer(const he_ctx* c, const he_conv_desc* d, uint32_t B, uint
   if (!d_in || !d_wntt || !d_out) return HE_EINVAL;
   he_status s = he_ntt_fwd(c, d_in, (uint64_t)B * g.CB * g.S * 2, stream);
   if (s) return s;
+  if (c->tune.layer_fused) return he_conv_mac_intt(c, d, B, d_in, d_wntt, d_out, stream);
   s = he_conv_ntt_mac(c, d, B, d_in, d_wntt, d_out, stream);
   if (s) return s;
   return he_ntt_inv(c, d_out, (uint64_t)B * d->M * g.S * 2, stream);

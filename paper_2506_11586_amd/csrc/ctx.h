@@ -18,7 +18,7 @@ struct he_ctx {
   heconv::Tw* d_fwd = nullptr;  // [L][N] psi^brv(k) with Shoup quotient
   heconv::Tw* d_inv = nullptr;  // [L][N] psi^-brv(k) with Shoup quotient
   heconv::LimbConst* d_lc = nullptr;
-  he_tuning tune{3, 4, 512, 0, 0};
+  he_tuning tune{3, 4, 512, 0, 0, 0};
 };
 
 namespace heconv {

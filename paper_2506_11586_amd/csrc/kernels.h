@@ -28,4 +28,9 @@ hipError_t mac_launch(const uint64_t* in, const uint64_t* w, uint64_t* out, uint
                       uint32_t M, uint32_t L, uint32_t N, const LimbConst* lc, uint32_t mt, uint32_t rt,
                       hipStream_t st);
 
+// Fused MAC + inverse NTT: in (NTT form) x w -> out (coefficient form).
+hipError_t mac_intt_launch(uint32_t logN, const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t B,
+                           uint32_t CB, uint32_t S, uint32_t M, uint32_t L, const Tw* twi, const LimbConst* lc,
+                           hipStream_t st);
+
 }  // namespace heconv

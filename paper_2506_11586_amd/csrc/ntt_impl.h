@@ -154,18 +154,27 @@ __device__ __forceinline__ void ntt_fwd_poly(gword* __restrict__ a, const Tw* __
   for (int k = 0; k < E; k++) a[tid + k * T] = x[k];
 }
 
+// Inverse transform of NTT values already in registers in the top mapping
+// (register k of thread t = entry t + k*N/E); leaves the coefficients, in
+// the same mapping, canonical.
+template <int LOGN, int LOGE>
+__device__ __forceinline__ void ntt_inv_regs(uint64_t (&x)[1 << LOGE], const Tw* __restrict__ tw, const LimbConst& c,
+                                             uint64_t* lds, int tid) {
+  constexpr int TOP = LOGN - LOGE, REM = LOGN % LOGE;
+  exchange<LOGE, TOP, 0>(lds, x, tid);
+  if constexpr (REM > 0) inv_pass<LOGN, LOGE, 0, LOGE - REM, false>(x, tid, tw, c);
+  inv_rest<LOGN, LOGE, 0>(x, lds, tid, tw, c);
+}
+
 // Inverse transform of one limb polynomial a[N] (in place).
 template <int LOGN, int LOGE>
 __device__ __forceinline__ void ntt_inv_poly(gword* __restrict__ a, const Tw* __restrict__ tw, const LimbConst& c,
                                              uint64_t* lds, int tid) {
-  constexpr int N = 1 << LOGN, E = 1 << LOGE, T = N / E, TOP = LOGN - LOGE, REM = LOGN % LOGE;
+  constexpr int N = 1 << LOGN, E = 1 << LOGE, T = N / E;
   uint64_t x[E];
 #pragma unroll
   for (int k = 0; k < E; k++) x[k] = a[tid + k * T];  // coalesced, top mapping
-  exchange<LOGE, TOP, 0>(lds, x, tid);
-  if constexpr (REM > 0) inv_pass<LOGN, LOGE, 0, LOGE - REM, false>(x, tid, tw, c);
-  inv_rest<LOGN, LOGE, 0>(x, lds, tid, tw, c);
-  // the last pass ran at LO = n-LOGE: element j = tid + k*T, canonical
+  ntt_inv_regs<LOGN, LOGE>(x, tw, c, lds, tid);
 #pragma unroll
   for (int k = 0; k < E; k++) a[tid + k * T] = x[k];
 }

@@ -28,7 +28,7 @@ class Tuning(ctypes.Structure):
     """he_tuning: launch-shape choices (speed only, never results)."""
 
     _fields_ = [(n, ctypes.c_uint32) for n in ("ntt_loge_small", "ntt_loge_large", "ntt_small_below",
-                                               "mac_mt", "mac_rt")]
+                                               "mac_mt", "mac_rt", "layer_fused")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -90,6 +90,7 @@ def _lib_handle():
         L.he_ntt_inv.argtypes = [vp, vp, u64, vp]
         L.he_conv_ntt_mac.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
         L.he_conv_layer.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
+        L.he_conv_mac_intt.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
         L.he_batch_create.argtypes = [vp, P(_Job), u32, u32, P(vp)]
         L.he_batch_launch.argtypes = [vp, vp, i32]
         L.he_batch_status.argtypes = [vp, vp]
@@ -99,7 +100,8 @@ def _lib_handle():
         for name in ("he_batch_create", "he_batch_launch", "he_batch_status", "he_batch_info"):
             getattr(L, name).restype = i32
         for name in ("he_gen_primes", "he_ctx_create", "he_ctx_psi", "he_ctx_get_tuning", "he_ctx_set_tuning", "he_plan_conv", "he_plan_conv_host", "he_min_root", "he_conv_sizes",
-                     "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer"):
+                     "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer",
+                     "he_conv_mac_intt"):
             getattr(L, name).restype = i32
         _LIB = L
     return _LIB
@@ -258,6 +260,13 @@ class Context:
         _check(lib().he_conv_ntt_mac(self._h, ctypes.byref(d), int(B), _ptr(in_dev, B * s.in_cts * ct, "in"),
                                      _ptr(wntt_dev, s.w_words, "wntt"), _ptr(out_dev, B * s.out_cts * ct, "out"),
                                      _stream(stream)), "he_conv_ntt_mac")
+
+    def conv_mac_intt(self, d: ConvDesc, B: int, in_dev, wntt_dev, out_dev, stream=None):
+        s = self.sizes(d)
+        ct = 2 * self.L * self.N
+        _check(lib().he_conv_mac_intt(self._h, ctypes.byref(d), int(B), _ptr(in_dev, B * s.in_cts * ct, "in"),
+                                      _ptr(wntt_dev, s.w_words, "wntt"), _ptr(out_dev, B * s.out_cts * ct, "out"),
+                                      _stream(stream)), "he_conv_mac_intt")
 
     def conv_layer(self, d: ConvDesc, B: int, in_dev, wntt_dev, out_dev, stream=None):
         s = self.sizes(d)

@@ -204,3 +204,46 @@ def test_error_statuses():
             ctx.set_tuning(**bad)
         assert e.value.status == heconv.HE_EINVAL
     assert ctx.get_tuning().as_dict() == before
+
+
+@pytest.mark.parametrize("shape,params,packing,B", MAC_CASES)
+def test_fused_mac_intt_equals_mac_then_intt(shape, params, packing, B):
+    """he_conv_mac_intt = he_conv_ntt_mac followed by he_ntt_inv, word for
+    word (including the 128-bit fold case CB = 70 and all-(q-1) operands)."""
+    ctx, prm = ctx_and_prm(*params)
+    cv = oracle.Conv(*shape)
+    d = ctx.plan(shape, packing=packing)
+    g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+    x = rand_polys(21, B * g.CB * g.S * 2, prm)
+    w = rand_polys(22, cv.M * g.CB, prm)
+    if B == 2:
+        x[:] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)
+        w[:] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)
+    want = oracle.intt(oracle.conv_mac(x, w, B, g, cv.M, prm), prm)
+    out = empty_words(want.size)
+    ctx.conv_mac_intt(d, B, to_dev(x), to_dev(w), out)
+    assert np.array_equal(to_host(out).reshape(want.shape), want)
+
+
+@pytest.mark.parametrize("fused", [0, 1])
+def test_layer_fused_and_unfused_agree(fused):
+    """he_conv_layer with the MAC and inverse NTT fused or not: same words as
+    the oracle's flow on the 64->64 layer."""
+    cfg = synth.CONFIGS[2]
+    shape = cfg["layers"][0]
+    ctx, prm = ctx_and_prm(cfg["N"], cfg["L"], cfg["bits"])
+    ctx.set_tuning(layer_fused=fused)
+    cv = wl.conv_of(shape)
+    d = ctx.plan(shape)
+    g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+    x = rand_polys(31, g.CB * g.S * 2, prm)
+    K = Stream(32, synth.WEIGHT).ints(cv.M * cv.C * 9, -2 ** 8, 2 ** 8).reshape(cv.M, cv.C, 3, 3)
+    s = ctx.sizes(d)
+    wntt = empty_words(s.w_words)
+    ctx.encode_weights(d, to_dev(K), wntt)
+    out = empty_words(s.out_cts * 2 * prm.L * prm.N)
+    ctx.conv_layer(d, 1, to_dev(x), wntt, out)
+    want = oracle.conv_layer_ntt(x.reshape(1, g.CB, g.S, 2, prm.L, prm.N), oracle.encode_weights(K, cv, g, prm), 1, g,
+                                 cv.M, prm)
+    ctx.set_tuning(layer_fused=0)
+    assert np.array_equal(to_host(out).reshape(want.shape), want)
