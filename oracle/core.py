@@ -12,6 +12,8 @@ Paper passages (SecONNds, arXiv 2506.11586):
   coefficient encoding, sparse
   results, extraction .............. Sec. 6.1 (HE kernels) and Sec. 2.3
                                      (Cheetah paragraph)
+  server share, mask, extraction ... Sec. 7 (online protocol, linear
+                                     layers) and Sec. 6.2
 The paper gives no formula for the packing, no HE parameters and no tiling
 rule; the readings used (packing layout, largest primes, smallest root,
 bytes-objective planner, round-half-up decode) are listed with the design
@@ -494,3 +496,66 @@ def centre_mod(y: np.ndarray, t: int) -> np.ndarray:
     """y mod t, centred into [-t/2, t/2)."""
     r = np.mod(y, t)
     return np.where(r >= t // 2, r - t, r).astype(np.int64)
+
+
+# --------------------------------------------------------------------------
+# Protocol steps either side of the layer (Sec. 7, online protocol for
+# linear layers; Sec. 6.2, extraction of the sparse results)
+# --------------------------------------------------------------------------
+def add_share(ct, xs: np.ndarray, cv: Conv, g: Geometry, prm: Params) -> np.ndarray:
+    """The server folds its additive share of the layer input into the
+    client's input ciphertexts of one image: with m = pack_input(xs) (values
+    taken mod t), b_l <- b_l + delta_l * m mod q_l; the a components are
+    untouched.  ct [CB][S][2][L][N] in coefficient form -> a new array that
+    decrypts to the packing of (x_client + xs) mod t."""
+    m = pack_input(np.asarray(xs, dtype=np.int64), cv, g, prm.t, prm.N).astype(object)  # [CB][S][N]
+    out = _u64(ct).reshape(g.CB, g.S, 2, prm.L, prm.N).copy()
+    for l, q in enumerate(prm.q):
+        b = out[:, :, 1, l, :].astype(object)
+        out[:, :, 1, l, :] = ((b + prm.delta_l[l] * m) % q).astype(np.uint64)
+    return out
+
+
+def output_coeffs(cv: Conv, g: Geometry):
+    """For every output position (oy, ox) at the layer's stride: the tile s
+    and the coefficient index that hold it (as assemble_output reads them),
+    two int arrays [Ho][Wo]."""
+    step = 1 if g.sub else cv.stride
+    si, i = np.divmod(np.arange(g.Ho) * step, g.bh)
+    sj, j = np.divmod(np.arange(g.Wo) * step, g.bw)
+    s = si[:, None] * g.nsj + sj[None, :]
+    k = g.O + i[:, None] * g.Ww + j[None, :]
+    return s, k
+
+
+def mask_extract(out_ct, R: np.ndarray, e, cv: Conv, g: Geometry, prm: Params) -> np.ndarray:
+    """After the inverse NTT the server keeps only the b coefficients that
+    hold outputs, masked with its output share R (values taken mod t) and an
+    optional signed smudging term e (None = 0):
+    y[m][l][oy][ox] = b_l[slot(oy, ox)] - delta_l * R[m][oy][ox] + e[m][oy][ox] mod q_l.
+    out_ct [M][S][2][L][N] (coefficient form, one image) -> y [M][L][Ho][Wo].
+    The a components go to the client unchanged."""
+    s, k = output_coeffs(cv, g)
+    ct = _u64(out_ct).reshape(cv.M, g.S, 2, prm.L, prm.N)
+    Rm = np.mod(np.asarray(R, dtype=np.int64), prm.t).astype(object)
+    ev = 0 if e is None else np.asarray(e, dtype=np.int64).astype(object)
+    y = np.zeros((cv.M, prm.L, g.Ho, g.Wo), dtype=np.uint64)
+    for l, q in enumerate(prm.q):
+        b = ct[:, s, 1, l, k].astype(object)  # [M][Ho][Wo]
+        y[:, l] = ((b - prm.delta_l[l] * Rm + ev) % q).astype(np.uint64)
+    return y
+
+
+def decrypt_extracted(a_polys, y, sk, cv: Conv, g: Geometry, prm: Params, with_noise: bool = False):
+    """Client side: decode the extracted outputs y [M][L][Ho][Wo] with the a
+    components a_polys [M][S][L][N] of the output ciphertexts: the phase of
+    output (m, oy, ox) is y - (a*sk)[slot] mod q_l.  -> [M][Ho][Wo] centred."""
+    a = _u64(a_polys).reshape(cv.M * g.S, prm.L, prm.N)
+    ct0 = np.zeros((cv.M * g.S, 2, prm.L, prm.N), dtype=np.uint64)
+    ct0[:, 0] = a
+    v0 = bfv_phase(ct0, sk, prm).reshape(cv.M, g.S, prm.L, prm.N)  # -(a*sk) mod q_l
+    s, k = output_coeffs(cv, g)
+    v = np.zeros((cv.M, g.Ho, g.Wo, prm.L), dtype=np.uint64)
+    for l, q in enumerate(prm.q):
+        v[..., l] = ((_u64(y)[:, l].astype(object) + v0[:, s, l, k].astype(object)) % q).astype(np.uint64)
+    return bfv_decode(v, prm, with_noise)

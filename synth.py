@@ -24,6 +24,7 @@ M1 = np.uint64(0xBF58476D1CE4E5B9)
 M2 = np.uint64(0x94D049BB133111EB)
 
 KEY, UNIFORM, ERROR, INPUT, WEIGHT, ARRIVAL, MIX = 1, 2, 3, 4, 5, 6, 7
+SHARE, MASK, FLOOD = 8, 9, 10  # server input share, server output share (mask), smudging noise
 
 
 def _mix(z: np.ndarray) -> np.ndarray:
