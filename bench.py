@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched fire-module CNN section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-bottleneck", action="store_true",
+                    help="skip the batch-16 bottleneck residual CNN section (about 230 GiB resident)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -205,6 +207,10 @@ def main():
 
     if not args.no_batched:
         result["batched"] = run_batched(torch, heconv)
+    if not args.no_bottleneck:
+        torch.cuda.empty_cache()
+        result["bottleneck_b16"] = run_bottleneck(torch, heconv)
+        torch.cuda.empty_cache()
     if not args.no_serving:
         result["serving"] = run_serving(torch, heconv, args)
 
@@ -282,6 +288,128 @@ def run_batched(torch, heconv):
             "plain_ctpt_macs_per_s": macs / t_plain * 1e3, "batched_ctpt_macs_per_s": macs / t_batch * 1e3,
             "speedup": t_plain / t_batch, "bit_exact_vs_plain": bool(exact),
             "batched_form": "two chains of three grids (forward NTTs, MAC tiles, inverse NTTs), one hipGraph"}
+
+
+def run_bottleneck(torch, heconv):
+    """Bottleneck residual CNN (53 convs at 224 input, batch 16, N=8192, L=3)
+    with every layer solve of all 16 images resident at once: NTT-form
+    weights about 62 GiB, inputs 8 GiB, outputs about 159 GiB.  Plain: 53
+    he_conv_layer calls of 16 images each; batched: one he_batch (two chains
+    of three grids, one hipGraph).  Sampled output words of both are compared
+    with the oracle's definition, and the two outputs with each other by
+    per-layer checksums (sum and sum of squares of the words, mod 2^64).
+
+    Input words are drawn on the device (torch's seeded generator, uniform
+    mod q_l): 8 GiB of host-drawn words would dominate the set-up time.  The
+    oracle samples read the input words back from the device before the
+    first run."""
+    import oracle
+
+    cfg = synth.CONFIGS[4]
+    N, L, bits, B = cfg["N"], cfg["L"], cfg["bits"], cfg["batch"]
+    prm = oracle.Params(N, L, bits, 2 ** synth.T_BITS)
+    ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), 2 ** synth.T_BITS)
+    assert prm.q == ctx.q
+    qd = torch.tensor(ctx.q, dtype=torch.int64, device="cuda").view(1, L, 1)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64).copy()).cuda()
+    descs, sizes, Ks, wntts, ins, outs, macs = [], [], [], [], [], [], 0
+    t_enc = 0.0
+    for i, shape in enumerate(cfg["layers"]):
+        C, H, W, M, kh, kw, stride, pad = shape
+        d = ctx.plan(shape, batch=B)
+        s = ctx.sizes(d)
+        K = Stream(cfg["seed"] * 1000 + i, synth.WEIGHT).ints(M * C * kh * kw, *cfg["w_range"]).reshape(M, C, kh, kw)
+        w = torch.empty(s.w_words, dtype=torch.int64, device="cuda")
+        Kd = dev(K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.encode_weights(d, Kd, w)
+        torch.cuda.synchronize()
+        t_enc += time.perf_counter() - t0
+        del Kd
+        descs.append(d), sizes.append(s), Ks.append(K), wntts.append(w)
+        ins.append(torch.empty(B * s.in_cts * 2 * L * N, dtype=torch.int64, device="cuda"))
+        outs.append(torch.empty(B * s.out_cts * 2 * L * N, dtype=torch.int64, device="cuda"))
+        macs += B * M * s.CB * s.S
+    gen = torch.Generator(device="cuda")
+
+    def fill_inputs():
+        for j, x in enumerate(ins):
+            gen.manual_seed(4000 + j)
+            v = x.view(-1, L, N)
+            for r0 in range(0, v.shape[0], 4096):
+                r1 = min(v.shape[0], r0 + 4096)
+                v[r0:r1] = torch.randint(0, 2 ** 62, (r1 - r0, L, N), generator=gen, device="cuda") % qd
+
+    def checksums():
+        out = []
+        for o in outs:
+            s1 = s2 = 0
+            for c0 in range(0, o.numel(), 1 << 27):
+                ch = o[c0:c0 + (1 << 27)]
+                s1 += int(ch.sum())
+                s2 += int((ch * ch).sum())
+            out.append((s1 % 2 ** 64, s2 % 2 ** 64))
+        return out
+
+    # sampled words: (job, image, m, s, comp, limb, k), inputs read back now
+    fill_inputs()
+    rng = Stream(cfg["seed"], synth.MIX)
+    picks = []
+    for j in np.linspace(0, len(descs) - 1, 8).astype(int):
+        s, K = sizes[j], Ks[j]
+        M = K.shape[0]
+        b, m, sp, c, l, k = (int(rng.below(1, v)[0]) for v in (B, M, s.S, 2, L, N))
+        img = ins[j].view(B, -1)[b].cpu().numpy().view(np.uint64).reshape(1, s.CB, s.S, 2, L, N).copy()
+        picks.append((int(j), b, m, sp, c, l, k, img))
+    torch.cuda.synchronize()
+
+    def sampled():
+        got = []
+        for j, b, m, sp, c, l, k, _ in picks:
+            s = sizes[j]
+            idx = ((((b * Ks[j].shape[0] + m) * s.S + sp) * 2 + c) * L + l) * N + k
+            got.append(int(outs[j][idx].item()) % 2 ** 64)
+        return got
+
+    def plain():
+        for d, x, w, o in zip(descs, ins, wntts, outs):
+            ctx.conv_layer(d, B, x, w, o)
+
+    plain()
+    torch.cuda.synchronize()
+    got_plain, sums_plain = sampled(), checksums()
+    want = []
+    for (j, b, m, sp, c, l, k, img) in picks:
+        cv = oracle.Conv(*cfg["layers"][j])
+        d = descs[j]
+        g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+        wc = oracle.pack_weights(Ks[j][m:m + 1], cv, g, prm)
+        want.append(oracle.conv_layer_coeff(img, wc, g, prm, 0, 0, sp, c, l, k))
+    fill_inputs()
+    for o in outs:
+        o.zero_()
+    jobs = [(d, B, x, w, o) for d, x, w, o in zip(descs, ins, wntts, outs)]
+    bt = heconv.Batch(ctx, jobs, schedule=heconv.SCHED_TWO_CHAINS)
+    bt.launch(graph=True)
+    bt.status()
+    got_batch, sums_batch = sampled(), checksums()
+    t_plain = _timed(torch, plain, 3, warm=1)
+    t_batch = _timed(torch, lambda: bt.launch(graph=True), 3, warm=1)
+    n = len(descs) * B
+    res = {"workload": cfg["name"], "layer_solves": n, "ctpt_macs_per_pass": macs,
+           "resident_GiB": round(sum(t.numel() * 8 for t in wntts + ins + outs) / 2 ** 30, 1),
+           "offline_encode_ms": t_enc * 1e3,
+           "plain_ms": t_plain, "batched_ms": t_batch,
+           "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_batch * 1e3,
+           "plain_ctpt_macs_per_s": macs / t_plain * 1e3, "batched_ctpt_macs_per_s": macs / t_batch * 1e3,
+           "speedup": t_plain / t_batch,
+           "sampled_words_vs_oracle": len(picks),
+           "bit_exact": bool(got_plain == want and got_batch == want and sums_plain == sums_batch)}
+    bt.close()
+    del ins, outs, wntts, jobs
+    ctx.close()
+    return res
 
 
 def run_serving(torch, heconv, args):

@@ -49,8 +49,10 @@ typedef enum {
 
 /* BFV/RNS parameters.  N: ring degree, a power of two in [2^10, 2^14].
  * L: number of RNS limbs, 1..8.  q[0..L-1]: distinct primes, q_l = 1 mod 2N,
- * 2^30 < q_l < 2^60 (the MAC splits residues into 30-bit halves).  t: plaintext modulus (informational; the server-side path
- * does not depend on it). */
+ * 2^30 < q_l < 2^60 (the MAC splits residues into 30-bit halves).
+ * t: plaintext modulus.  The layer path does not depend on it; the protocol
+ * steps (he_add_share, he_mask_extract) need 2 <= t <= 2^62 and t < Q and
+ * return HE_EPARAM otherwise. */
 typedef struct {
   uint32_t N, L;
   const uint64_t* q;
@@ -104,13 +106,22 @@ void he_ctx_destroy(he_ctx* ctx);
  * by shape; supported pairs: (4,4) (4,2) (2,4) (8,2) (2,8) (8,1) (1,8) (2,2).
  * layer_fused: 1 = he_conv_layer runs the MAC and the inverse NTT as one
  * kernel (he_conv_mac_intt), 0 = as two (he_conv_ntt_mac, he_ntt_inv).
- * Defaults: {3, 4, 512, 0, 0, 0} (the fused kernel gives up the MAC's
- * register tiling, so it moves several times more data through L2 and is
- * slower on the 64->64 3x3 layer: 153 us against 106 us for the pair). */
+ * (the fused kernel gives up the MAC's register tiling, so it moves several
+ * times more data through L2 and is slower on the 64->64 3x3 layer: 153 us
+ * against 106 us for the pair).
+ * layer_split: 1, 2 or 4.  For one image (B = 1, M >= 8*split) he_conv_layer
+ * cuts the output channels into that many slices: their MACs run in order
+ * on the caller's stream, and the inverse NTT of each slice runs on the
+ * context's internal stream once its MAC is done, beside the next slice's
+ * MAC; the caller's stream then waits for the last transform.  The internal
+ * stream is shared by all calls on the context: concurrent calls on several
+ * streams should use 1.
+ * Defaults: {3, 4, 512, 0, 0, 0, 1}. */
 typedef struct {
   uint32_t ntt_loge_small, ntt_loge_large, ntt_small_below;
   uint32_t mac_mt, mac_rt;
   uint32_t layer_fused;
+  uint32_t layer_split;
 } he_tuning;
 
 he_status he_ctx_get_tuning(const he_ctx* ctx, he_tuning* out);
@@ -181,6 +192,47 @@ he_status he_conv_mac_intt(const he_ctx* ctx, const he_conv_desc* desc, uint32_t
  * coefficient form. */
 he_status he_conv_layer(const he_ctx* ctx, const he_conv_desc* desc, uint32_t B, uint64_t* d_in,
                         const uint64_t* d_wntt, uint64_t* d_out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Protocol steps either side of the layer (Sec. 7, online protocol for a
+ * linear layer: the server adds its share of the input to the client's
+ * ciphertexts, runs the layer on NTT-preprocessed weights, masks the result;
+ * Sec. 6.2: only the coefficients that hold outputs are extracted).
+ * delta_l = floor(Q/t) mod q_l, Q = q_0 * ... * q_{L-1}.
+ * ------------------------------------------------------------------------ */
+
+/* delta_l for L moduli q[0..L-1] (host only, no device needed):
+ * HE_EPARAM if t is outside [2, 2^62] or exceeds Q (or some delta_l is 0). */
+he_status he_delta_host(const uint64_t* q, uint32_t L, uint64_t t, uint64_t* delta_out);
+
+/* Fold the server's additive share of the layer input into the client's
+ * input ciphertexts, before he_conv_layer: with m = the share packed as the
+ * layout above packs an input (values taken mod t, zero outside the
+ * tensor), b_l <- b_l + delta_l * m mod q_l for every ciphertext; the a
+ * components are untouched.  The result decrypts to (client share + server
+ * share) mod t.
+ * d_in: [B][CB][S][2][L][N] coefficient form, canonical, updated in place.
+ * d_share: int64 [B][C][H][W] (unpadded; any values, reduced mod t).
+ * HE_EPARAM if the context's t is unusable; B = 0 is a no-op. */
+he_status he_add_share(const he_ctx* ctx, const he_conv_desc* desc, uint32_t B, uint64_t* d_in,
+                       const int64_t* d_share, void* stream);
+
+/* Mask and extract the outputs, after he_conv_layer: for every output
+ * position (oy, ox) at the layer's stride (Ho = (H+2*pad-kh)/stride + 1,
+ * Wo likewise) take the b coefficient that holds it (tile and index as in
+ * the layout above; stride-1 position (oy*stride, ox*stride), or (oy, ox)
+ * for a strided 1x1 conv), and write
+ *   y[b][m][l][oy][ox] = b_l - delta_l * (mask mod t) + noise mod q_l.
+ * The mask is the server's output share (the client decrypts conv - mask
+ * mod t); noise is an optional signed smudging term per output (NULL = 0).
+ * The random values are drawn by the caller.  The a components of d_out
+ * are what the client needs besides y; they are not copied.
+ * d_out: [B][M][S][2][L][N] coefficient form (read only).
+ * d_mask, d_noise: int64 [B][M][Ho][Wo].  d_y: uint64 [B][M][L][Ho][Wo],
+ * written completely, canonical.
+ * HE_EPARAM if the context's t is unusable; B = 0 is a no-op. */
+he_status he_mask_extract(const he_ctx* ctx, const he_conv_desc* desc, uint32_t B, const uint64_t* d_out,
+                          const int64_t* d_mask, const int64_t* d_noise, uint64_t* d_y, void* stream);
 
 /* ------------------------------------------------------------------------
  * Batch executor: many layer solves of uneven shape in one launch.

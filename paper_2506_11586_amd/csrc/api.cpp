@@ -84,6 +84,40 @@ uint64_t min_root(uint64_t q, uint32_t N) {
 
 uint64_t shoup(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
 
+// delta_l = floor(Q/t) mod q_l for Q = prod q_l, in multi-word arithmetic
+// (little-endian 64-bit words).  All zero when t is outside [2, 2^62] or
+// t > Q: the protocol steps then refuse to run.
+std::vector<uint64_t> deltas(const std::vector<uint64_t>& q, uint64_t t) {
+  std::vector<uint64_t> out(q.size(), 0);
+  if (t < 2 || t > (1ull << 62)) return out;
+  std::vector<uint64_t> Q{1};
+  for (uint64_t ql : q) {
+    u128 carry = 0;
+    for (uint64_t& w : Q) {
+      const u128 p = (u128)w * ql + carry;
+      w = (uint64_t)p;
+      carry = p >> 64;
+    }
+    if (carry) Q.push_back((uint64_t)carry);
+  }
+  std::vector<uint64_t> D(Q.size());
+  u128 rem = 0;
+  bool nonzero = false;
+  for (size_t i = Q.size(); i-- > 0;) {
+    const u128 cur = (rem << 64) | Q[i];
+    D[i] = (uint64_t)(cur / t);
+    rem = cur % t;
+    nonzero |= D[i] != 0;
+  }
+  if (!nonzero) return out;
+  for (size_t l = 0; l < q.size(); l++) {
+    u128 r = 0;
+    for (size_t i = D.size(); i-- > 0;) r = ((r << 64) | D[i]) % q[l];
+    out[l] = (uint64_t)r;
+  }
+  return out;
+}
+
 }  // namespace
 
 namespace {
@@ -142,6 +176,8 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
   }
   c->N = N, c->logN = log2u(N), c->L = L, c->t = prm->t;
   c->q.assign(prm->q, prm->q + L);
+  const std::vector<uint64_t> dl = deltas(c->q, c->t);
+  c->proto_ok = std::all_of(dl.begin(), dl.end(), [](uint64_t v) { return v != 0; });
   std::vector<Tw> fwd((size_t)L * N), inv((size_t)L * N);
   std::vector<uint64_t> pw(N);
   for (uint32_t l = 0; l < L; l++) {
@@ -171,6 +207,7 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
     k.mu64 = (uint64_t)(((u128)1 << 64) / q);
     k.c30 = (uint64_t)(((u128)1 << 30) % q), k.c30_sh = shoup(k.c30, q);
     k.c60 = (uint64_t)(((u128)1 << 60) % q), k.c60_sh = shoup(k.c60, q);
+    k.delta = dl[l], k.delta_sh = shoup(dl[l], q);
     c->lc.push_back(k);
   }
   const size_t tb = sizeof(Tw) * (size_t)L * N;
@@ -178,6 +215,14 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
       hipMalloc(&c->d_lc, sizeof(LimbConst) * L) != hipSuccess) {
     he_ctx_destroy(c);
     return HE_ENOMEM;
+  }
+  bool ok_ev = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < 4 && ok_ev; i++)
+    ok_ev = hipEventCreateWithFlags(&c->ev_mac[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok_ev) {
+    he_ctx_destroy(c);
+    return HE_EDEVICE;
   }
   if (hipMemcpy(c->d_fwd, fwd.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_inv, inv.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
@@ -194,6 +239,10 @@ void he_ctx_destroy(he_ctx* c) {
   if (c->d_fwd) (void)hipFree(c->d_fwd);
   if (c->d_inv) (void)hipFree(c->d_inv);
   if (c->d_lc) (void)hipFree(c->d_lc);
+  for (int i = 0; i < 4; i++)
+    if (c->ev_mac[i]) (void)hipEventDestroy(c->ev_mac[i]);
+  if (c->ev_done) (void)hipEventDestroy(c->ev_done);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
 }
 
@@ -217,6 +266,7 @@ he_status he_ctx_set_tuning(he_ctx* c, const he_tuning* t) {
   bool ok = false;
   for (auto& p : tiles) ok |= (p[0] == t->mac_mt && p[1] == t->mac_rt);
   if (!ok || t->layer_fused > 1) return HE_EINVAL;
+  if (t->layer_split != 1 && t->layer_split != 2 && t->layer_split != 4) return HE_EINVAL;
   c->tune = *t;
   return HE_OK;
 }
@@ -339,12 +389,87 @@ he_status he_conv_layer(const he_ctx* c, const he_conv_desc* d, uint32_t B, uint
   if (!geo_of(*d, c->N, g)) return HE_ESHAPE;
   if (B == 0) return HE_OK;
   if (!d_in || !d_wntt || !d_out) return HE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
   he_status s = he_ntt_fwd(c, d_in, (uint64_t)B * g.CB * g.S * 2, stream);
   if (s) return s;
   if (c->tune.layer_fused) return he_conv_mac_intt(c, d, B, d_in, d_wntt, d_out, stream);
-  s = he_conv_ntt_mac(c, d, B, d_in, d_wntt, d_out, stream);
-  if (s) return s;
-  return he_ntt_inv(c, d_out, (uint64_t)B * d->M * g.S * 2, stream);
+  const uint32_t P = c->tune.layer_split;
+  if (P == 1 || B != 1 || d->M < 8 * P) {
+    s = he_conv_ntt_mac(c, d, B, d_in, d_wntt, d_out, stream);
+    if (s) return s;
+    return he_ntt_inv(c, d_out, (uint64_t)B * d->M * g.S * 2, stream);
+  }
+  // One image: output channels in slices (contiguous in the weights and in
+  // the output).  The slices' MACs run one after another on the caller's
+  // stream; the inverse NTT of slice p runs on the context's internal
+  // stream once MAC p is done, beside MAC p+1 (HBM-bound MAC, VALU-bound
+  // transform).  The caller's stream then waits for the last transform.
+  const uint64_t w_per_m = (uint64_t)g.CB * c->L * c->N, out_per_m = (uint64_t)g.S * 2 * c->L * c->N;
+  uint32_t m0 = 0;
+  for (uint32_t p = 0; p < P; p++) {
+    // slice boundaries on multiples of 4 (the MAC's channel tile)
+    const uint32_t m_end = p + 1 == P ? d->M : (uint32_t)((uint64_t)d->M * (p + 1) / P) & ~3u;
+    const uint32_t Mp = m_end - m0;
+    s = dev_err(heconv::mac_launch(d_in, d_wntt + m0 * w_per_m, d_out + m0 * out_per_m, 1, g.CB, g.S, Mp, c->L,
+                                   c->N, c->d_lc, c->tune.mac_mt, c->tune.mac_rt, st));
+    if (s) return s;
+    if (hipEventRecord(c->ev_mac[p], st) != hipSuccess || hipStreamWaitEvent(c->aux, c->ev_mac[p], 0) != hipSuccess)
+      return HE_EDEVICE;
+    s = dev_err(heconv::ntt_launch(true, c->logN, ntt_loge(c, (uint64_t)Mp * g.S * 2), d_out + m0 * out_per_m,
+                                   (uint64_t)Mp * g.S * 2, c->L, c->d_inv, c->d_lc, c->aux));
+    if (s) return s;
+    m0 = m_end;
+  }
+  if (hipEventRecord(c->ev_done, c->aux) != hipSuccess || hipStreamWaitEvent(st, c->ev_done, 0) != hipSuccess)
+    return HE_EDEVICE;
+  return HE_OK;
+}
+
+namespace {
+
+// Geometry of the protocol kernels; HE_ESHAPE for an invalid descriptor.
+he_status proto_geom(const he_ctx* c, const he_conv_desc* d, uint32_t B, heconv::ProtoGeom& p) {
+  Geo g;
+  if (!geo_of(*d, c->N, g) || d->pad > (1u << 20) || d->H > (1u << 20) || d->W > (1u << 20)) return HE_ESHAPE;
+  p = heconv::ProtoGeom{};
+  p.B = B, p.C = d->C, p.H = d->H, p.W = d->W, p.M = d->M, p.Cw = d->Cw, p.Hw = d->Hw, p.Ww = d->Ww;
+  p.bh = g.bh, p.bw = g.bw, p.nsj = g.nsj, p.S = g.S, p.CB = g.CB, p.O = g.O, p.He = g.He, p.We = g.We;
+  p.Ho = (d->H + 2 * d->pad - d->kh) / d->stride + 1, p.Wo = (d->W + 2 * d->pad - d->kw) / d->stride + 1;
+  p.step = g.sub ? d->stride : 1, p.ostep = g.sub ? 1 : d->stride;
+  p.pad = (int32_t)d->pad, p.L = c->L, p.N = c->N, p.t = c->t;
+  return HE_OK;
+}
+
+}  // namespace
+
+he_status he_delta_host(const uint64_t* q, uint32_t L, uint64_t t, uint64_t* delta_out) {
+  if (!q || !delta_out || L == 0 || L > 8) return HE_EINVAL;
+  const std::vector<uint64_t> dl = deltas(std::vector<uint64_t>(q, q + L), t);
+  if (!std::all_of(dl.begin(), dl.end(), [](uint64_t v) { return v != 0; })) return HE_EPARAM;
+  std::copy(dl.begin(), dl.end(), delta_out);
+  return HE_OK;
+}
+
+he_status he_add_share(const he_ctx* c, const he_conv_desc* d, uint32_t B, uint64_t* d_in, const int64_t* d_share,
+                       void* stream) {
+  if (check_ctx(c) || !d) return HE_EINVAL;
+  heconv::ProtoGeom p;
+  if (he_status s = proto_geom(c, d, B, p)) return s;
+  if (!c->proto_ok) return HE_EPARAM;
+  if (B == 0) return HE_OK;
+  if (!d_in || !d_share) return HE_EINVAL;
+  return dev_err(heconv::add_share_launch(d_in, d_share, p, c->d_lc, (hipStream_t)stream));
+}
+
+he_status he_mask_extract(const he_ctx* c, const he_conv_desc* d, uint32_t B, const uint64_t* d_out,
+                          const int64_t* d_mask, const int64_t* d_noise, uint64_t* d_y, void* stream) {
+  if (check_ctx(c) || !d) return HE_EINVAL;
+  heconv::ProtoGeom p;
+  if (he_status s = proto_geom(c, d, B, p)) return s;
+  if (!c->proto_ok) return HE_EPARAM;
+  if (B == 0) return HE_OK;
+  if (!d_out || !d_mask || !d_y) return HE_EINVAL;
+  return dev_err(heconv::mask_extract_launch(d_out, d_mask, d_noise, d_y, p, c->d_lc, (hipStream_t)stream));
 }
 
 }  // extern "C"

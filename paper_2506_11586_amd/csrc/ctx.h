@@ -13,12 +13,17 @@ struct he_ctx {
   int device = 0;
   uint32_t N = 0, logN = 0, L = 0;
   uint64_t t = 0;
+  bool proto_ok = false;  // t usable by the protocol steps (delta_l != 0)
   std::vector<uint64_t> q, psi;
   std::vector<heconv::LimbConst> lc;
   heconv::Tw* d_fwd = nullptr;  // [L][N] psi^brv(k) with Shoup quotient
   heconv::Tw* d_inv = nullptr;  // [L][N] psi^-brv(k) with Shoup quotient
   heconv::LimbConst* d_lc = nullptr;
-  he_tuning tune{3, 4, 512, 0, 0, 0};
+  he_tuning tune{3, 4, 512, 0, 0, 0, 1};
+  // internal stream and events of the output-channel pipeline of he_conv_layer
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_mac[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_done = nullptr;
 };
 
 namespace heconv {

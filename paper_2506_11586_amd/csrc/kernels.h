@@ -33,4 +33,24 @@ hipError_t mac_intt_launch(uint32_t logN, const uint64_t* in, const uint64_t* w,
                            uint32_t CB, uint32_t S, uint32_t M, uint32_t L, const Tw* twi, const LimbConst* lc,
                            hipStream_t st);
 
+// Geometry of the protocol steps around a layer (conv, packing, tiling).
+struct ProtoGeom {
+  uint32_t B, C, H, W, M, Cw, Hw, Ww;
+  uint32_t bh, bw, nsj, S, CB, O, He, We, Ho, Wo;
+  uint32_t step;   // stride of the packed tensor's rows/columns in the padded input (strided 1x1: stride, else 1)
+  uint32_t ostep;  // stride-1 output rows/columns per kept output (1 for a strided 1x1 conv, else stride)
+  int32_t pad;
+  uint32_t L, N;
+  uint64_t t;
+};
+
+// b_l += delta_l * pack(share) mod q_l for in [B][CB][S][2][L][N], share
+// [B][C][H][W] (values taken mod t).
+hipError_t add_share_launch(uint64_t* in, const int64_t* share, const ProtoGeom& g, const LimbConst* lc,
+                            hipStream_t st);
+
+// y[b][m][l][oy][ox] = b-coefficient of output (oy, ox) - delta_l * mask + noise mod q_l.
+hipError_t mask_extract_launch(const uint64_t* out, const int64_t* mask, const int64_t* noise, uint64_t* y,
+                               const ProtoGeom& g, const LimbConst* lc, hipStream_t st);
+
 }  // namespace heconv

@@ -19,6 +19,7 @@ struct LimbConst {
   uint64_t mu64;               // floor(2^64 / q): Shoup quotient of w = 1
   uint64_t c30, c30_sh;        // 2^30 mod q and its Shoup quotient
   uint64_t c60, c60_sh;        // 2^60 mod q and its Shoup quotient
+  uint64_t delta, delta_sh;    // floor(Q/t) mod q and its Shoup quotient (0 if t is unusable)
 };
 
 // Device buffers are passed to the transform and MAC bodies as pointers in

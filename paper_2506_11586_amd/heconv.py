@@ -28,7 +28,7 @@ class Tuning(ctypes.Structure):
     """he_tuning: launch-shape choices (speed only, never results)."""
 
     _fields_ = [(n, ctypes.c_uint32) for n in ("ntt_loge_small", "ntt_loge_large", "ntt_small_below",
-                                               "mac_mt", "mac_rt", "layer_fused")]
+                                               "mac_mt", "mac_rt", "layer_fused", "layer_split")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -91,6 +91,9 @@ def _lib_handle():
         L.he_conv_ntt_mac.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
         L.he_conv_layer.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
         L.he_conv_mac_intt.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
+        L.he_delta_host.argtypes = [P(u64), u32, u64, P(u64)]
+        L.he_add_share.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp]
+        L.he_mask_extract.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp, vp]
         L.he_batch_create.argtypes = [vp, P(_Job), u32, u32, P(vp)]
         L.he_batch_launch.argtypes = [vp, vp, i32]
         L.he_batch_status.argtypes = [vp, vp]
@@ -101,7 +104,7 @@ def _lib_handle():
             getattr(L, name).restype = i32
         for name in ("he_gen_primes", "he_ctx_create", "he_ctx_psi", "he_ctx_get_tuning", "he_ctx_set_tuning", "he_plan_conv", "he_plan_conv_host", "he_min_root", "he_conv_sizes",
                      "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer",
-                     "he_conv_mac_intt"):
+                     "he_conv_mac_intt", "he_add_share", "he_mask_extract", "he_delta_host"):
             getattr(L, name).restype = i32
         _LIB = L
     return _LIB
@@ -128,6 +131,14 @@ def plan_host(N: int, L: int, shape, batch: int = 1) -> ConvDesc:
     d = ConvDesc(*[int(v) for v in shape], 0, 0, 0)
     _check(lib().he_plan_conv_host(int(N), int(L), ctypes.byref(d), int(batch)), "he_plan_conv_host")
     return d
+
+
+def delta_host(q: list[int], t: int) -> list[int]:
+    """The library's delta_l = floor(Q/t) mod q_l (host only)."""
+    qa = (ctypes.c_uint64 * len(q))(*[int(v) for v in q])
+    out = (ctypes.c_uint64 * len(q))()
+    _check(lib().he_delta_host(qa, len(q), int(t), out), "he_delta_host")
+    return [int(v) for v in out]
 
 
 def min_root(q: int, N: int) -> int:
@@ -274,6 +285,28 @@ class Context:
         _check(lib().he_conv_layer(self._h, ctypes.byref(d), int(B), _ptr(in_dev, B * s.in_cts * ct, "in"),
                                    _ptr(wntt_dev, s.w_words, "wntt"), _ptr(out_dev, B * s.out_cts * ct, "out"),
                                    _stream(stream)), "he_conv_layer")
+
+    @staticmethod
+    def out_hw(d: ConvDesc) -> tuple[int, int]:
+        """(Ho, Wo): output size at the layer's stride."""
+        return ((d.H + 2 * d.pad - d.kh) // d.stride + 1, (d.W + 2 * d.pad - d.kw) // d.stride + 1)
+
+    def add_share(self, d: ConvDesc, B: int, in_dev, share_dev, stream=None):
+        """he_add_share: b_l += delta_l * pack(share) on the input cts (in place)."""
+        s = self.sizes(d)
+        _check(lib().he_add_share(self._h, ctypes.byref(d), int(B),
+                                  _ptr(in_dev, B * s.in_cts * 2 * self.L * self.N, "in"),
+                                  _ptr(share_dev, B * d.C * d.H * d.W, "share"), _stream(stream)), "he_add_share")
+
+    def mask_extract(self, d: ConvDesc, B: int, out_dev, mask_dev, noise_dev, y_dev, stream=None):
+        """he_mask_extract: y[b][m][l][oy][ox] = masked output coefficients."""
+        s = self.sizes(d)
+        Ho, Wo = self.out_hw(d)
+        n = B * d.M * Ho * Wo
+        _check(lib().he_mask_extract(self._h, ctypes.byref(d), int(B),
+                                     _ptr(out_dev, B * s.out_cts * 2 * self.L * self.N, "out"),
+                                     _ptr(mask_dev, n, "mask"), _ptr(noise_dev, n, "noise"),
+                                     _ptr(y_dev, n * self.L, "y"), _stream(stream)), "he_mask_extract")
 
 
 class Batch:

@@ -199,7 +199,8 @@ def test_error_statuses():
     st = heconv.lib().he_conv_layer(ctx.handle, heconv.ctypes.byref(d), 1, None, None, None, None)
     assert st == heconv.HE_EINVAL
     before = ctx.get_tuning().as_dict()
-    for bad in (dict(ntt_loge_small=5), dict(mac_mt=3, mac_rt=3)):
+    for bad in (dict(ntt_loge_small=5), dict(mac_mt=3, mac_rt=3), dict(layer_fused=2), dict(layer_split=3),
+                dict(layer_split=0)):
         with pytest.raises(heconv.HeError) as e:
             ctx.set_tuning(**bad)
         assert e.value.status == heconv.HE_EINVAL
@@ -225,14 +226,15 @@ def test_fused_mac_intt_equals_mac_then_intt(shape, params, packing, B):
     assert np.array_equal(to_host(out).reshape(want.shape), want)
 
 
-@pytest.mark.parametrize("fused", [0, 1])
-def test_layer_fused_and_unfused_agree(fused):
-    """he_conv_layer with the MAC and inverse NTT fused or not: same words as
-    the oracle's flow on the 64->64 layer."""
+@pytest.mark.parametrize("fused,split", [(0, 1), (1, 1), (0, 2), (0, 4)])
+def test_layer_modes_agree(fused, split):
+    """he_conv_layer with the MAC and inverse NTT fused or not, and split over
+    output-channel slices on internal streams or not: same words as the
+    oracle's flow on the 64->64 layer."""
     cfg = synth.CONFIGS[2]
     shape = cfg["layers"][0]
     ctx, prm = ctx_and_prm(cfg["N"], cfg["L"], cfg["bits"])
-    ctx.set_tuning(layer_fused=fused)
+    ctx.set_tuning(layer_fused=fused, layer_split=split)
     cv = wl.conv_of(shape)
     d = ctx.plan(shape)
     g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
@@ -245,5 +247,28 @@ def test_layer_fused_and_unfused_agree(fused):
     ctx.conv_layer(d, 1, to_dev(x), wntt, out)
     want = oracle.conv_layer_ntt(x.reshape(1, g.CB, g.S, 2, prm.L, prm.N), oracle.encode_weights(K, cv, g, prm), 1, g,
                                  cv.M, prm)
-    ctx.set_tuning(layer_fused=0)
+    ctx.set_tuning(layer_fused=0, layer_split=1)
+    assert np.array_equal(to_host(out).reshape(want.shape), want)
+
+
+@pytest.mark.parametrize("M,split", [(33, 4), (19, 2), (7, 4)])
+def test_layer_split_ragged_channels(M, split):
+    """Channel slices with M not a multiple of 4 (and M below 8*split, where
+    the layer runs unsplit): same words as the oracle."""
+    ctx, prm = ctx_and_prm(4096, 2, 50)
+    ctx.set_tuning(layer_split=split)
+    shape = (5, 12, 12, M, 3, 3, 1, 1)
+    cv = wl.conv_of(shape)
+    d = ctx.plan(shape)
+    g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+    x = rand_polys(41, g.CB * g.S * 2, prm)
+    K = Stream(42, synth.WEIGHT).ints(cv.M * cv.C * 9, -2 ** 8, 2 ** 8).reshape(cv.M, cv.C, 3, 3)
+    s = ctx.sizes(d)
+    wntt = empty_words(s.w_words)
+    ctx.encode_weights(d, to_dev(K), wntt)
+    out = empty_words(s.out_cts * 2 * prm.L * prm.N)
+    ctx.conv_layer(d, 1, to_dev(x), wntt, out)
+    want = oracle.conv_layer_ntt(x.reshape(1, g.CB, g.S, 2, prm.L, prm.N), oracle.encode_weights(K, cv, g, prm), 1, g,
+                                 cv.M, prm)
+    ctx.set_tuning(layer_split=1)
     assert np.array_equal(to_host(out).reshape(want.shape), want)

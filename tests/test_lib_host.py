@@ -75,3 +75,24 @@ def test_planner_matches_oracle_on_every_workload_shape():
             d = heconv.plan_host(N, L, s, B)
             g = oracle.plan_conv(oracle.Conv(*s), N, L, B)
             assert (d.Cw, d.Hw, d.Ww) == (g.Cw, g.Hw, g.Ww), (s, B)
+
+
+@pytest.mark.parametrize("N,bits,L,t", [(4096, 50, 2, 2 ** 37), (8192, 60, 3, 2 ** 37), (1024, 40, 4, 3),
+                                        (2048, 31, 1, 2 ** 30 + 3), (8192, 60, 8, 2 ** 62)])
+def test_delta_matches_oracle(N, bits, L, t):
+    """delta_l = floor(Q/t) mod q_l from the library's multi-word arithmetic
+    equals the oracle's Python big integers."""
+    ensure_built()
+    from paper_2506_11586_amd import heconv
+    prm = oracle.Params(N, L, bits, t)
+    assert heconv.delta_host(prm.q, t) == prm.delta_l
+
+
+def test_delta_rejects_unusable_t():
+    ensure_built()
+    from paper_2506_11586_amd import heconv
+    q = oracle.find_primes(1024, 31, 1)
+    for t in (0, 1, 2 ** 62 + 1, q[0] + 1):
+        with pytest.raises(heconv.HeError) as e:
+            heconv.delta_host(q, t)
+        assert e.value.status == heconv.HE_EPARAM
