@@ -498,11 +498,33 @@ def cpu_baseline(args, cfg, ctx, d, sz, x_host, K_host, gpu_out):
             break
     macs = B * cv.M * g.CB * g.S
     bit_exact = bool(np.array_equal(gpu_out.reshape(want.shape), want))
-    return ({"value": macs * reps / spent, "unit": "ct×pt MACs/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # the same flow on one core, one layer solve
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.conv_layer_ntt(x, w_ntt, B, g, cv.M, prm)
+    one_core = macs / (time.perf_counter() - t0)
+    oracle.set_threads(cores)
+    # the layer by definition (schoolbook negacyclic products, all cores) on
+    # the small 4->4 layer at N=4096
+    c1 = synth.CONFIGS[1]
+    p1 = oracle.Params(c1["N"], c1["L"], c1["bits"], 2 ** synth.T_BITS)
+    cv1 = oracle.Conv(*c1["layers"][0])
+    g1 = oracle.plan_conv(cv1, p1.N, p1.L)
+    x1 = synth.uniform_mod(Stream(c1["seed"], synth.UNIFORM), (1, g1.CB, g1.S, 2, p1.L, p1.N), p1.q)
+    K1 = Stream(c1["seed"], synth.WEIGHT).ints(cv1.M * cv1.C * 9, *c1["w_range"]).reshape(cv1.M, cv1.C, 3, 3)
+    t0 = time.perf_counter()
+    oracle.conv_layer_def(x1, oracle.pack_weights(K1, cv1, g1, p1), 1, g1, cv1.M, p1)
+    def_rate = cv1.M * g1.CB * g1.S / (time.perf_counter() - t0)
+    return ({"value": macs * reps / spent, "unit": "ct×pt MACs/s", "cores": cores,
              "kind": "oracle",
              "sample": f"{reps} full layer solve(s) of the same workload through the oracle's textbook "
                        f"NTT flow (forward NTT, MAC, inverse NTT; OpenMP over limb polynomials), "
-                       f"{spent:.1f} s; weight preprocessing {enc_s:.2f} s not included"},
+                       f"{spent:.1f} s; weight preprocessing {enc_s:.2f} s not included",
+             "value_one_core": one_core,
+             "value_by_definition_small_layer": def_rate,
+             "by_definition_sample": "one 4->4 3x3 16x16 layer solve at N=4096, L=2 by schoolbook negacyclic "
+                                     "products (O(N^2) per ct x pt product), all cores"},
             bit_exact)
 
 

@@ -67,6 +67,8 @@ def lib():
         L.or_bfv_encrypt.argtypes = [u64, u32, u32, _u64p, _u64p, _i64p, _u64p, _i64p, _u64p, _u64p, _u64p, i32]
         L.or_bfv_phase.argtypes = [u64, u32, u32, _u64p, _u64p, _i64p, _u64p, _u64p, i32]
         L.or_num_threads.restype = i32
+        L.or_set_threads.argtypes = [i32]
+        L.or_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -87,6 +89,11 @@ def _u64(x) -> np.ndarray:
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(lib().or_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads for the oracle's OpenMP loops from now on."""
+    lib().or_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------

@@ -436,3 +436,14 @@ int or_num_threads(void) {
   }
   return n;
 }
+
+/* Set the number of OpenMP threads of the parallel loops (n >= 1); used to
+ * time the oracle on one core as well as on all of them. */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  omp_set_num_threads(n < 1 ? 1 : n);
+#else
+  (void)n;
+#endif
+}
