@@ -208,6 +208,7 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
     k.c30 = (uint64_t)(((u128)1 << 30) % q), k.c30_sh = shoup(k.c30, q);
     k.c60 = (uint64_t)(((u128)1 << 60) % q), k.c60_sh = shoup(k.c60, q);
     k.delta = dl[l], k.delta_sh = shoup(dl[l], q);
+    k.negq = 0 - q, k.neg2q = 0 - 2 * q;
     c->lc.push_back(k);
   }
   const size_t tb = sizeof(Tw) * (size_t)L * N;

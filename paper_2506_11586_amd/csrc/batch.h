@@ -9,6 +9,8 @@
 namespace heconv {
 
 constexpr uint32_t BATCH_MAC_THREADS = 256;
+constexpr uint32_t BATCH_XCDS = 8;              // workgroup b of a grid runs on XCD b mod 8
+constexpr uint32_t BATCH_NO_JOB = 0xffffffffu;  // padding entry of a MAC work list
 
 struct BatchJob {
   uint64_t* in;             // [B][CB][S][2][L][N]

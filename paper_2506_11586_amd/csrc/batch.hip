@@ -20,7 +20,8 @@ __global__ __launch_bounds__((1 << LOGN) >> LOGE) void batch_fwd_kernel(const Ba
   const BatchItem it = items[blockIdx.x];
   gword* in = as_global(jobs[it.job].in);
   const uint32_t l = it.idx % L;
-  ntt_fwd_poly<LOGN, LOGE>(in + (size_t)it.idx * N, tw + (size_t)l * N, lcs[l].q, lcs[l].two_q, lds, threadIdx.x);
+  const LimbConst c = lcs[l];
+  ntt_fwd_poly<LOGN, LOGE>(in + (size_t)it.idx * N, tw + (size_t)l * N, c, lds, threadIdx.x);
 }
 
 template <int LOGN, int LOGE>
@@ -38,15 +39,18 @@ __global__ __launch_bounds__((1 << LOGN) >> LOGE) void batch_inv_kernel(const Ba
   ntt_inv_poly<LOGN, LOGE>(out + (size_t)it.idx * N, tw + (size_t)l * N, c, lds, threadIdx.x);
 }
 
-// MAC items are listed job by job, tile index k-chunk-major, so the XCD remap
-// keeps the tiles of one k-chunk (which share input and weight words) on one
-// XCD's L2.
+// MAC work list: the host interleaves eight per-XCD lists (workgroup b runs
+// on XCD b mod 8), each holding that XCD's share of every job's tiles --
+// a contiguous range of k-chunks, whose tiles share input and weight words
+// in the XCD's L2 -- so every XCD gets an equal slice of every job.  Padding
+// entries (job = BATCH_NO_JOB) end at once.
 template <int MT, int RT>
 __global__ __launch_bounds__(BATCH_MAC_THREADS) void batch_mac_kernel(const BatchItem* __restrict__ items,
                                                                        const BatchJob* __restrict__ jobs,
                                                                        const LimbConst* __restrict__ lcs,
                                                                        uint32_t L, uint32_t N) {
-  const BatchItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+  const BatchItem it = items[blockIdx.x];
+  if (it.job == BATCH_NO_JOB) return;
   const BatchJob jd = jobs[it.job];
   const uint32_t per_chunk = jd.n_mt * jd.n_rt;
   const uint32_t kc = it.idx / per_chunk;

@@ -138,9 +138,28 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
   for (uint32_t ch = 0; ch < b->n_chains; ch++) {
     for (int ph = 0; ph < 3; ph++) {
       off[ch][ph] = items.size();
-      for (uint32_t j = 0; j < n_jobs; j++) {
-        if (chain_of[j] != ch) continue;
-        for (uint64_t i = 0; i < (*counts[ph])[j]; i++) items.push_back(BatchItem{j, (uint32_t)i});
+      if (ph == 1) {
+        // MAC tiles: XCD x takes the x-th eighth of every job's tiles (tiles
+        // are k-chunk-major, so that is a contiguous range of k-chunks); the
+        // eight lists are interleaved (entry 8i+x runs on XCD x) and padded
+        // to equal length
+        std::vector<BatchItem> per[heconv::BATCH_XCDS];
+        for (uint32_t j = 0; j < n_jobs; j++) {
+          if (chain_of[j] != ch) continue;
+          const uint64_t T = n_mac[j];
+          for (uint32_t x = 0; x < heconv::BATCH_XCDS; x++)
+            for (uint64_t i = T * x / heconv::BATCH_XCDS; i < T * (x + 1) / heconv::BATCH_XCDS; i++)
+              per[x].push_back(BatchItem{j, (uint32_t)i});
+        }
+        size_t len = 0;
+        for (const auto& v : per) len = std::max(len, v.size());
+        for (size_t i = 0; i < len; i++)
+          for (const auto& v : per) items.push_back(i < v.size() ? v[i] : BatchItem{heconv::BATCH_NO_JOB, 0});
+      } else {
+        for (uint32_t j = 0; j < n_jobs; j++) {
+          if (chain_of[j] != ch) continue;
+          for (uint64_t i = 0; i < (*counts[ph])[j]; i++) items.push_back(BatchItem{j, (uint32_t)i});
+        }
       }
       cnt[ch][ph] = items.size() - off[ch][ph];
       if (cnt[ch][ph] > 0x7fffffffull) {

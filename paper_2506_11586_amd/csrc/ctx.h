@@ -19,7 +19,7 @@ struct he_ctx {
   heconv::Tw* d_fwd = nullptr;  // [L][N] psi^brv(k) with Shoup quotient
   heconv::Tw* d_inv = nullptr;  // [L][N] psi^-brv(k) with Shoup quotient
   heconv::LimbConst* d_lc = nullptr;
-  he_tuning tune{3, 4, 512, 0, 0, 0, 1};
+  he_tuning tune{3, 3, 512, 0, 0, 0, 1};
   // internal stream and events of the output-channel pipeline of he_conv_layer
   hipStream_t aux = nullptr;
   hipEvent_t ev_mac[4] = {nullptr, nullptr, nullptr, nullptr};

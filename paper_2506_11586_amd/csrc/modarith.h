@@ -20,6 +20,7 @@ struct LimbConst {
   uint64_t c30, c30_sh;        // 2^30 mod q and its Shoup quotient
   uint64_t c60, c60_sh;        // 2^60 mod q and its Shoup quotient
   uint64_t delta, delta_sh;    // floor(Q/t) mod q and its Shoup quotient (0 if t is unusable)
+  uint64_t negq, neg2q;        // 2^64 - q and 2^64 - 2q
 };
 
 // Device buffers are passed to the transform and MAC bodies as pointers in
@@ -45,6 +46,20 @@ __device__ __forceinline__ uint64_t mul_shoup_lazy(uint64_t x, uint64_t w, uint6
 }
 
 __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
+
+// The same two operations for the transforms' hot loops, written with the
+// negated modulus (negq = 2^64 - q, a value loaded from memory, so the
+// compiler keeps the additions): x*w + hi*negq is one multiply-add chain
+// with no 64-bit subtract, and the conditional subtract selects on the sign
+// of x - m, which holds for x, m < 2^63 (every value here is below 8q < 2^63).
+__device__ __forceinline__ uint64_t mul_shoup_neg(uint64_t x, uint64_t w, uint64_t wsh, uint64_t negq) {
+  return x * w + __umul64hi(x, wsh) * negq;  // in [0, 2q)
+}
+
+__device__ __forceinline__ uint64_t csub_neg(uint64_t x, uint64_t negm) {
+  const uint64_t d = x + negm;
+  return (int64_t)d < 0 ? x : d;
+}
 
 // x < 2^64 reduced into [0, 2q) (Shoup with w = 1).
 __device__ __forceinline__ uint64_t reduce64_lazy(uint64_t x, uint64_t mu64, uint64_t q) {

@@ -13,8 +13,8 @@ __global__ __launch_bounds__((1 << LOGN) >> LOGE) void ntt_fwd_kernel(uint64_t* 
   __shared__ uint64_t lds[N + N / 16];
   const uint32_t p = blockIdx.x;
   const uint32_t l = p % L;
-  ntt_fwd_poly<LOGN, LOGE>(as_global(polys) + (size_t)p * N, tw_all + (size_t)l * N, lcs[l].q, lcs[l].two_q, lds,
-                           threadIdx.x);
+  const LimbConst c = lcs[l];
+  ntt_fwd_poly<LOGN, LOGE>(as_global(polys) + (size_t)p * N, tw_all + (size_t)l * N, c, lds, threadIdx.x);
 }
 
 template <int LOGN, int LOGE>

@@ -35,9 +35,10 @@ __device__ __forceinline__ int elem_index(int tid, int k) {
 
 // Forward stages u in [U0, LOGE) of the pass at bit offset LO.
 template <int LOGN, int LOGE, int LO, int U0>
-__device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LOGE], int tid, const Tw* __restrict__ tw, uint64_t q,
-                                         uint64_t q2) {
+__device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LOGE], int tid, const Tw* __restrict__ tw,
+                                         const LimbConst& c) {
   const int high = tid >> LO;
+  const uint64_t q2 = c.two_q;
 #pragma unroll
   for (int u = U0; u < LOGE; u++) {
     const int s = LOGN - LOGE - LO + u;  // stage index: butterflies on bit LO+LOGE-1-u
@@ -48,8 +49,8 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LOGE], int tid, cons
 #pragma unroll
       for (int e = 0; e < half; e++) {
         const int k0 = g * 2 * half + e, k1 = k0 + half;
-        uint64_t X = csub(x[k0], q2);
-        uint64_t T = mul_shoup_lazy(x[k1], t.w, t.wsh, q);
+        uint64_t X = csub_neg(x[k0], c.neg2q);
+        uint64_t T = mul_shoup_neg(x[k1], t.w, t.wsh, c.negq);
         x[k0] = X + T;
         x[k1] = X - T + q2;
       }
@@ -64,7 +65,7 @@ template <int LOGN, int LOGE, int LO, int U0, bool LAST>
 __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LOGE], int tid, const Tw* __restrict__ tw,
                                          const LimbConst& c) {
   const int high = tid >> LO;
-  const uint64_t q = c.q, q2 = c.two_q;
+  const uint64_t q2 = c.two_q;
 #pragma unroll
   for (int u = LOGE - 1; u >= U0; u--) {
     const int s = LOGN - LOGE - LO + u;
@@ -74,8 +75,8 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LOGE], int tid, cons
       for (int e = 0; e < half; e++) {
         const int k0 = e, k1 = e + half;
         uint64_t X = x[k0], Y = x[k1];
-        x[k0] = csub(mul_shoup_lazy(X + Y, c.ninv, c.ninv_sh, q), q);
-        x[k1] = csub(mul_shoup_lazy(X - Y + q2, c.ninv_w, c.ninv_w_sh, q), q);
+        x[k0] = csub_neg(mul_shoup_neg(X + Y, c.ninv, c.ninv_sh, c.negq), c.negq);
+        x[k1] = csub_neg(mul_shoup_neg(X - Y + q2, c.ninv_w, c.ninv_w_sh, c.negq), c.negq);
       }
       continue;
     }
@@ -86,8 +87,8 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LOGE], int tid, cons
       for (int e = 0; e < half; e++) {
         const int k0 = g * 2 * half + e, k1 = k0 + half;
         uint64_t X = x[k0], Y = x[k1];
-        x[k0] = csub(X + Y, q2);
-        x[k1] = mul_shoup_lazy(X - Y + q2, t.w, t.wsh, q);
+        x[k0] = csub_neg(X + Y, c.neg2q);
+        x[k1] = mul_shoup_neg(X - Y + q2, t.w, t.wsh, c.negq);
       }
     }
   }
@@ -109,16 +110,16 @@ __device__ __forceinline__ void exchange(uint64_t* lds, uint64_t (&x)[1 << LOGE]
 // Forward full passes at LO = LOGN-LOGE*(P+1), then the partial pass.
 template <int LOGN, int LOGE, int P>
 __device__ __forceinline__ void fwd_rest(uint64_t (&x)[1 << LOGE], uint64_t* lds, int tid,
-                                         const Tw* __restrict__ tw, uint64_t q, uint64_t q2) {
+                                         const Tw* __restrict__ tw, const LimbConst& c) {
   constexpr int NFULL = LOGN / LOGE, REM = LOGN % LOGE;
   if constexpr (P < NFULL) {
     constexpr int LO = LOGN - LOGE * (P + 1);
     if constexpr (P > 0) exchange<LOGE, LO + LOGE, LO>(lds, x, tid);
-    fwd_pass<LOGN, LOGE, LO, 0>(x, tid, tw, q, q2);
-    fwd_rest<LOGN, LOGE, P + 1>(x, lds, tid, tw, q, q2);
+    fwd_pass<LOGN, LOGE, LO, 0>(x, tid, tw, c);
+    fwd_rest<LOGN, LOGE, P + 1>(x, lds, tid, tw, c);
   } else if constexpr (REM > 0) {
     exchange<LOGE, LOGN - LOGE * NFULL, 0>(lds, x, tid);
-    fwd_pass<LOGN, LOGE, 0, LOGE - REM>(x, tid, tw, q, q2);
+    fwd_pass<LOGN, LOGE, 0, LOGE - REM>(x, tid, tw, c);
   }
 }
 
@@ -140,15 +141,15 @@ __device__ __forceinline__ void inv_rest(uint64_t (&x)[1 << LOGE], uint64_t* lds
 // Forward transform of one limb polynomial a[N] (in place) by the calling
 // workgroup of N/2^LOGE threads.
 template <int LOGN, int LOGE>
-__device__ __forceinline__ void ntt_fwd_poly(gword* __restrict__ a, const Tw* __restrict__ tw, uint64_t q,
-                                             uint64_t q2, uint64_t* lds, int tid) {
+__device__ __forceinline__ void ntt_fwd_poly(gword* __restrict__ a, const Tw* __restrict__ tw, const LimbConst& c,
+                                             uint64_t* lds, int tid) {
   constexpr int N = 1 << LOGN, E = 1 << LOGE, T = N / E, TOP = LOGN - LOGE;
   uint64_t x[E];
 #pragma unroll
   for (int k = 0; k < E; k++) x[k] = a[tid + k * T];
-  fwd_rest<LOGN, LOGE, 0>(x, lds, tid, tw, q, q2);
+  fwd_rest<LOGN, LOGE, 0>(x, lds, tid, tw, c);
 #pragma unroll
-  for (int k = 0; k < E; k++) x[k] = csub(csub(x[k], q2), q);
+  for (int k = 0; k < E; k++) x[k] = csub_neg(csub_neg(x[k], c.neg2q), c.negq);
   exchange<LOGE, 0, TOP>(lds, x, tid);  // back to j = tid + k*T for a coalesced store
 #pragma unroll
   for (int k = 0; k < E; k++) a[tid + k * T] = x[k];

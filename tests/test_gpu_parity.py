@@ -47,6 +47,7 @@ def test_context_matches_oracle(N, L, bits):
 def test_ntt_forward_and_inverse(N, L, bits, loge):
     """Both launch shapes (8 or 16 words per thread) against the oracle."""
     ctx, prm = ctx_and_prm(N, L, bits)
+    before = ctx.get_tuning().as_dict()
     ctx.set_tuning(ntt_loge_small=loge, ntt_loge_large=loge)
     x = rand_polys(N + L, 3, prm)
     x[2] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)  # all q-1: lazy-range edge
@@ -63,7 +64,7 @@ def test_ntt_forward_and_inverse(N, L, bits, loge):
     d2 = to_dev(y)
     ctx.ntt_inv(d2, 2)
     assert np.array_equal(to_host(d2).reshape(y.shape), oracle.intt(y, prm))
-    ctx.set_tuning(ntt_loge_small=3, ntt_loge_large=4)
+    ctx.set_tuning(**before)
 
 
 def test_ntt_zero_count_is_noop():
