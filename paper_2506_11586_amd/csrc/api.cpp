@@ -84,6 +84,9 @@ uint64_t min_root(uint64_t q, uint32_t N) {
 
 uint64_t shoup(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
 
+// Shoup quotient at scale 2^63 (the transforms' twiddle tables).
+uint64_t shoup63(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 63) / q); }
+
 // delta_l = floor(Q/t) mod q_l for Q = prod q_l, in multi-word arithmetic
 // (little-endian 64-bit words).  All zero when t is outside [2, 2^62] or
 // t > Q: the protocol steps then refuse to run.
@@ -196,7 +199,7 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
       Tw* tab = (dir ? inv.data() : fwd.data()) + (size_t)l * N;
       for (uint32_t k = 0; k < N; k++) {
         const uint64_t w = pw[bitrev(k, c->logN)];
-        tab[k] = Tw{w, shoup(w, q)};
+        tab[k] = Tw{w, shoup63(w, q)};
       }
     }
     LimbConst k{};

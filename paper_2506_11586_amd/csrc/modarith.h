@@ -35,7 +35,8 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) 
   return (__attribute__((address_space(1))) T*)p;
 }
 
-// A twiddle with its Shoup quotient, stored side by side (one 16-byte load).
+// A twiddle with its Shoup quotient at scale 2^63, wsh = floor(w*2^63/q),
+// stored side by side (one 16-byte load).  See mul_shoup63.
 struct Tw {
   uint64_t w, wsh;
 };
@@ -54,6 +55,22 @@ __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) { return x >= m
 // of x - m, which holds for x, m < 2^63 (every value here is below 8q < 2^63).
 __device__ __forceinline__ uint64_t mul_shoup_neg(uint64_t x, uint64_t w, uint64_t wsh, uint64_t negq) {
   return x * w + __umul64hi(x, wsh) * negq;  // in [0, 2q)
+}
+
+// Shoup multiplication at scale 2^63 for x < 2^62 and wsh = floor(w*2^63/q)
+// (so wsh < 2^63): hi = floor(x*wsh / 2^63) = floor((2x)*wsh / 2^64), and
+// with both 2x and wsh below 2^63 the two 32x32 cross products plus the
+// carry word sum to less than 2^64, so the high word needs three
+// multiply-adds and no carry handling.  Result in [0, 2q) (the Shoup bound
+// holds for any x < 2^63 at this scale).
+__device__ __forceinline__ uint64_t mul_shoup63(uint64_t x, uint64_t w, uint64_t wsh, uint64_t negq) {
+  const uint64_t x2 = x << 1;
+  const uint32_t a0 = (uint32_t)x2, a1 = (uint32_t)(x2 >> 32);
+  const uint32_t b0 = (uint32_t)wsh, b1 = (uint32_t)(wsh >> 32);
+  uint64_t s = (uint64_t)a1 * b0 + __umulhi(a0, b0);
+  s += (uint64_t)a0 * b1;  // < 2^64: a1, b1 < 2^31
+  const uint64_t hi = (uint64_t)a1 * b1 + (s >> 32);
+  return x * w + hi * negq;
 }
 
 __device__ __forceinline__ uint64_t csub_neg(uint64_t x, uint64_t negm) {

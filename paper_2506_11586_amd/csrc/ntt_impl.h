@@ -8,7 +8,8 @@
 // inverse (Gentleman-Sande) uses the same index with psi^-1 and runs from
 // bit 0 up; its last stage also applies N^-1.  Lazy reduction after Harvey:
 // forward values stay in [0, 4q), inverse values in [0, 2q), and every
-// stored word is canonical.
+// stored word is canonical.  Every twiddle product has an input below
+// 4q < 2^62, as the scale-2^63 Shoup product (mul_shoup63) requires.
 //
 // Thread/element mapping of a pass over bits [lo, lo+LOGE): register k of
 // thread t holds element j = (t mod 2^lo) | k << lo | (t >> lo) << (lo+LOGE).
@@ -50,7 +51,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LOGE], int tid, cons
       for (int e = 0; e < half; e++) {
         const int k0 = g * 2 * half + e, k1 = k0 + half;
         uint64_t X = csub_neg(x[k0], c.neg2q);
-        uint64_t T = mul_shoup_neg(x[k1], t.w, t.wsh, c.negq);
+        uint64_t T = mul_shoup63(x[k1], t.w, t.wsh, c.negq);
         x[k0] = X + T;
         x[k1] = X - T + q2;
       }
@@ -88,7 +89,7 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LOGE], int tid, cons
         const int k0 = g * 2 * half + e, k1 = k0 + half;
         uint64_t X = x[k0], Y = x[k1];
         x[k0] = csub_neg(X + Y, c.neg2q);
-        x[k1] = mul_shoup_neg(X - Y + q2, t.w, t.wsh, c.negq);
+        x[k1] = mul_shoup63(X - Y + q2, t.w, t.wsh, c.negq);
       }
     }
   }
