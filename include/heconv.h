@@ -241,6 +241,38 @@ he_status he_mask_extract(const he_ctx* ctx, const he_conv_desc* desc, uint32_t 
                           const int64_t* d_mask, const int64_t* d_noise, uint64_t* d_y, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Client side on the GPU (App. C, symmetric-key BFV): encryption of
+ * coefficient-encoded messages and decryption, for load generation and for
+ * checking results.  These calls take the secret key; the server-side calls
+ * above never do.  Random values (a, e) are drawn by the caller.
+ * ------------------------------------------------------------------------ */
+
+/* The secret key in NTT form: d_sk_ntt[l][k] = NTT_l(sk mod q_l), from the
+ * key's N integer coefficients d_sk (int64, normally in {-1, 0, 1}). */
+he_status he_key_encode(const he_ctx* ctx, const int64_t* d_sk, uint64_t* d_sk_ntt, void* stream);
+
+/* Encrypt n messages: for each i and limb l,
+ *   ct[i][0][l] = a[i][l],  ct[i][1][l] = a[i][l]*sk + delta_l*(m[i] mod t) + e[i]  (mod q_l),
+ * products in Z_q[X]/(X^N+1).  d_msgs, d_err: int64 [n][N]; d_a: [n][L][N]
+ * canonical; d_sk_ntt from he_key_encode; d_ct: [n][2][L][N] written
+ * completely; d_work: [n][L][N] caller-provided scratch (clobbered).
+ * HE_EPARAM if the context's t is unusable; n = 0 is a no-op. */
+he_status he_encrypt(const he_ctx* ctx, uint64_t n, const int64_t* d_msgs, const uint64_t* d_a,
+                     const int64_t* d_err, const uint64_t* d_sk_ntt, uint64_t* d_ct, uint64_t* d_work,
+                     void* stream);
+
+/* Decrypt n ciphertexts [n][2][L][N]: v = b - a*sk per limb, then
+ * m = round(t*V/Q) mod t for V the CRT lift of v, centred into
+ * [-t/2, t/2), written to d_msgs (int64 [n][N]).  The rounding is computed
+ * from fixed-point constants (128-bit fractions, total error below
+ * L * 2^-68); it equals exact rounding whenever t*V/Q is not within that of
+ * a half-integer, which holds for every ciphertext whose noise is below
+ * delta/2 by a margin of a few units.  Needs t a power of two (HE_EPARAM
+ * otherwise).  d_work: [n][L][N] scratch. */
+he_status he_decrypt(const he_ctx* ctx, uint64_t n, const uint64_t* d_ct, const uint64_t* d_sk_ntt, int64_t* d_msgs,
+                     uint64_t* d_work, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batch executor: many layer solves of uneven shape in one launch.
  * Each job is one he_conv_layer call's worth of work (same buffers, same
  * result).  A batch runs the forward NTT of every job's input limb

@@ -214,9 +214,25 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
     k.negq = 0 - q, k.neg2q = 0 - 2 * q;
     c->lc.push_back(k);
   }
+  // client-side decoding constants (power-of-two t only)
+  std::vector<heconv::DecodeConst> dc(L);
+  c->decode_ok = c->proto_ok && pow2(c->t);
+  for (uint32_t l = 0; l < L && c->decode_ok; l++) {
+    const uint64_t q = c->q[l];
+    uint64_t qh = 1;
+    for (uint32_t j = 0; j < L; j++)
+      if (j != l) qh = mmul(qh, c->q[j] % q, q);
+    const uint64_t y = mpow(qh, q - 2, q);
+    const u128 ty = (u128)c->t * y;
+    const uint64_t r = (uint64_t)(ty % q);
+    const u128 r64 = (u128)r << 64;
+    const uint64_t fh = (uint64_t)(r64 / q), r2 = (uint64_t)(r64 % q);
+    dc[l] = heconv::DecodeConst{(uint64_t)(ty / q), fh, (uint64_t)(((u128)r2 << 64) / q)};
+  }
   const size_t tb = sizeof(Tw) * (size_t)L * N;
   if (hipMalloc(&c->d_fwd, tb) != hipSuccess || hipMalloc(&c->d_inv, tb) != hipSuccess ||
-      hipMalloc(&c->d_lc, sizeof(LimbConst) * L) != hipSuccess) {
+      hipMalloc(&c->d_lc, sizeof(LimbConst) * L) != hipSuccess ||
+      hipMalloc(&c->d_dc, sizeof(heconv::DecodeConst) * L) != hipSuccess) {
     he_ctx_destroy(c);
     return HE_ENOMEM;
   }
@@ -230,7 +246,8 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
   }
   if (hipMemcpy(c->d_fwd, fwd.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_inv, inv.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->d_lc, c->lc.data(), sizeof(LimbConst) * L, hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(c->d_lc, c->lc.data(), sizeof(LimbConst) * L, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_dc, dc.data(), sizeof(heconv::DecodeConst) * L, hipMemcpyHostToDevice) != hipSuccess) {
     he_ctx_destroy(c);
     return HE_EDEVICE;
   }
@@ -243,6 +260,7 @@ void he_ctx_destroy(he_ctx* c) {
   if (c->d_fwd) (void)hipFree(c->d_fwd);
   if (c->d_inv) (void)hipFree(c->d_inv);
   if (c->d_lc) (void)hipFree(c->d_lc);
+  if (c->d_dc) (void)hipFree(c->d_dc);
   for (int i = 0; i < 4; i++)
     if (c->ev_mac[i]) (void)hipEventDestroy(c->ev_mac[i]);
   if (c->ev_done) (void)hipEventDestroy(c->ev_done);
@@ -474,6 +492,73 @@ he_status he_mask_extract(const he_ctx* c, const he_conv_desc* d, uint32_t B, co
   if (B == 0) return HE_OK;
   if (!d_out || !d_mask || !d_y) return HE_EINVAL;
   return dev_err(heconv::mask_extract_launch(d_out, d_mask, d_noise, d_y, p, c->d_lc, (hipStream_t)stream));
+}
+
+// ---- client side (secret key on the device) ----
+
+he_status he_key_encode(const he_ctx* c, const int64_t* d_sk, uint64_t* d_sk_ntt, void* stream) {
+  if (check_ctx(c) || !d_sk || !d_sk_ntt) return HE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  he_status s = dev_err(heconv::key_lift_launch(d_sk, d_sk_ntt, c->N, c->L, c->d_lc, st));
+  if (s) return s;
+  return dev_err(heconv::ntt_launch(false, c->logN, ntt_loge(c, 1), d_sk_ntt, 1, c->L, c->d_fwd, c->d_lc, st));
+}
+
+namespace {
+
+// work[i] = a * sk (coefficient form) for the a polynomials at src (stride
+// src_stride words); with ct_out, a is also copied to ct_out[i][0].
+he_status key_product(const he_ctx* c, uint64_t n, const uint64_t* src, uint64_t src_stride, uint64_t* ct_out,
+                      const uint64_t* sk_ntt, uint64_t* work, hipStream_t st) {
+  he_status s = dev_err(heconv::copy_a_launch(src, src_stride, work, ct_out, n, c->N, c->L, st));
+  if (!s) s = dev_err(heconv::ntt_launch(false, c->logN, ntt_loge(c, n), work, n, c->L, c->d_fwd, c->d_lc, st));
+  if (!s) s = dev_err(heconv::pointwise_key_launch(work, sk_ntt, n, c->N, c->L, c->d_lc, st));
+  if (!s) s = dev_err(heconv::ntt_launch(true, c->logN, ntt_loge(c, n), work, n, c->L, c->d_inv, c->d_lc, st));
+  return s;
+}
+
+constexpr uint64_t CLIENT_CHUNK = 65535;  // RNS polynomials per launch (grid.y)
+
+}  // namespace
+
+he_status he_encrypt(const he_ctx* c, uint64_t n, const int64_t* d_msgs, const uint64_t* d_a, const int64_t* d_err,
+                     const uint64_t* d_sk_ntt, uint64_t* d_ct, uint64_t* d_work, void* stream) {
+  if (check_ctx(c)) return HE_EINVAL;
+  if (!c->proto_ok) return HE_EPARAM;
+  if (n == 0) return HE_OK;
+  if (!d_msgs || !d_a || !d_err || !d_sk_ntt || !d_ct || !d_work) return HE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t LN = (uint64_t)c->L * c->N;
+  for (uint64_t i0 = 0; i0 < n; i0 += CLIENT_CHUNK) {
+    const uint64_t m = n - i0 < CLIENT_CHUNK ? n - i0 : CLIENT_CHUNK;
+    uint64_t* ct = d_ct + i0 * 2 * LN;
+    he_status s = key_product(c, m, d_a + i0 * LN, LN, ct, d_sk_ntt, d_work, st);
+    if (!s)
+      s = dev_err(heconv::encrypt_finish_launch(d_work, d_msgs + i0 * c->N, d_err + i0 * c->N, ct, m, c->N, c->L,
+                                                c->t, c->d_lc, st));
+    if (s) return s;
+  }
+  return HE_OK;
+}
+
+he_status he_decrypt(const he_ctx* c, uint64_t n, const uint64_t* d_ct, const uint64_t* d_sk_ntt, int64_t* d_msgs,
+                     uint64_t* d_work, void* stream) {
+  if (check_ctx(c)) return HE_EINVAL;
+  if (!c->decode_ok) return HE_EPARAM;
+  if (n == 0) return HE_OK;
+  if (!d_ct || !d_sk_ntt || !d_msgs || !d_work) return HE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t LN = (uint64_t)c->L * c->N;
+  for (uint64_t i0 = 0; i0 < n; i0 += CLIENT_CHUNK) {
+    const uint64_t m = n - i0 < CLIENT_CHUNK ? n - i0 : CLIENT_CHUNK;
+    const uint64_t* ct = d_ct + i0 * 2 * LN;
+    he_status s = key_product(c, m, ct, 2 * LN, nullptr, d_sk_ntt, d_work, st);
+    if (!s)
+      s = dev_err(heconv::decrypt_finish_launch(ct, d_work, d_msgs + i0 * c->N, m, c->N, c->L, c->t, c->d_dc,
+                                                c->d_lc, st));
+    if (s) return s;
+  }
+  return HE_OK;
 }
 
 }  // extern "C"

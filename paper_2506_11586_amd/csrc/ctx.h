@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "heconv.h"
+#include "kernels.h"
 #include "modarith.h"
 
 struct he_ctx {
@@ -19,6 +20,8 @@ struct he_ctx {
   heconv::Tw* d_fwd = nullptr;  // [L][N] psi^brv(k) with Shoup quotient
   heconv::Tw* d_inv = nullptr;  // [L][N] psi^-brv(k) with Shoup quotient
   heconv::LimbConst* d_lc = nullptr;
+  heconv::DecodeConst* d_dc = nullptr;  // client-side decoding constants (t a power of two)
+  bool decode_ok = false;
   he_tuning tune{3, 3, 512, 0, 0, 0, 1};
   // internal stream and events of the output-channel pipeline of he_conv_layer
   hipStream_t aux = nullptr;

@@ -53,4 +53,24 @@ hipError_t add_share_launch(uint64_t* in, const int64_t* share, const ProtoGeom&
 hipError_t mask_extract_launch(const uint64_t* out, const int64_t* mask, const int64_t* noise, uint64_t* y,
                                const ProtoGeom& g, const LimbConst* lc, hipStream_t st);
 
+// Client-side decoding constants of one limb: with y_l = (Q/q_l)^-1 mod q_l,
+// ipart = floor(t*y_l/q_l) and (frac_hi, frac_lo) = floor(frac(t*y_l/q_l) * 2^128).
+struct DecodeConst {
+  uint64_t ipart, frac_hi, frac_lo;
+};
+
+// Client-side steps (secret key on the device): key lift, copy of the a
+// components, point-wise product with the transformed key, encryption and
+// decryption finish.  n <= 65535 RNS polynomials per call.
+hipError_t key_lift_launch(const int64_t* sk, uint64_t* out, uint32_t N, uint32_t L, const LimbConst* lc,
+                           hipStream_t st);
+hipError_t copy_a_launch(const uint64_t* src, uint64_t src_stride, uint64_t* work, uint64_t* ct_out, uint64_t n,
+                         uint32_t N, uint32_t L, hipStream_t st);
+hipError_t pointwise_key_launch(uint64_t* work, const uint64_t* sk_ntt, uint64_t n, uint32_t N, uint32_t L,
+                                const LimbConst* lc, hipStream_t st);
+hipError_t encrypt_finish_launch(const uint64_t* as, const int64_t* msg, const int64_t* err, uint64_t* ct, uint64_t n,
+                                 uint32_t N, uint32_t L, uint64_t t, const LimbConst* lc, hipStream_t st);
+hipError_t decrypt_finish_launch(const uint64_t* ct, const uint64_t* as, int64_t* out, uint64_t n, uint32_t N,
+                                 uint32_t L, uint64_t t, const DecodeConst* dc, const LimbConst* lc, hipStream_t st);
+
 }  // namespace heconv

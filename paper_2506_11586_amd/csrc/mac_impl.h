@@ -27,7 +27,10 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
   return (bid % 8) * per + bid / 8;
 }
 
-constexpr int MAC_DEPTH = 4;
+#ifndef HECONV_MAC_DEPTH
+#define HECONV_MAC_DEPTH 4
+#endif
+constexpr int MAC_DEPTH = HECONV_MAC_DEPTH;
 
 // One channel block: the four 30-bit partial products of every (m, row).
 template <int MT, int RT>
@@ -112,7 +115,13 @@ __device__ __forceinline__ void mac_tile(cgword* __restrict__ in, cgword* __rest
 #pragma unroll
         for (int i = 0; i < RT; i++) xr[d][i] = ip[i][(uint64_t)(cb + d) * in_cb_stride];
 #pragma unroll
-        for (int j = 0; j < MT; j++) wr[d][j] = wp[j][(uint64_t)(cb + d) * LN];
+        for (int j = 0; j < MT; j++) {
+#ifdef HECONV_MAC_NT
+          wr[d][j] = __builtin_nontemporal_load(&wp[j][(uint64_t)(cb + d) * LN]);
+#else
+          wr[d][j] = wp[j][(uint64_t)(cb + d) * LN];
+#endif
+        }
       }
 #pragma unroll
       for (int d = 0; d < MAC_DEPTH; d++) mac_step<MT, RT>(xr[d], wr[d], a00, a01, a10, a11);

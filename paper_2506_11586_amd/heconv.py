@@ -92,6 +92,9 @@ def _lib_handle():
         L.he_conv_layer.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
         L.he_conv_mac_intt.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp]
         L.he_delta_host.argtypes = [P(u64), u32, u64, P(u64)]
+        L.he_key_encode.argtypes = [vp, vp, vp, vp]
+        L.he_encrypt.argtypes = [vp, u64, vp, vp, vp, vp, vp, vp, vp]
+        L.he_decrypt.argtypes = [vp, u64, vp, vp, vp, vp, vp]
         L.he_add_share.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp]
         L.he_mask_extract.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp, vp]
         L.he_batch_create.argtypes = [vp, P(_Job), u32, u32, P(vp)]
@@ -104,7 +107,8 @@ def _lib_handle():
             getattr(L, name).restype = i32
         for name in ("he_gen_primes", "he_ctx_create", "he_ctx_psi", "he_ctx_get_tuning", "he_ctx_set_tuning", "he_plan_conv", "he_plan_conv_host", "he_min_root", "he_conv_sizes",
                      "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer",
-                     "he_conv_mac_intt", "he_add_share", "he_mask_extract", "he_delta_host"):
+                     "he_conv_mac_intt", "he_add_share", "he_mask_extract", "he_delta_host",
+                     "he_key_encode", "he_encrypt", "he_decrypt"):
             getattr(L, name).restype = i32
         _LIB = L
     return _LIB
@@ -307,6 +311,27 @@ class Context:
                                      _ptr(out_dev, B * s.out_cts * 2 * self.L * self.N, "out"),
                                      _ptr(mask_dev, n, "mask"), _ptr(noise_dev, n, "noise"),
                                      _ptr(y_dev, n * self.L, "y"), _stream(stream)), "he_mask_extract")
+
+    # -- client side (holds the secret key) ----------------------------------
+    def key_encode(self, sk_dev, sk_ntt_dev, stream=None):
+        """he_key_encode: sk (int64 [N]) -> NTT form [L][N]."""
+        _check(lib().he_key_encode(self._h, _ptr(sk_dev, self.N, "sk"), _ptr(sk_ntt_dev, self.L * self.N, "sk_ntt"),
+                                   _stream(stream)), "he_key_encode")
+
+    def encrypt(self, n: int, msgs_dev, a_dev, err_dev, sk_ntt_dev, ct_dev, work_dev, stream=None):
+        """he_encrypt: n coefficient-encoded messages -> ct [n][2][L][N]."""
+        LN = self.L * self.N
+        _check(lib().he_encrypt(self._h, int(n), _ptr(msgs_dev, n * self.N, "msgs"), _ptr(a_dev, n * LN, "a"),
+                                _ptr(err_dev, n * self.N, "err"), _ptr(sk_ntt_dev, LN, "sk_ntt"),
+                                _ptr(ct_dev, n * 2 * LN, "ct"), _ptr(work_dev, n * LN, "work"), _stream(stream)),
+               "he_encrypt")
+
+    def decrypt(self, n: int, ct_dev, sk_ntt_dev, msgs_dev, work_dev, stream=None):
+        """he_decrypt: ct [n][2][L][N] -> centred messages int64 [n][N]."""
+        LN = self.L * self.N
+        _check(lib().he_decrypt(self._h, int(n), _ptr(ct_dev, n * 2 * LN, "ct"), _ptr(sk_ntt_dev, LN, "sk_ntt"),
+                                _ptr(msgs_dev, n * self.N, "msgs"), _ptr(work_dev, n * LN, "work"),
+                                _stream(stream)), "he_decrypt")
 
 
 class Batch:
