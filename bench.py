@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched fire-module CNN section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-client", action="store_true", help="skip the client-side encrypt/decrypt section")
     ap.add_argument("--no-bottleneck", action="store_true",
                     help="skip the batch-16 bottleneck residual CNN section (about 230 GiB resident)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -213,6 +214,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_serving:
         result["serving"] = run_serving(torch, heconv, args)
+    if not args.no_client:
+        result["client"] = run_client(torch, heconv)
 
     if args.copy_probe:
         src = torch.ones(32 << 20, dtype=torch.int64, device="cuda")
@@ -410,6 +413,40 @@ def run_bottleneck(torch, heconv):
     del ins, outs, wntts, jobs
     ctx.close()
     return res
+
+
+def run_client(torch, heconv):
+    """Client-side encryption and decryption on the GPU (load generation):
+    256 ciphertexts at N=8192, L=3 (eight times the 64->64 layer's input),
+    messages uniform in [0, t), ternary key, small errors; every decrypted
+    coefficient must equal its message."""
+    cfg = synth.CONFIGS[2]
+    N, L, bits = cfg["N"], cfg["L"], cfg["bits"]
+    t = 2 ** synth.T_BITS
+    ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), t)
+    n = 256
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    q = torch.tensor(ctx.q, dtype=torch.int64, device="cuda").view(1, L, 1)
+    sk = torch.randint(-1, 2, (N,), dtype=torch.int64, generator=gen, device="cuda")
+    msgs = torch.randint(0, t, (n, N), dtype=torch.int64, generator=gen, device="cuda")
+    a = torch.randint(0, 2 ** 62, (n, L, N), dtype=torch.int64, generator=gen, device="cuda") % q
+    err = torch.randint(-21, 22, (n, N), dtype=torch.int64, generator=gen, device="cuda")
+    skn = torch.empty(L * N, dtype=torch.int64, device="cuda")
+    ct = torch.empty(n * 2 * L * N, dtype=torch.int64, device="cuda")
+    work = torch.empty(n * L * N, dtype=torch.int64, device="cuda")
+    out = torch.empty(n * N, dtype=torch.int64, device="cuda")
+    ctx.key_encode(sk, skn)
+    ctx.encrypt(n, msgs, a, err, skn, ct, work)
+    ctx.decrypt(n, ct, skn, out, work)
+    want = torch.where(msgs >= t // 2, msgs - t, msgs).reshape(-1)
+    exact = bool(torch.equal(out, want))
+    t_enc = _timed(torch, lambda: ctx.encrypt(n, msgs, a, err, skn, ct, work), 20)
+    t_dec = _timed(torch, lambda: ctx.decrypt(n, ct, skn, out, work), 20)
+    ctx.close()
+    return {"workload": f"{n} ciphertexts, N={N}, L={L}", "encrypt_ms": t_enc, "decrypt_ms": t_dec,
+            "encrypt_cts_per_s": n / t_enc * 1e3, "decrypt_cts_per_s": n / t_dec * 1e3,
+            "roundtrip_exact": exact}
 
 
 def run_serving(torch, heconv, args):

@@ -116,7 +116,14 @@ void he_ctx_destroy(he_ctx* ctx);
  * MAC; the caller's stream then waits for the last transform.  The internal
  * stream is shared by all calls on the context: concurrent calls on several
  * streams should use 1.
- * Defaults: {3, 3, 512, 0, 0, 0, 1}: 8 words per thread was measured faster
+ * ntt_split_below: he_ntt_fwd (and so he_conv_layer's forward step) runs
+ * the forward NTT of fewer than this many limb polynomials (N = 2^12 ..
+ * 2^14) as two grids of 128-thread workgroups, eight per 2^13 points,
+ * instead of one workgroup per polynomial, so that every compute unit
+ * takes part; 0 = never.  Measured at N = 2^13: 10.2 against 14.2 us for 48
+ * limb polynomials, 11.2 against 14.9 for 96, 14.5 against 15.3 for 144,
+ * but 16.9 against 15.6 for 192.
+ * Defaults: {3, 3, 512, 0, 0, 0, 1, 160}: 8 words per thread was measured faster
  * than 16 at every count at N = 8192 (768 limb polys: 47.7 against 51.4 us
  * inverse); N = 16384 always uses 16.  The channel pipeline (layer_split)
  * was measured slower than the plain order on 64->64, 128->128 and
@@ -128,6 +135,7 @@ typedef struct {
   uint32_t mac_mt, mac_rt;
   uint32_t layer_fused;
   uint32_t layer_split;
+  uint32_t ntt_split_below;
 } he_tuning;
 
 he_status he_ctx_get_tuning(const he_ctx* ctx, he_tuning* out);

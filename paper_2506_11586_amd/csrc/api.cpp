@@ -371,6 +371,8 @@ he_status he_ntt_fwd(const he_ctx* c, uint64_t* d_polys, uint64_t n, void* strea
   if (check_ctx(c)) return HE_EINVAL;
   if (n == 0) return HE_OK;
   if (!d_polys) return HE_EINVAL;
+  if (n * c->L < c->tune.ntt_split_below && heconv::ntt_fwd_split_supported(c->logN))
+    return dev_err(heconv::ntt_fwd_split_launch(c->logN, d_polys, n, c->L, c->d_fwd, c->d_lc, (hipStream_t)stream));
   return dev_err(heconv::ntt_launch(false, c->logN, ntt_loge(c, n), d_polys, n, c->L, c->d_fwd, c->d_lc, (hipStream_t)stream));
 }
 

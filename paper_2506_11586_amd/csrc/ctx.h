@@ -22,7 +22,7 @@ struct he_ctx {
   heconv::LimbConst* d_lc = nullptr;
   heconv::DecodeConst* d_dc = nullptr;  // client-side decoding constants (t a power of two)
   bool decode_ok = false;
-  he_tuning tune{3, 3, 512, 0, 0, 0, 1};
+  he_tuning tune{3, 3, 512, 0, 0, 0, 1, 160};
   // internal stream and events of the output-channel pipeline of he_conv_layer
   hipStream_t aux = nullptr;
   hipEvent_t ev_mac[4] = {nullptr, nullptr, nullptr, nullptr};

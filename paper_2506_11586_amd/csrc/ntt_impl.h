@@ -34,10 +34,13 @@ __device__ __forceinline__ int elem_index(int tid, int k) {
   return low | (k << LO) | (high << (LO + LOGE));
 }
 
-// Forward stages u in [U0, LOGE) of the pass at bit offset LO.
+// Forward stages u in [U0, LOGE) of the pass at bit offset LO.  jb: index
+// of the workgroup's first element when it transforms a block of a longer
+// polynomial (the stages on bits below the block size only; jb a multiple of
+// the block size), else 0.
 template <int LOGN, int LOGE, int LO, int U0>
 __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LOGE], int tid, const Tw* __restrict__ tw,
-                                         const LimbConst& c) {
+                                         const LimbConst& c, uint32_t jb = 0) {
   const int high = tid >> LO;
   const uint64_t q2 = c.two_q;
 #pragma unroll
@@ -46,7 +49,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LOGE], int tid, cons
     const int half = 1 << (LOGE - 1 - u);
 #pragma unroll
     for (int g = 0; g < (1 << u); g++) {
-      const Tw t = tw[(1 << s) + (high << u) + g];
+      const Tw t = tw[(1 << s) + (jb >> (LO + LOGE - u)) + (high << u) + g];
 #pragma unroll
       for (int e = 0; e < half; e++) {
         const int k0 = g * 2 * half + e, k1 = k0 + half;

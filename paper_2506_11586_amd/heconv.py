@@ -28,7 +28,8 @@ class Tuning(ctypes.Structure):
     """he_tuning: launch-shape choices (speed only, never results)."""
 
     _fields_ = [(n, ctypes.c_uint32) for n in ("ntt_loge_small", "ntt_loge_large", "ntt_small_below",
-                                               "mac_mt", "mac_rt", "layer_fused", "layer_split")]
+                                               "mac_mt", "mac_rt", "layer_fused", "layer_split",
+                                               "ntt_split_below")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -273,3 +273,21 @@ def test_layer_split_ragged_channels(M, split):
                                  cv.M, prm)
     ctx.set_tuning(layer_split=1)
     assert np.array_equal(to_host(out).reshape(want.shape), want)
+
+
+@pytest.mark.parametrize("N,L,bits", [(4096, 2, 50), (8192, 3, 60), (16384, 2, 60)])
+@pytest.mark.parametrize("n_rns", [1, 3, 8, 40])
+def test_ntt_forward_two_grid_split(N, L, bits, n_rns):
+    """The two-grid forward NTT (forced for every count) against the
+    oracle; counts with and without the XCD grouping (limb polys a multiple
+    of 8 or not), lazy-range edge words included."""
+    ctx, prm = ctx_and_prm(N, L, bits)
+    before = ctx.get_tuning().as_dict()
+    ctx.set_tuning(ntt_split_below=1 << 30)
+    x = rand_polys(7 * N + n_rns, n_rns, prm)
+    x[0] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)
+    d = to_dev(x)
+    ctx.ntt_fwd(d, n_rns)
+    got = to_host(d).reshape(x.shape)
+    ctx.set_tuning(**before)
+    assert np.array_equal(got, oracle.ntt(x, prm))
