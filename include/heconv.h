@@ -187,7 +187,10 @@ he_status he_ntt_inv(const he_ctx* ctx, uint64_t* d_polys, uint64_t n, void* str
  *   out[b][m][s][c][l][k] = sum_{cb<CB} in[b][cb][s][c][l][k] * w[m][cb][l][k] mod q_l
  * d_in_ntt: [B][CB][S][2][L][N], d_wntt: [M][CB][L][N],
  * d_out_ntt: [B][M][S][2][L][N] (written completely; must not alias the
- * inputs). */
+ * inputs).  HE_ESHAPE if one image's input ciphertexts (CB*S*2*L*N words)
+ * or one output channel's weights (CB*L*N words) reach 2^31 bytes: the MAC
+ * addresses them with 32-bit offsets (he_conv_layer and he_batch_create
+ * check the same). */
 he_status he_conv_ntt_mac(const he_ctx* ctx, const he_conv_desc* desc, uint32_t B, const uint64_t* d_in_ntt,
                           const uint64_t* d_wntt, uint64_t* d_out_ntt, void* stream);
 

@@ -390,7 +390,7 @@ he_status he_conv_ntt_mac(const he_ctx* c, const he_conv_desc* d, uint32_t B, co
   if (!geo_of(*d, c->N, g)) return HE_ESHAPE;
   if (B == 0) return HE_OK;
   if (!d_in_ntt || !d_wntt || !d_out_ntt) return HE_EINVAL;
-  if ((uint64_t)B * g.S * 2 > 0xffffffffull) return HE_ESHAPE;
+  if ((uint64_t)B * g.S * 2 > 0xffffffffull || !heconv::mac_offsets_fit(g, c->L, c->N)) return HE_ESHAPE;
   return dev_err(heconv::mac_launch(d_in_ntt, d_wntt, d_out_ntt, B, g.CB, g.S, d->M, c->L, c->N, c->d_lc,
                                     c->tune.mac_mt, c->tune.mac_rt, (hipStream_t)stream));
 }
@@ -413,6 +413,7 @@ he_status he_conv_layer(const he_ctx* c, const he_conv_desc* d, uint32_t B, uint
   if (!geo_of(*d, c->N, g)) return HE_ESHAPE;
   if (B == 0) return HE_OK;
   if (!d_in || !d_wntt || !d_out) return HE_EINVAL;
+  if ((uint64_t)B * g.S * 2 > 0xffffffffull || !heconv::mac_offsets_fit(g, c->L, c->N)) return HE_ESHAPE;
   hipStream_t st = (hipStream_t)stream;
   he_status s = he_ntt_fwd(c, d_in, (uint64_t)B * g.CB * g.S * 2, stream);
   if (s) return s;

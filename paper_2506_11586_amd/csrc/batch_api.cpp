@@ -85,7 +85,7 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
   bool small = false;
   for (uint32_t j = 0; j < n_jobs; j++) {
     const he_job& jb = jobs[j];
-    if (!heconv::geo_of(jb.desc, c->N, geo[j])) {
+    if (!heconv::geo_of(jb.desc, c->N, geo[j]) || !heconv::mac_offsets_fit(geo[j], c->L, c->N)) {
       free_batch(b);
       return HE_ESHAPE;
     }

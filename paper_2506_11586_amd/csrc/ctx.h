@@ -59,4 +59,11 @@ inline bool geo_of(const he_conv_desc& d, uint32_t N, Geo& g) {
   return true;
 }
 
+// The MAC addresses one image's input ciphertexts and one output channel's
+// weights with 32-bit byte offsets below 2^31.
+inline bool mac_offsets_fit(const Geo& g, uint32_t L, uint32_t N) {
+  const uint64_t LN8 = (uint64_t)L * N * 8;
+  return (uint64_t)g.CB * g.S * 2 * LN8 < (1ull << 31) && (uint64_t)g.CB * LN8 < (1ull << 31);
+}
+
 }  // namespace heconv

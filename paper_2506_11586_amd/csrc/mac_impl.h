@@ -27,6 +27,33 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
   return (bid % 8) * per + bid / 8;
 }
 
+// Buffer resources (gfx9 layout: base, no stride, size in bytes, raw dword
+// access) let a load take a uniform byte offset in a scalar register and
+// the lane's offset in one 32-bit register, with no per-lane 64-bit address
+// arithmetic.  Every offset used here stays below 2^31 bytes; the launchers
+// check that one image's input and one output channel's weights do.
+constexpr int MAC_BUF_FLAGS = 0x00020000;
+constexpr uint64_t MAC_BUF_MAX_BYTES = 0x7fffffffull;
+
+// A value the caller knows to be the same in every lane, moved to scalar
+// registers (integer division of uniform values is expanded with vector
+// instructions, after which the compiler no longer sees the result as
+// uniform and would wrap every buffer load in a loop over lane values).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mac_rsrc(const void* base, uint64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, MAC_BUF_FLAGS);
+}
+
+__device__ __forceinline__ uint64_t mac_load(__amdgpu_buffer_rsrc_t r, uint32_t lane_bytes, uint32_t uniform_bytes) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)lane_bytes, (int)uniform_bytes, 0);
+  return ((uint64_t)v[1] << 32) | v[0];
+}
+
 #ifndef HECONV_MAC_DEPTH
 #define HECONV_MAC_DEPTH 4
 #endif
@@ -62,11 +89,17 @@ __device__ __forceinline__ void mac_tile(cgword* __restrict__ in, cgword* __rest
                                          const LimbConst& c, int tid) {
   const uint32_t chunks_per_limb = N / THREADS;
   const uint32_t l = kc / chunks_per_limb;
-  const uint32_t k = (kc % chunks_per_limb) * THREADS + tid;
+  // element (l, k) with k = kbase + tid: every address is a uniform base
+  // (scalar registers) plus the lane's tid, so the loads take the
+  // scalar-base form and need no per-lane address arithmetic
+  const uint64_t kofs = (uint64_t)l * N + (kc % chunks_per_limb) * THREADS;
   const uint64_t LN = (uint64_t)L * N;
 
-  // row r = (b*S + s)*2 + comp; input address of (r, cb) and output of (r, m)
-  cgword* ip[RT];
+  // row r = (b*S + s)*2 + comp; input of (r, cb) at ib[i] + cb*in_cb_stride,
+  // weights of (m, cb) at wb[j] + cb*LN, output of (r, m) at out_off[i] + m*out_m_stride
+  const uint64_t in_cb_stride = (uint64_t)S * 2 * LN;  // cb -> cb+1 in the input
+  const uint64_t out_m_stride = (uint64_t)S * 2 * LN;  // m -> m+1 in the output
+  __amdgpu_buffer_rsrc_t ib[RT], wb[MT];
   uint64_t out_off[RT];
   bool rv[RT];
 #pragma unroll
@@ -76,19 +109,19 @@ __device__ __forceinline__ void mac_tile(cgword* __restrict__ in, cgword* __rest
     const uint32_t rr = rv[i] ? r : 0;
     const uint32_t comp = rr & 1, bs = rr >> 1;
     const uint32_t b = bs / S, s = bs % S;
-    ip[i] = in + ((((uint64_t)b * CB) * S + s) * 2 + comp) * LN + (uint64_t)l * N + k;
-    out_off[i] = ((((uint64_t)b * M) * S + s) * 2 + comp) * LN + (uint64_t)l * N + k;
+    ib[i] = mac_rsrc((const uint64_t*)in + uniform64(((((uint64_t)b * CB) * S + s) * 2 + comp) * LN + kofs),
+                     (uint64_t)CB * in_cb_stride * 8);
+    out_off[i] = ((((uint64_t)b * M) * S + s) * 2 + comp) * LN + kofs;
   }
-  const uint64_t in_cb_stride = (uint64_t)S * 2 * LN;  // cb -> cb+1 in the input
-  const uint64_t out_m_stride = (uint64_t)S * 2 * LN;  // m -> m+1 in the output
   bool mv[MT];
-  cgword* wp[MT];
 #pragma unroll
   for (int j = 0; j < MT; j++) {
     const uint32_t m = mt * MT + j;
     mv[j] = m < M;
-    wp[j] = w + ((uint64_t)(mv[j] ? m : 0) * CB) * LN + (uint64_t)l * N + k;
+    wb[j] = mac_rsrc((const uint64_t*)w + uniform64(((uint64_t)(mv[j] ? m : 0) * CB) * LN + kofs),
+                     (uint64_t)CB * LN * 8);
   }
+  const uint32_t lane = (uint32_t)tid * 8;
 
   uint64_t res[MT][RT];
 #pragma unroll
@@ -113,15 +146,9 @@ __device__ __forceinline__ void mac_tile(cgword* __restrict__ in, cgword* __rest
 #pragma unroll
       for (int d = 0; d < MAC_DEPTH; d++) {
 #pragma unroll
-        for (int i = 0; i < RT; i++) xr[d][i] = ip[i][(uint64_t)(cb + d) * in_cb_stride];
+        for (int i = 0; i < RT; i++) xr[d][i] = mac_load(ib[i], lane, (uint32_t)((cb + d) * in_cb_stride * 8));
 #pragma unroll
-        for (int j = 0; j < MT; j++) {
-#ifdef HECONV_MAC_NT
-          wr[d][j] = __builtin_nontemporal_load(&wp[j][(uint64_t)(cb + d) * LN]);
-#else
-          wr[d][j] = wp[j][(uint64_t)(cb + d) * LN];
-#endif
-        }
+        for (int j = 0; j < MT; j++) wr[d][j] = mac_load(wb[j], lane, (uint32_t)((cb + d) * LN * 8));
       }
 #pragma unroll
       for (int d = 0; d < MAC_DEPTH; d++) mac_step<MT, RT>(xr[d], wr[d], a00, a01, a10, a11);
@@ -129,9 +156,9 @@ __device__ __forceinline__ void mac_tile(cgword* __restrict__ in, cgword* __rest
     for (; cb < cb1; cb++) {
       uint64_t xr[RT], wr[MT];
 #pragma unroll
-      for (int i = 0; i < RT; i++) xr[i] = ip[i][(uint64_t)cb * in_cb_stride];
+      for (int i = 0; i < RT; i++) xr[i] = mac_load(ib[i], lane, (uint32_t)(cb * in_cb_stride * 8));
 #pragma unroll
-      for (int j = 0; j < MT; j++) wr[j] = wp[j][(uint64_t)cb * LN];
+      for (int j = 0; j < MT; j++) wr[j] = mac_load(wb[j], lane, (uint32_t)(cb * LN * 8));
       mac_step<MT, RT>(xr, wr, a00, a01, a10, a11);
     }
 #pragma unroll
@@ -144,7 +171,7 @@ __device__ __forceinline__ void mac_tile(cgword* __restrict__ in, cgword* __rest
   for (int j = 0; j < MT; j++)
 #pragma unroll
     for (int i = 0; i < RT; i++)
-      if (mv[j] && rv[i]) out[out_off[i] + (uint64_t)(mt * MT + j) * out_m_stride] = res[j][i];
+      if (mv[j] && rv[i]) out[out_off[i] + (uint64_t)(mt * MT + j) * out_m_stride + (uint32_t)tid] = res[j][i];
 }
 
 }  // namespace heconv
