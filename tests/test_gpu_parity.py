@@ -106,6 +106,9 @@ MAC_CASES = [  # (shape, params, packing, B)
     ((64, 56, 56, 64, 3, 3, 1, 1), (8192, 3, 60), None, 1),
     ((5, 12, 12, 5, 3, 3, 1, 1), (4096, 2, 50), (1, 6, 9), 3),  # ragged M, odd row count
     ((70, 6, 6, 3, 1, 1, 1, 0), (1024, 2, 50), (1, 6, 6), 2),  # CB = 70 > 32: 128-bit fold
+    ((20, 10, 10, 6, 1, 1, 1, 0), (1024, 8, 40), (1, 10, 10), 2),  # eight limbs, CB = 16 + 4, all q-1
+    ((17, 8, 8, 5, 1, 1, 1, 0), (16384, 2, 60), (1, 8, 8), 1),  # largest ring, CB = 16 + 1
+    ((33, 9, 9, 7, 3, 3, 1, 1), (8192, 3, 60), (1, 11, 11), 3),  # CB = 33: two chunks and a tail
 ]
 
 
@@ -291,3 +294,23 @@ def test_ntt_forward_two_grid_split(N, L, bits, n_rns):
     got = to_host(d).reshape(x.shape)
     ctx.set_tuning(**before)
     assert np.array_equal(got, oracle.ntt(x, prm))
+
+
+def test_layer_largest_ring():
+    """he_conv_layer at N = 2^14 (16 words per thread; the two-grid forward
+    transform for a small count) against the oracle's flow."""
+    ctx, prm = ctx_and_prm(16384, 2, 60)
+    shape = (6, 30, 30, 5, 3, 3, 1, 1)
+    cv = wl.conv_of(shape)
+    d = ctx.plan(shape)
+    g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+    x = rand_polys(71, g.CB * g.S * 2, prm)
+    K = Stream(72, synth.WEIGHT).ints(cv.M * cv.C * 9, -2 ** 8, 2 ** 8).reshape(cv.M, cv.C, 3, 3)
+    s = ctx.sizes(d)
+    wntt = empty_words(s.w_words)
+    ctx.encode_weights(d, to_dev(K), wntt)
+    out = empty_words(s.out_cts * 2 * prm.L * prm.N)
+    ctx.conv_layer(d, 1, to_dev(x), wntt, out)
+    want = oracle.conv_layer_ntt(x.reshape(1, g.CB, g.S, 2, prm.L, prm.N), oracle.encode_weights(K, cv, g, prm), 1, g,
+                                 cv.M, prm)
+    assert np.array_equal(to_host(out).reshape(want.shape), want)
