@@ -123,7 +123,13 @@ void he_ctx_destroy(he_ctx* ctx);
  * takes part; 0 = never.  Measured at N = 2^13: 10.2 against 14.2 us for 48
  * limb polynomials, 11.2 against 14.9 for 96, 14.5 against 15.3 for 144,
  * but 16.9 against 15.6 for 192.
- * Defaults: {3, 3, 512, 0, 0, 0, 1, 160}: 8 words per thread was measured faster
+ * ntt_fp64: 1 = when every q_l < 2^50, every transform of the library
+ * (except the batch executor's and the fused kernel's) runs in double
+ * precision: residues are exact doubles and a modular product is two
+ * products, two fused multiply-adds, a rounding and a conditional add, all
+ * at the full fp64 rate, where the integer path's 32-bit multiplies run at
+ * half rate.  0 = always the integer kernels.
+ * Defaults: {3, 3, 512, 0, 0, 0, 1, 160, 1}: 8 words per thread was measured faster
  * than 16 at every count at N = 8192 (768 limb polys: 47.7 against 51.4 us
  * inverse); N = 16384 always uses 16.  The channel pipeline (layer_split)
  * was measured slower than the plain order on 64->64, 128->128 and
@@ -136,6 +142,7 @@ typedef struct {
   uint32_t layer_fused;
   uint32_t layer_split;
   uint32_t ntt_split_below;
+  uint32_t ntt_fp64;
 } he_tuning;
 
 he_status he_ctx_get_tuning(const he_ctx* ctx, he_tuning* out);

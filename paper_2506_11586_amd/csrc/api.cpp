@@ -133,6 +133,19 @@ uint32_t ntt_loge(const he_ctx* c, uint64_t n_rns_polys) {
 
 he_status dev_err(hipError_t e) { return e == hipSuccess ? HE_OK : HE_EDEVICE; }
 
+// Every transform of the library goes through here: double precision when
+// all primes allow it (and the tuning asks for it), else the integer
+// kernels -- for a small forward count, in two grids.
+hipError_t ntt_run(const he_ctx* c, bool inverse, uint64_t* polys, uint64_t n, hipStream_t st) {
+  if (c->fp64_ok && c->tune.ntt_fp64)
+    return heconv::ntt_f64_launch(inverse, c->logN, ntt_loge(c, n), polys, n, c->L, inverse ? c->d_inv64 : c->d_fwd64,
+                                  c->d_fc, st);
+  if (!inverse && n * c->L < c->tune.ntt_split_below && heconv::ntt_fwd_split_supported(c->logN))
+    return heconv::ntt_fwd_split_launch(c->logN, polys, n, c->L, c->d_fwd, c->d_lc, st);
+  return heconv::ntt_launch(inverse, c->logN, ntt_loge(c, n), polys, n, c->L, inverse ? c->d_inv : c->d_fwd, c->d_lc,
+                            st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -229,10 +242,24 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
     const uint64_t fh = (uint64_t)(r64 / q), r2 = (uint64_t)(r64 % q);
     dc[l] = heconv::DecodeConst{(uint64_t)(ty / q), fh, (uint64_t)(((u128)r2 << 64) / q)};
   }
+  // double-precision transforms when every prime is below 2^50
+  c->fp64_ok = std::all_of(c->q.begin(), c->q.end(), [](uint64_t q) { return q < (1ull << 50); });
+  std::vector<double> fwd64, inv64;
+  std::vector<unsigned char> fc;
+  if (c->fp64_ok) {
+    fwd64.resize((size_t)L * N), inv64.resize((size_t)L * N), fc.resize(heconv::f64_const_size() * L);
+    for (size_t i = 0; i < (size_t)L * N; i++) fwd64[i] = (double)fwd[i].w, inv64[i] = (double)inv[i].w;
+    for (uint32_t l = 0; l < L; l++)
+      heconv::f64_const_fill(fc.data() + heconv::f64_const_size() * l, (double)c->q[l], 1.0 / (double)c->q[l],
+                             (double)c->lc[l].ninv, (double)c->lc[l].ninv_w);
+  }
   const size_t tb = sizeof(Tw) * (size_t)L * N;
   if (hipMalloc(&c->d_fwd, tb) != hipSuccess || hipMalloc(&c->d_inv, tb) != hipSuccess ||
       hipMalloc(&c->d_lc, sizeof(LimbConst) * L) != hipSuccess ||
-      hipMalloc(&c->d_dc, sizeof(heconv::DecodeConst) * L) != hipSuccess) {
+      hipMalloc(&c->d_dc, sizeof(heconv::DecodeConst) * L) != hipSuccess ||
+      (c->fp64_ok && (hipMalloc(&c->d_fwd64, sizeof(double) * L * N) != hipSuccess ||
+                      hipMalloc(&c->d_inv64, sizeof(double) * L * N) != hipSuccess ||
+                      hipMalloc(&c->d_fc, fc.size()) != hipSuccess))) {
     he_ctx_destroy(c);
     return HE_ENOMEM;
   }
@@ -247,7 +274,11 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
   if (hipMemcpy(c->d_fwd, fwd.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_inv, inv.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_lc, c->lc.data(), sizeof(LimbConst) * L, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->d_dc, dc.data(), sizeof(heconv::DecodeConst) * L, hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(c->d_dc, dc.data(), sizeof(heconv::DecodeConst) * L, hipMemcpyHostToDevice) != hipSuccess ||
+      (c->fp64_ok &&
+       (hipMemcpy(c->d_fwd64, fwd64.data(), sizeof(double) * L * N, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_inv64, inv64.data(), sizeof(double) * L * N, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_fc, fc.data(), fc.size(), hipMemcpyHostToDevice) != hipSuccess))) {
     he_ctx_destroy(c);
     return HE_EDEVICE;
   }
@@ -261,6 +292,9 @@ void he_ctx_destroy(he_ctx* c) {
   if (c->d_inv) (void)hipFree(c->d_inv);
   if (c->d_lc) (void)hipFree(c->d_lc);
   if (c->d_dc) (void)hipFree(c->d_dc);
+  if (c->d_fwd64) (void)hipFree(c->d_fwd64);
+  if (c->d_inv64) (void)hipFree(c->d_inv64);
+  if (c->d_fc) (void)hipFree(c->d_fc);
   for (int i = 0; i < 4; i++)
     if (c->ev_mac[i]) (void)hipEventDestroy(c->ev_mac[i]);
   if (c->ev_done) (void)hipEventDestroy(c->ev_done);
@@ -287,7 +321,7 @@ he_status he_ctx_set_tuning(he_ctx* c, const he_tuning* t) {
   static const uint32_t tiles[][2] = {{0, 0}, {4, 4}, {4, 2}, {2, 4}, {8, 2}, {2, 8}, {8, 1}, {1, 8}, {2, 2}};
   bool ok = false;
   for (auto& p : tiles) ok |= (p[0] == t->mac_mt && p[1] == t->mac_rt);
-  if (!ok || t->layer_fused > 1) return HE_EINVAL;
+  if (!ok || t->layer_fused > 1 || t->ntt_fp64 > 1) return HE_EINVAL;
   if (t->layer_split != 1 && t->layer_split != 2 && t->layer_split != 4) return HE_EINVAL;
   c->tune = *t;
   return HE_OK;
@@ -363,24 +397,21 @@ he_status he_encode_weights(const he_ctx* c, const he_conv_desc* d, const int64_
   hipStream_t st = (hipStream_t)stream;
   he_status s = dev_err(heconv::pack_weights_launch(pg, d_w, d_wntt, c->d_lc, st));
   if (s) return s;
-  return dev_err(heconv::ntt_launch(false, c->logN, ntt_loge(c, (uint64_t)d->M * g.CB), d_wntt,
-                                    (uint64_t)d->M * g.CB, c->L, c->d_fwd, c->d_lc, st));
+  return dev_err(ntt_run(c, false, d_wntt, (uint64_t)d->M * g.CB, st));
 }
 
 he_status he_ntt_fwd(const he_ctx* c, uint64_t* d_polys, uint64_t n, void* stream) {
   if (check_ctx(c)) return HE_EINVAL;
   if (n == 0) return HE_OK;
   if (!d_polys) return HE_EINVAL;
-  if (n * c->L < c->tune.ntt_split_below && heconv::ntt_fwd_split_supported(c->logN))
-    return dev_err(heconv::ntt_fwd_split_launch(c->logN, d_polys, n, c->L, c->d_fwd, c->d_lc, (hipStream_t)stream));
-  return dev_err(heconv::ntt_launch(false, c->logN, ntt_loge(c, n), d_polys, n, c->L, c->d_fwd, c->d_lc, (hipStream_t)stream));
+  return dev_err(ntt_run(c, false, d_polys, n, (hipStream_t)stream));
 }
 
 he_status he_ntt_inv(const he_ctx* c, uint64_t* d_polys, uint64_t n, void* stream) {
   if (check_ctx(c)) return HE_EINVAL;
   if (n == 0) return HE_OK;
   if (!d_polys) return HE_EINVAL;
-  return dev_err(heconv::ntt_launch(true, c->logN, ntt_loge(c, n), d_polys, n, c->L, c->d_inv, c->d_lc, (hipStream_t)stream));
+  return dev_err(ntt_run(c, true, d_polys, n, (hipStream_t)stream));
 }
 
 he_status he_conv_ntt_mac(const he_ctx* c, const he_conv_desc* d, uint32_t B, const uint64_t* d_in_ntt,
@@ -440,8 +471,7 @@ he_status he_conv_layer(const he_ctx* c, const he_conv_desc* d, uint32_t B, uint
     if (s) return s;
     if (hipEventRecord(c->ev_mac[p], st) != hipSuccess || hipStreamWaitEvent(c->aux, c->ev_mac[p], 0) != hipSuccess)
       return HE_EDEVICE;
-    s = dev_err(heconv::ntt_launch(true, c->logN, ntt_loge(c, (uint64_t)Mp * g.S * 2), d_out + m0 * out_per_m,
-                                   (uint64_t)Mp * g.S * 2, c->L, c->d_inv, c->d_lc, c->aux));
+    s = dev_err(ntt_run(c, true, d_out + m0 * out_per_m, (uint64_t)Mp * g.S * 2, c->aux));
     if (s) return s;
     m0 = m_end;
   }
@@ -504,7 +534,7 @@ he_status he_key_encode(const he_ctx* c, const int64_t* d_sk, uint64_t* d_sk_ntt
   hipStream_t st = (hipStream_t)stream;
   he_status s = dev_err(heconv::key_lift_launch(d_sk, d_sk_ntt, c->N, c->L, c->d_lc, st));
   if (s) return s;
-  return dev_err(heconv::ntt_launch(false, c->logN, ntt_loge(c, 1), d_sk_ntt, 1, c->L, c->d_fwd, c->d_lc, st));
+  return dev_err(ntt_run(c, false, d_sk_ntt, 1, st));
 }
 
 namespace {
@@ -514,9 +544,9 @@ namespace {
 he_status key_product(const he_ctx* c, uint64_t n, const uint64_t* src, uint64_t src_stride, uint64_t* ct_out,
                       const uint64_t* sk_ntt, uint64_t* work, hipStream_t st) {
   he_status s = dev_err(heconv::copy_a_launch(src, src_stride, work, ct_out, n, c->N, c->L, st));
-  if (!s) s = dev_err(heconv::ntt_launch(false, c->logN, ntt_loge(c, n), work, n, c->L, c->d_fwd, c->d_lc, st));
+  if (!s) s = dev_err(ntt_run(c, false, work, n, st));
   if (!s) s = dev_err(heconv::pointwise_key_launch(work, sk_ntt, n, c->N, c->L, c->d_lc, st));
-  if (!s) s = dev_err(heconv::ntt_launch(true, c->logN, ntt_loge(c, n), work, n, c->L, c->d_inv, c->d_lc, st));
+  if (!s) s = dev_err(ntt_run(c, true, work, n, st));
   return s;
 }
 

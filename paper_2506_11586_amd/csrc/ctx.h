@@ -21,8 +21,13 @@ struct he_ctx {
   heconv::Tw* d_inv = nullptr;  // [L][N] psi^-brv(k) with Shoup quotient
   heconv::LimbConst* d_lc = nullptr;
   heconv::DecodeConst* d_dc = nullptr;  // client-side decoding constants (t a power of two)
+  // double-precision transforms (every q_l < 2^50)
+  bool fp64_ok = false;
+  double* d_fwd64 = nullptr;  // [L][N] forward twiddles as doubles
+  double* d_inv64 = nullptr;  // [L][N] inverse twiddles as doubles
+  void* d_fc = nullptr;       // per-limb F64Const
   bool decode_ok = false;
-  he_tuning tune{3, 3, 512, 0, 0, 0, 1, 160};
+  he_tuning tune{3, 3, 512, 0, 0, 0, 1, 160, 1};
   // internal stream and events of the output-channel pipeline of he_conv_layer
   hipStream_t aux = nullptr;
   hipEvent_t ev_mac[4] = {nullptr, nullptr, nullptr, nullptr};

@@ -19,6 +19,14 @@ bool ntt_fwd_split_supported(uint32_t logN);
 hipError_t ntt_fwd_split_launch(uint32_t logN, uint64_t* polys, uint64_t n_rns_polys, uint32_t L, const Tw* tw,
                                 const LimbConst* lc, hipStream_t st);
 
+// NTT / inverse NTT in double precision (every q_l < 2^50): tw are the
+// twiddles as doubles ([L][N], forward or inverse table), fc the per-limb
+// constants filled by f64_const_fill (f64_const_size bytes each).
+size_t f64_const_size();
+void f64_const_fill(void* out, double q, double qinv, double ninv, double ninv_w);
+hipError_t ntt_f64_launch(bool inverse, uint32_t logN, uint32_t loge, uint64_t* polys, uint64_t n_rns_polys,
+                          uint32_t L, const double* tw, const void* fc, hipStream_t st);
+
 // Geometry of a planned conv as the kernels need it.
 struct PackGeom {
   uint32_t M, C, kh, kw, Cw, Hw, Ww, CB, L, N, O;

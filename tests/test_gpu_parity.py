@@ -42,13 +42,15 @@ def test_context_matches_oracle(N, L, bits):
     assert ctx.q == prm.q and ctx.psi == prm.psi
 
 
+@pytest.mark.parametrize("fp64", [0, 1])
 @pytest.mark.parametrize("loge", [3, 4])
-@pytest.mark.parametrize("N,L,bits", PARAMS)
-def test_ntt_forward_and_inverse(N, L, bits, loge):
-    """Both launch shapes (8 or 16 words per thread) against the oracle."""
+@pytest.mark.parametrize("N,L,bits", PARAMS + [(2048, 4, 40), (16384, 3, 49)])
+def test_ntt_forward_and_inverse(N, L, bits, loge, fp64):
+    """Both launch shapes (8 or 16 words per thread), integer and (primes
+    below 2^50) double-precision kernels, against the oracle."""
     ctx, prm = ctx_and_prm(N, L, bits)
     before = ctx.get_tuning().as_dict()
-    ctx.set_tuning(ntt_loge_small=loge, ntt_loge_large=loge)
+    ctx.set_tuning(ntt_loge_small=loge, ntt_loge_large=loge, ntt_fp64=fp64, ntt_split_below=0)
     x = rand_polys(N + L, 3, prm)
     x[2] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)  # all q-1: lazy-range edge
     x[1, 0, :5] = [0, 1, 2, 3, 0]
