@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2])
+    ap.add_argument("--workload", default="conv64_56x56", choices=["conv4_16x16", "conv64_56x56"],
+                    help="single-layer workload of the main line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched fire-module CNN section")
@@ -93,7 +94,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    cfg = synth.CONFIGS[args.workload]
+    cfg = synth.WORKLOADS[args.workload]
     shape = cfg["layers"][0]
     N, L, bits, B = cfg["N"], cfg["L"], cfg["bits"], cfg["batch"]
     ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), 2 ** synth.T_BITS)
@@ -249,7 +250,7 @@ def run_batched(torch, heconv):
     solves one after another through he_conv_layer (plain) vs one batch (two
     chains of three grids, one hipGraph launch).  Outputs compared word for
     word."""
-    cfg = synth.CONFIGS[3]
+    cfg = synth.WORKLOADS["fire_cnn"]
     N, L, bits = cfg["N"], cfg["L"], cfg["bits"]
     ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), 2 ** synth.T_BITS)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64).copy()).cuda()
@@ -308,7 +309,7 @@ def run_bottleneck(torch, heconv):
     first run."""
     import oracle
 
-    cfg = synth.CONFIGS[4]
+    cfg = synth.WORKLOADS["bottleneck_cnn_b16"]
     N, L, bits, B = cfg["N"], cfg["L"], cfg["bits"], cfg["batch"]
     prm = oracle.Params(N, L, bits, 2 ** synth.T_BITS)
     ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), 2 ** synth.T_BITS)
@@ -420,7 +421,7 @@ def run_client(torch, heconv):
     256 ciphertexts at N=8192, L=3 (eight times the 64->64 layer's input),
     messages uniform in [0, t), ternary key, small errors; every decrypted
     coefficient must equal its message."""
-    cfg = synth.CONFIGS[2]
+    cfg = synth.WORKLOADS["conv64_56x56"]
     N, L, bits = cfg["N"], cfg["L"], cfg["bits"]
     t = 2 ** synth.T_BITS
     ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), t)
@@ -456,12 +457,13 @@ def run_serving(torch, heconv, args):
     (saturation), served vs one at a time on one stream."""
     from paper_2506_11586_amd import serving
 
-    shapes = [(1, synth.CONFIGS[1]["layers"][0]), (2, synth.CONFIGS[2]["layers"][0])] + \
-             [(3, s) for s in synth.CONFIGS[3]["layers"]]
+    shapes = [("conv4_16x16", synth.WORKLOADS["conv4_16x16"]["layers"][0]),
+              ("conv64_56x56", synth.WORKLOADS["conv64_56x56"]["layers"][0])] + \
+             [("fire_cnn", s) for s in synth.WORKLOADS["fire_cnn"]["layers"]]
     ctxs, layers = {}, []
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64).copy()).cuda()
     for i, (c, shape) in enumerate(shapes):
-        cfg = synth.CONFIGS[c]
+        cfg = synth.WORKLOADS[c]
         key = (cfg["N"], cfg["L"], cfg["bits"])
         if key not in ctxs:
             ctxs[key] = heconv.Context(cfg["N"], heconv.gen_primes(cfg["N"], cfg["bits"], cfg["L"]))
@@ -544,7 +546,7 @@ def cpu_baseline(args, cfg, ctx, d, sz, x_host, K_host, gpu_out):
     oracle.set_threads(cores)
     # the layer by definition (schoolbook negacyclic products, all cores) on
     # the small 4->4 layer at N=4096
-    c1 = synth.CONFIGS[1]
+    c1 = synth.WORKLOADS["conv4_16x16"]
     p1 = oracle.Params(c1["N"], c1["L"], c1["bits"], 2 ** synth.T_BITS)
     cv1 = oracle.Conv(*c1["layers"][0])
     g1 = oracle.plan_conv(cv1, p1.N, p1.L)

@@ -69,7 +69,7 @@ def _lib_handle():
     global _LIB
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+            raise ImportError(f"HIP library not built: {LIB_PATH} is missing (run paper_2506_11586_amd/build.py)")
         L = ctypes.CDLL(LIB_PATH)
         P, u32, u64, vp = ctypes.POINTER, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
         i32 = ctypes.c_int

@@ -9,7 +9,7 @@ passed to the oracle as inputs.
 Generator: SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom
 number generators", OOPSLA 2014).  It is counter based: output k of a stream
 with start state s0 is mix(s0 + (k + 1) * GAMMA), so whole arrays are made at
-once with wrapping uint64 arithmetic.  One stream per (config seed, purpose);
+once with wrapping uint64 arithmetic.  One stream per (workload seed, purpose);
 the start state is (seed << 8) | purpose.
 
 Purposes: 1 secret key, 2 uniform a-polynomials / ciphertext words,
@@ -159,13 +159,13 @@ def bottleneck_cnn_layers():
     return L
 
 
-CONFIGS = {
-    1: dict(name="single 3x3 conv 4->4 @16x16, N=4096, L=2x50-bit", layers=[conv(4, 16, 16, 4, 3, 1, 1)],
+WORKLOADS = {
+    "conv4_16x16": dict(name="single 3x3 conv 4->4 @16x16, N=4096, L=2x50-bit", layers=[conv(4, 16, 16, 4, 3, 1, 1)],
             N=4096, L=2, bits=50, batch=1, x_range=(-2 ** 7, 2 ** 7), w_range=(-2 ** 7, 2 ** 7), seed=1),
-    2: dict(name="3x3 conv 64->64 @56x56, N=8192, L=3x60-bit", layers=[conv(64, 56, 56, 64, 3, 1, 1)],
+    "conv64_56x56": dict(name="3x3 conv 64->64 @56x56, N=8192, L=3x60-bit", layers=[conv(64, 56, 56, 64, 3, 1, 1)],
             N=8192, L=3, bits=60, batch=1, x_range=(-2 ** 12, 2 ** 12), w_range=(-2 ** 8, 2 ** 8), seed=2),
-    3: dict(name="fire-module CNN, 26 convs @224, B=1", layers=fire_cnn_layers(),
+    "fire_cnn": dict(name="fire-module CNN, 26 convs @224, B=1", layers=fire_cnn_layers(),
             N=8192, L=3, bits=60, batch=1, x_range=(0, 2 ** 37), w_range=(-2 ** 12, 2 ** 12), seed=3),
-    4: dict(name="bottleneck residual CNN, 53 convs @224, B=16", layers=bottleneck_cnn_layers(),
+    "bottleneck_cnn_b16": dict(name="bottleneck residual CNN, 53 convs @224, B=16", layers=bottleneck_cnn_layers(),
             N=8192, L=3, bits=60, batch=16, x_range=(0, 2 ** 37), w_range=(-2 ** 12, 2 ** 12), seed=4),
 }

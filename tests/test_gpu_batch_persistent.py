@@ -138,7 +138,7 @@ def test_batch_cfg2_and_fire_layers():
     prm = oracle.Params(8192, 3, 60, 2 ** 37)
     ctx = heconv.Context(8192, heconv.gen_primes(8192, 60, 3))
     fire = synth.fire_cnn_layers()
-    shapes = [(synth.CONFIGS[2]["layers"][0], 1), (fire[1], 1), (fire[3], 1), (fire[-1], 1)]
+    shapes = [(synth.WORKLOADS["conv64_56x56"]["layers"][0], 1), (fire[1], 1), (fire[3], 1), (fire[-1], 1)]
     jobs, host = make_jobs(ctx, prm, shapes, 500)
     b = heconv.Batch(ctx, jobs)
     b.launch(graph=True)

@@ -78,11 +78,11 @@ def test_encrypt_reduces_messages_mod_t():
     assert np.array_equal(to_host(ct).reshape(want.shape), want)
 
 
-@pytest.mark.parametrize("cfg_id", [1, 2])
+@pytest.mark.parametrize("cfg_id", ["conv4_16x16", "conv64_56x56"])
 def test_decrypt_layer_output_matches_oracle(cfg_id):
     """Layer outputs carry grown noise; every coefficient decrypts as the
     oracle's exact decoding does, and the output slots give the conv."""
-    cfg = synth.CONFIGS[cfg_id]
+    cfg = synth.WORKLOADS[cfg_id]
     shape = cfg["layers"][0]
     ctx, prm = ctx_and_prm(cfg["N"], cfg["L"], cfg["bits"])
     cv = wl.conv_of(shape)

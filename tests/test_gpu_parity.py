@@ -141,7 +141,7 @@ def test_conv_ntt_mac(shape, params, packing, B):
 
 
 def run_layer(cfg_id):
-    cfg = synth.CONFIGS[cfg_id]
+    cfg = synth.WORKLOADS[cfg_id]
     shape = cfg["layers"][0]
     ctx, prm = ctx_and_prm(cfg["N"], cfg["L"], cfg["bits"])
     cv = wl.conv_of(shape)
@@ -164,7 +164,7 @@ def run_layer(cfg_id):
 def test_layer_cfg1_bit_exact_and_decrypts():
     """4->4 3x3 @16x16, N=4096: every output word equals the layer by
     definition (schoolbook products); decrypted slots = integer conv."""
-    cfg, cv, g, prm, x, K, sk, ct, got, in_after = run_layer(1)
+    cfg, cv, g, prm, x, K, sk, ct, got, in_after = run_layer("conv4_16x16")
     wc = oracle.pack_weights(K, cv, g, prm)
     assert np.array_equal(got, oracle.conv_layer_def(ct, wc, 1, g, cv.M, prm))
     assert np.array_equal(in_after, oracle.ntt(ct, prm))  # d_in holds the NTT form afterwards
@@ -175,7 +175,7 @@ def test_layer_cfg1_bit_exact_and_decrypts():
 def test_layer_cfg2_bit_exact_and_decrypts():
     """64->64 3x3 @56x56, N=8192, L=3: every word equals the oracle's NTT
     flow; sampled words equal the definition; decrypted slots = conv."""
-    cfg, cv, g, prm, x, K, sk, ct, got, _ = run_layer(2)
+    cfg, cv, g, prm, x, K, sk, ct, got, _ = run_layer("conv64_56x56")
     wc = oracle.pack_weights(K, cv, g, prm)
     want = oracle.conv_layer_ntt(ct, oracle.ntt(wc, prm), 1, g, cv.M, prm)
     assert np.array_equal(got, want)
@@ -237,7 +237,7 @@ def test_layer_modes_agree(fused, split):
     """he_conv_layer with the MAC and inverse NTT fused or not, and split over
     output-channel slices on internal streams or not: same words as the
     oracle's flow on the 64->64 layer."""
-    cfg = synth.CONFIGS[2]
+    cfg = synth.WORKLOADS["conv64_56x56"]
     shape = cfg["layers"][0]
     ctx, prm = ctx_and_prm(cfg["N"], cfg["L"], cfg["bits"])
     ctx.set_tuning(layer_fused=fused, layer_split=split)

@@ -77,11 +77,11 @@ def test_mask_extract_matches_oracle(N, L, bits, shape, B, with_noise):
         assert np.array_equal(got[b], want), b
 
 
-@pytest.mark.parametrize("cfg_id", [1, 2])
+@pytest.mark.parametrize("cfg_id", ["conv4_16x16", "conv64_56x56"])
 def test_server_flow_reconstructs_convolution(cfg_id):
     """Client encrypts its share; the GPU adds the server's share, runs the
     layer, masks and extracts; client decryption + mask = conv(x) mod t."""
-    cfg = synth.CONFIGS[cfg_id]
+    cfg = synth.WORKLOADS[cfg_id]
     shape = cfg["layers"][0]
     ctx, prm = ctx_and_prm(cfg["N"], cfg["L"], cfg["bits"])
     cv = wl.conv_of(shape)

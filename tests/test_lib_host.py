@@ -59,7 +59,7 @@ def test_bad_parameters_rejected():
 
 def all_shapes():
     shapes = set()
-    for cfg in synth.CONFIGS.values():
+    for cfg in synth.WORKLOADS.values():
         for s in cfg["layers"]:
             shapes.add((cfg["N"], cfg["L"], s))
     return sorted(shapes)

@@ -34,7 +34,7 @@ def test_encrypt_decrypt_roundtrip(which, prm4096, prm8192):
 def test_cfg1_layer_end_to_end(prm4096):
     """4->4 3x3 conv @16x16: encrypt, layer by the NTT flow and by the
     definition, decrypt; equals the exact integer convolution (|y| < t/2)."""
-    cfg = synth.CONFIGS[1]
+    cfg = synth.WORKLOADS["conv4_16x16"]
     p = prm4096
     cv = wl.conv_of(cfg["layers"][0])
     g = oracle.plan_conv(cv, p.N, p.L)
@@ -99,7 +99,7 @@ def test_rns_flow_matches_bigint_mirror():
 def test_cfg2_layer_decrypts_to_conv(prm8192):
     """64->64 3x3 @56x56, N=8192, L=3: oracle NTT flow, decrypted, equals the
     exact integer convolution; sampled words equal the definition."""
-    cfg = synth.CONFIGS[2]
+    cfg = synth.WORKLOADS["conv64_56x56"]
     p = prm8192
     shape = cfg["layers"][0]
     cv = wl.conv_of(shape)

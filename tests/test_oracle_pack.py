@@ -3,7 +3,7 @@ and the planner.
 
 The paper only says messages are placed in the coefficients so that a
 polynomial product computes the dot products (Sec. 2.3, Cheetah paragraph;
-Sec. 6.1).  The layout used is this build's reading; it is pinned here by
+Sec. 6.1).  The layout used is the library's reading; it is pinned here by
 brute force: packed ring products, extracted, equal the plaintext integer
 convolution for strides 1/2, pads 0/1/2/3, kernels 1/3/5/7 and several
 tilings, and the plaintext convolution is itself pinned to scipy."""

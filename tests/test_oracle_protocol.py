@@ -86,7 +86,7 @@ def test_shares_reconstruct_the_convolution(shape, prm4096):
 
 def test_extract_without_mask_equals_output_decryption(prm4096):
     p = prm4096
-    cfg = synth.CONFIGS[1]
+    cfg = synth.WORKLOADS["conv4_16x16"]
     cv = wl.conv_of(cfg["layers"][0])
     g = oracle.plan_conv(cv, p.N, p.L)
     x, K = wl.draw_layer(cfg, cfg["layers"][0])
