@@ -454,7 +454,9 @@ def run_serving(torch, heconv, args):
     """Open-loop Poisson arrivals over the 28 single-layer shapes of the three
     workloads above (the small layer keeps N=4096, L=2), weights resident,
     HBM budget 200 GB, four streams; then the same requests closed-loop
-    (saturation), served vs one at a time on one stream."""
+    (saturation), served vs one at a time on one stream; then closed-loop in
+    protocol mode (each request also folds in the server's input share and
+    returns masked, extracted outputs)."""
     from paper_2506_11586_amd import serving
 
     shapes = [("conv4_16x16", synth.WORKLOADS["conv4_16x16"]["layers"][0]),
@@ -493,6 +495,21 @@ def run_serving(torch, heconv, args):
     one = serving.Server(layers, n_streams=1, hbm_budget=200e9)
     one.run(requests()[:32], closed_loop=True)
     seq = one.run(requests(), closed_loop=True)
+    # protocol mode: a seeded share and mask per layer, reused by its requests
+    shares = [torch.from_numpy(Stream(7000 + i, synth.SHARE).below(lay.share_words, 2 ** synth.T_BITS)
+                               .astype(np.int64)).pin_memory() for i, lay in enumerate(layers)]
+    masks = [torch.from_numpy(Stream(7000 + i, synth.MASK).below(lay.mask_words, 2 ** synth.T_BITS)
+                              .astype(np.int64)).pin_memory() for i, lay in enumerate(layers)]
+
+    def proto_requests():
+        rs = requests()
+        for r in rs:
+            r.host_share, r.host_mask = shares[r.layer], masks[r.layer]
+        return rs
+
+    proto = serving.Server(layers, n_streams=4, hbm_budget=200e9, protocol=True)
+    proto.run(proto_requests()[:32], closed_loop=True)
+    pcl = proto.run(proto_requests(), closed_loop=True)
     macs = {i: lay.desc.M * lay.sizes.CB * lay.sizes.S for i, lay in enumerate(layers)}
     tot_macs = sum(macs[int(m)] for m in mix)
     out = {"workload": f"Poisson {args.serve_rate:g} req/s, {n} single-layer requests over {len(layers)} shapes",
@@ -502,6 +519,9 @@ def run_serving(torch, heconv, args):
                                   "p50_ms": cl.p50_ms, "p99_ms": cl.p99_ms, "max_inflight": cl.max_inflight},
            "closed_loop_plain_one_stream": {"layers_per_s": seq.layers_per_s, "ctpt_macs_per_s": tot_macs / seq.wall_s},
            "served_vs_plain": cl.layers_per_s / seq.layers_per_s,
+           "closed_loop_protocol": {"layers_per_s": pcl.layers_per_s, "ctpt_macs_per_s": tot_macs / pcl.wall_s,
+                                    "p50_ms": pcl.p50_ms, "p99_ms": pcl.p99_ms,
+                                    "steps": "share folded in, layer, masked extraction (Sec. 7)"},
            "hbm_budget_GB": 200, "resident_weights_GB": server.resident / 1e9,
            "latency": "arrival -> device completion (H2D copy of the input included; results stay in HBM)"}
     for c in ctxs.values():

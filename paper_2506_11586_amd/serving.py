@@ -4,7 +4,12 @@ a pool of HIP streams with weights resident in HBM.
 Each request is one layer solve (one image) of a resident layer: its input
 ciphertexts arrive in host memory, are copied into a device slot, and the
 layer's NTT -> MAC -> iNTT runs on the device; results stay resident in the
-request's output slot.  The dispatcher admits requests as they arrive, as
+request's output slot.  In protocol mode (the server's whole step for a
+linear layer in the online protocol, Sec. 7) a request also brings the
+server's input share and output mask: the share is folded into the input
+ciphertexts before the layer, and the output is masked and reduced to the
+coefficients that hold results (he_add_share, he_conv_layer,
+he_mask_extract).  The dispatcher admits requests as they arrive, as
 long as the HBM budget allows their slots, and puts them on any free
 stream, so requests that arrive while others are on the GPU run alongside
 them.  Latency is arrival -> device completion, measured on the GPU timeline with
@@ -38,6 +43,9 @@ class Layer:
     wntt: object  # device tensor
     in_words: int
     out_words: int
+    share_words: int = 0  # C*H*W: the server's input share (protocol mode)
+    mask_words: int = 0   # M*Ho*Wo: the server's output share
+    y_words: int = 0      # M*L*Ho*Wo: the extracted, masked outputs
 
 
 @dataclass(eq=False)
@@ -48,6 +56,8 @@ class Request:
     host_in: object   # pinned host tensor with the request's input words
     t_done: float = math.nan
     slot: tuple = None
+    host_share: object = None  # protocol mode: pinned int64 share [C*H*W]
+    host_mask: object = None   # protocol mode: pinned int64 mask [M*Ho*Wo]
 
 
 @dataclass
@@ -65,9 +75,10 @@ class Stats:
 class Server:
     """Resident layers + slot pools + a stream pool."""
 
-    def __init__(self, layers: list[Layer], n_streams: int = 4, hbm_budget: float = 200e9):
+    def __init__(self, layers: list[Layer], n_streams: int = 4, hbm_budget: float = 200e9, protocol: bool = False):
         import torch
         self.torch = torch
+        self.protocol = protocol
         self.layers = layers
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]  # default priority
         self.budget = float(hbm_budget)
@@ -78,24 +89,29 @@ class Server:
         self.free_slots = {i: [] for i in range(len(layers))}
 
     # -- slots ---------------------------------------------------------------
+    def _slot_words(self, L: Layer) -> list[int]:
+        w = [L.in_words, L.out_words]
+        if self.protocol:
+            w += [L.share_words, L.mask_words, L.y_words]
+        return w
+
     def _slot(self, li: int):
-        """(d_in, d_out) for layer li from the pool, or a new pair if the
-        budget allows; None when it does not."""
+        """(d_in, d_out[, d_share, d_mask, d_y]) for layer li from the pool,
+        or a new set if the budget allows; None when it does not."""
         if self.free_slots[li]:
             return self.free_slots[li].pop()
         L = self.layers[li]
-        need = (L.in_words + L.out_words) * 8
+        need = sum(self._slot_words(L)) * 8
         # idle slots of other layers give their memory back first
         for lj, pool in self.free_slots.items():
             while pool and self.used + need > self.budget:
                 pool.pop()
-                Lj = self.layers[lj]
-                self.used -= (Lj.in_words + Lj.out_words) * 8
+                self.used -= sum(self._slot_words(self.layers[lj])) * 8
         if self.used + need > self.budget:
             return None
         self.used += need
         t = self.torch
-        return (t.empty(L.in_words, dtype=t.int64, device="cuda"), t.empty(L.out_words, dtype=t.int64, device="cuda"))
+        return tuple(t.empty(w, dtype=t.int64, device="cuda") for w in self._slot_words(L))
 
     def _release(self, li: int, slot):
         self.free_slots[li].append(slot)
@@ -106,7 +122,13 @@ class Server:
         L = self.layers[r.layer]
         with t.cuda.stream(stream):
             r.slot[0].copy_(r.host_in, non_blocking=True)
+            if self.protocol:
+                r.slot[2].copy_(r.host_share, non_blocking=True)
+                r.slot[3].copy_(r.host_mask, non_blocking=True)
+                L.ctx.add_share(L.desc, 1, r.slot[0], r.slot[2], stream=stream)
             L.ctx.conv_layer(L.desc, 1, r.slot[0], L.wntt, r.slot[1], stream=stream)
+            if self.protocol:
+                L.ctx.mask_extract(L.desc, 1, r.slot[1], r.slot[3], None, r.slot[4], stream=stream)
             ev = t.cuda.Event(enable_timing=True)
             ev.record(stream)
         return ev
@@ -115,7 +137,8 @@ class Server:
         """Serve `requests`.  Open loop: a request becomes available at its
         arrival time.  Closed loop: all are available at once (saturation).
         keep_outputs: completed requests keep their slot (r.slot[1] holds the
-        result after the run) instead of returning it to the pool."""
+        result after the run, and in protocol mode r.slot[4] the extracted
+        outputs) instead of returning it to the pool."""
         t = self.torch
         t.cuda.synchronize()
         start_ev = t.cuda.Event(enable_timing=True)
@@ -181,7 +204,9 @@ def make_layer(ctx: heconv.Context, shape, w_dev) -> Layer:
     wntt = torch.empty(s.w_words, dtype=torch.int64, device="cuda")
     ctx.encode_weights(d, w_dev, wntt)
     ct = 2 * ctx.L * ctx.N
-    return Layer(ctx, tuple(shape), d, s, wntt, s.in_cts * ct, s.out_cts * ct)
+    ho, wo = ctx.out_hw(d)
+    return Layer(ctx, tuple(shape), d, s, wntt, s.in_cts * ct, s.out_cts * ct,
+                 share_words=d.C * d.H * d.W, mask_words=d.M * ho * wo, y_words=d.M * ctx.L * ho * wo)
 
 
 def poisson_arrivals(rate: float, n: int, u: np.ndarray) -> np.ndarray:

@@ -92,3 +92,33 @@ def test_budget_too_small_for_weights():
     _, layers = build_server(n_streams=1, budget=200e9)
     with pytest.raises(MemoryError):
         serving.Server(layers, hbm_budget=1e6)
+
+
+def test_protocol_mode_equals_direct_calls():
+    """Protocol mode (share folded in, layer, masked extraction) gives the
+    same extracted words as the three calls made directly."""
+    require_gpu()
+    ensure_built()
+    import torch
+    from paper_2506_11586_amd import serving
+    _, layers = build_server(n_streams=4, budget=200e9)
+    server = serving.Server(layers, n_streams=4, hbm_budget=200e9, protocol=True)
+    reqs = make_requests(layers, 24, rate=5000.0, seed=43)
+    for r in reqs:
+        lay = layers[r.layer]
+        r.host_share = torch.from_numpy(Stream(4300 + r.rid, synth.SHARE).words(lay.share_words).view(np.int64)
+                                        .copy()).pin_memory()
+        r.host_mask = torch.from_numpy(Stream(4300 + r.rid, synth.MASK).words(lay.mask_words).view(np.int64)
+                                       .copy()).pin_memory()
+    direct = []
+    for r in reqs:
+        lay = layers[r.layer]
+        d_in, d_out, y = r.host_in.cuda(), empty_words(lay.out_words), empty_words(lay.y_words)
+        lay.ctx.add_share(lay.desc, 1, d_in, r.host_share.cuda())
+        lay.ctx.conv_layer(lay.desc, 1, d_in, lay.wntt, d_out)
+        lay.ctx.mask_extract(lay.desc, 1, d_out, r.host_mask.cuda(), None, y)
+        direct.append(to_host(y).copy())
+    st = server.run(reqs, keep_outputs=True)
+    assert st.n == len(reqs)
+    for r, want in zip(reqs, direct):
+        assert np.array_equal(to_host(r.slot[4]), want), r.rid
