@@ -127,3 +127,32 @@ def test_batch_cfg2_and_fire_layers():
         ctx.conv_layer(d, B, to_dev(x), wntt, ref_out)
         assert np.array_equal(to_host(d_out), to_host(ref_out)), d
     b.close()
+
+
+def test_full_fire_cnn_batched_sampled_against_oracle():
+    """The whole fire-module CNN (26 convs at 224 input, batch 1, N=8192,
+    L=3, the weights 3.9 GiB resident) as one batch (two chains, hipGraph):
+    three sampled output words of every layer equal the oracle's layer by
+    definition (one coefficient of the negacyclic sum over channel blocks)."""
+    require_gpu()
+    ensure_built()
+    from paper_2506_11586_amd import heconv
+    cfg = synth.WORKLOADS["fire_cnn"]
+    prm = oracle.Params(cfg["N"], cfg["L"], cfg["bits"], 2 ** 37)
+    ctx = heconv.Context(cfg["N"], heconv.gen_primes(cfg["N"], cfg["bits"], cfg["L"]))
+    jobs, host = make_jobs(ctx, prm, [(s, 1) for s in cfg["layers"]], 900)
+    b = heconv.Batch(ctx, jobs, schedule=2)
+    b.launch(graph=True)
+    b.status()
+    rng = Stream(901, synth.MIX)
+    for (d, B, d_in, wntt, d_out), (cv, _, _, x, K) in zip(jobs, host):
+        g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+        got = to_host(d_out).reshape(1, cv.M, g.S, 2, prm.L, prm.N)
+        xin = x.reshape(1, g.CB, g.S, 2, prm.L, prm.N)
+        for _ in range(3):
+            m, s, c, l, k = (int(rng.below(1, v)[0]) for v in (cv.M, g.S, 2, prm.L, prm.N))
+            wc = oracle.pack_weights(K[m:m + 1], cv, g, prm)
+            assert int(got[0, m, s, c, l, k]) == oracle.conv_layer_coeff(xin, wc, g, prm, 0, 0, s, c, l, k), \
+                (cv, m, s, c, l, k)
+    b.close()
+    ctx.close()
