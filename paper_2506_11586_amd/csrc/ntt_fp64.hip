@@ -2,14 +2,20 @@
 // residue is an exact double, and a modular product takes two products, two
 // fused multiply-adds, a rounding and one conditional add -- all full-rate
 // fp64 operations on gfx950, where the integer path's 32-bit multiplies run
-// at half rate.  Same transform, order, mapping and passes as ntt_impl.h;
-// values stay canonical in [0, q) between stages.
+// at half rate.  Same transform, order, mapping and passes as ntt_impl.h.
+// Between stages values are balanced residues, |x| <= q/2 + 1, so no
+// compare-and-select is needed anywhere but in the final canonical step.
 //
-// mulmod(a, b), a, b in [0, q), q < 2^50:
+// mulmod(a, b), |a| <= 2^50, 0 <= b < q < 2^50:
 //   hi = RN(a*b), lo = a*b - hi (exact, by the fused multiply-add),
-//   k = rint(RN(hi * RN(1/q))) is within 0.875 of a*b/q,
-//   r = RN(hi - k*q) + lo = a*b - k*q exactly (integers below 2^51),
-//   r in (-q, q); add q when negative.
+//   k = rint(RN(hi * RN(1/q))) is within 0.875 of a*b/q (three roundings of
+//   relative size 2^-53 on a quotient below 2^50, plus the rounding to an
+//   integer), and r = RN(hi - k*q) + lo = a*b - k*q exactly (integers below
+//   2^52), so |r| < 0.875 q.
+// red(s), |s| < 2^51: s - rint(RN(s * RN(1/q))) * q, exact, |result| <= q/2 + 1.
+// A forward butterfly is red(x0 + T), red(x0 - T) with T = mulmod(x1, w);
+// an inverse one red(X + Y), red(mulmod(X - Y, w)); with canonical inputs
+// (|x| < q) or balanced ones, every mulmod input stays below q + 2.
 #include "kernels.h"
 #include "ntt_impl.h"
 
@@ -23,19 +29,12 @@ __device__ __forceinline__ double mulmod_f64(double a, double b, double q, doubl
   const double hi = a * b;
   const double lo = __fma_rn(a, b, -hi);
   const double k = rint(hi * qinv);
-  const double r = __fma_rn(-k, q, hi) + lo;
-  return r < 0.0 ? r + q : r;
+  return __fma_rn(-k, q, hi) + lo;
 }
 
-__device__ __forceinline__ double addmod_f64(double a, double b, double q) {
-  const double s = a + b;
-  return s >= q ? s - q : s;
-}
+__device__ __forceinline__ double red_f64(double s, double q, double qinv) { return __fma_rn(-rint(s * qinv), q, s); }
 
-__device__ __forceinline__ double submod_f64(double a, double b, double q) {
-  const double d = a - b;
-  return d < 0.0 ? d + q : d;
-}
+__device__ __forceinline__ double canon_f64(double r, double q) { return r < 0.0 ? r + q : r; }
 
 template <int LOGN, int LOGE, int LO, int U0>
 __device__ __forceinline__ void fwd_pass_f64(double (&x)[1 << LOGE], int tid, const double* __restrict__ tw,
@@ -53,8 +52,8 @@ __device__ __forceinline__ void fwd_pass_f64(double (&x)[1 << LOGE], int tid, co
         const int k0 = g * 2 * half + e, k1 = k0 + half;
         const double T = mulmod_f64(x[k1], w, c.q, c.qinv);
         const double X = x[k0];
-        x[k0] = addmod_f64(X, T, c.q);
-        x[k1] = submod_f64(X, T, c.q);
+        x[k0] = red_f64(X + T, c.q, c.qinv);
+        x[k1] = red_f64(X - T, c.q, c.qinv);
       }
     }
   }
@@ -72,8 +71,8 @@ __device__ __forceinline__ void inv_pass_f64(double (&x)[1 << LOGE], int tid, co
 #pragma unroll
       for (int e = 0; e < half; e++) {
         const double X = x[e], Y = x[e + half];
-        x[e] = mulmod_f64(addmod_f64(X, Y, c.q), c.ninv, c.q, c.qinv);
-        x[e + half] = mulmod_f64(submod_f64(X, Y, c.q), c.ninv_w, c.q, c.qinv);
+        x[e] = canon_f64(mulmod_f64(red_f64(X + Y, c.q, c.qinv), c.ninv, c.q, c.qinv), c.q);
+        x[e + half] = canon_f64(mulmod_f64(X - Y, c.ninv_w, c.q, c.qinv), c.q);
       }
       continue;
     }
@@ -84,8 +83,8 @@ __device__ __forceinline__ void inv_pass_f64(double (&x)[1 << LOGE], int tid, co
       for (int e = 0; e < half; e++) {
         const int k0 = g * 2 * half + e, k1 = k0 + half;
         const double X = x[k0], Y = x[k1];
-        x[k0] = addmod_f64(X, Y, c.q);
-        x[k1] = mulmod_f64(submod_f64(X, Y, c.q), w, c.q, c.qinv);
+        x[k0] = red_f64(X + Y, c.q, c.qinv);
+        x[k1] = red_f64(mulmod_f64(X - Y, w, c.q, c.qinv), c.q, c.qinv);
       }
     }
   }
@@ -144,6 +143,8 @@ __global__ __launch_bounds__((1 << LOGN) >> LOGE) void ntt_fwd_f64_kernel(uint64
 #pragma unroll
   for (int k = 0; k < E; k++) x[k] = (double)a[tid + k * T];
   fwd_rest_f64<LOGN, LOGE, 0>(x, lds, tid, tw, c);
+#pragma unroll
+  for (int k = 0; k < E; k++) x[k] = canon_f64(x[k], c.q);
   exchange_f64<LOGE, 0, TOP>(lds, x, tid);
 #pragma unroll
   for (int k = 0; k < E; k++) a[tid + k * T] = (uint64_t)x[k];
