@@ -219,7 +219,7 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
     k.q = q, k.two_q = 2 * q;
     k.ninv = mpow(N % q, q - 2, q), k.ninv_sh = shoup(k.ninv, q);
     k.ninv_w = mmul(k.ninv, inv[(size_t)l * N + 1].w, q), k.ninv_w_sh = shoup(k.ninv_w, q);
-    k.r64 = (uint64_t)(((u128)1 << 64) % q), k.r64_sh = shoup(k.r64, q);
+    k.r64 = (uint64_t)(((u128)1 << 64) % q), k.r64_sh = shoup(k.r64, q), k.r64_sh63 = shoup63(k.r64, q);
     k.mu64 = (uint64_t)(((u128)1 << 64) / q);
     k.c30 = (uint64_t)(((u128)1 << 30) % q), k.c30_sh = shoup(k.c30, q);
     k.c60 = (uint64_t)(((u128)1 << 60) % q), k.c60_sh = shoup(k.c60, q);

@@ -21,6 +21,7 @@ struct LimbConst {
   uint64_t c60, c60_sh;        // 2^60 mod q and its Shoup quotient
   uint64_t delta, delta_sh;    // floor(Q/t) mod q and its Shoup quotient (0 if t is unusable)
   uint64_t negq, neg2q;        // 2^64 - q and 2^64 - 2q
+  uint64_t r64_sh63;           // Shoup quotient of 2^64 mod q at scale 2^63
 };
 
 // Device buffers are passed to the transform and MAC bodies as pointers in
@@ -113,13 +114,19 @@ __device__ __forceinline__ Half30 split30(uint64_t x) {
 // a11*2^60, reduced into [0, q).
 __device__ __forceinline__ uint64_t fold30(uint64_t a00, uint64_t a01, uint64_t a10, uint64_t a11,
                                            const LimbConst& c) {
-  uint64_t s = reduce64_lazy(a00, c.mu64, c.q);         // [0, 2q)
-  s += mul_shoup_lazy(a01, c.c30, c.c30_sh, c.q);       // [0, 4q)
-  s += mul_shoup_lazy(a10, c.c30, c.c30_sh, c.q);       // [0, 6q)
-  s += mul_shoup_lazy(a11, c.c60, c.c60_sh, c.q);       // [0, 8q) < 2^63
-  s = csub(s, 4 * c.q);
-  s = csub(s, c.two_q);
-  return csub(s, c.q);
+  // T = a00 + (a01 + a10)*2^30 + a11*2^60 < 2^125 as (hi, t), hi < 2^61 (q > 2^30,
+  // so 2^30 needs no reduction); then T mod q = hi*(2^64 mod q) + t mod q:
+  // one scale-2^63 Shoup product and one Shoup reduction of a word.
+  const uint64_t s = a01 + a10;
+  const uint64_t sc = s < a01;  // bit 64 of a01 + a10
+  const uint64_t lo = a00 + (s << 30);
+  const uint64_t c1 = lo < a00;
+  const uint64_t t = lo + (a11 << 60);
+  const uint64_t c2 = t < lo;
+  const uint64_t hi = (s >> 34) + (sc << 30) + (a11 >> 4) + c1 + c2;
+  uint64_t r = mul_shoup63(hi, c.r64, c.r64_sh63, c.negq) + reduce64_lazy(t, c.mu64, c.q);  // [0, 4q)
+  r = csub(r, c.two_q);
+  return csub(r, c.q);
 }
 
 }  // namespace heconv
