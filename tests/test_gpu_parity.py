@@ -316,3 +316,21 @@ def test_layer_largest_ring():
     want = oracle.conv_layer_ntt(x.reshape(1, g.CB, g.S, 2, prm.L, prm.N), oracle.encode_weights(K, cv, g, prm), 1, g,
                                  cv.M, prm)
     assert np.array_equal(to_host(out).reshape(want.shape), want)
+
+
+def test_empty_batch_is_a_noop():
+    """B = 0 (no images) is a successful no-op for every layer entry point,
+    with or without buffers; a descriptor error is still reported first."""
+    from paper_2506_11586_amd import heconv
+    ctx, prm = ctx_and_prm(4096, 2, 50)
+    d = ctx.plan((4, 16, 16, 4, 3, 3, 1, 1))
+    L = heconv.lib()
+    ref = heconv.ctypes.byref(d)
+    for fn in (L.he_conv_layer, L.he_conv_ntt_mac, L.he_conv_mac_intt):
+        assert fn(ctx.handle, ref, 0, None, None, None, None) == heconv.HE_OK
+    guard = empty_words(16)
+    guard.fill_(7)
+    assert L.he_conv_layer(ctx.handle, ref, 0, guard.data_ptr(), guard.data_ptr(), guard.data_ptr(), None) == heconv.HE_OK
+    assert bool((guard == 7).all())
+    bad = heconv.ConvDesc(*d.shape(), 5, d.Hw, d.Ww)  # Cw > C
+    assert L.he_conv_layer(ctx.handle, heconv.ctypes.byref(bad), 0, None, None, None, None) == heconv.HE_ESHAPE
