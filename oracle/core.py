@@ -14,6 +14,11 @@ Paper passages (SecONNds, arXiv 2506.11586):
                                      (Cheetah paragraph)
   server share, mask, extraction ... Sec. 7 (online protocol, linear
                                      layers) and Sec. 6.2
+  rotation (automorphism and key
+  switching) for the Z_P variant .... Sec. 2 (HE operations: rotations need
+                                     key switching with evaluation keys),
+                                     Sec. 6.1 (iterative MAC + rotation);
+                                     the key-switching method is a reading
 The paper gives no formula for the packing, no HE parameters and no tiling
 rule; the readings used (packing layout, largest primes, smallest root,
 bytes-objective planner, round-half-up decode) are listed with the design
@@ -566,3 +571,108 @@ def decrypt_extracted(a_polys, y, sk, cv: Conv, g: Geometry, prm: Params, with_n
     for l, q in enumerate(prm.q):
         v[..., l] = ((_u64(y)[:, l].astype(object) + v0[:, s, l, k].astype(object)) % q).astype(np.uint64)
     return bfv_decode(v, prm, with_noise)
+
+
+# --------------------------------------------------------------------------
+# Ciphertext rotation for the Z_P variant (Sec. 6.1: its linear kernels
+# combine multiply-accumulates with rotations; App. C, rotation): the Galois
+# automorphism X -> X^g and hybrid key switching with one special prime P.
+# --------------------------------------------------------------------------
+def automorphism(polys, g: int, q_list) -> np.ndarray:
+    """a(X) -> a(X^g) in Z_q[X]/(X^N+1) for odd g: coefficient i moves to
+    i*g mod 2N, negated (mod q_l) when that index is N or more.
+    polys [..., L, N] with q_list the L moduli."""
+    a = _u64(polys)
+    N = a.shape[-1]
+    assert g % 2 == 1
+    out = np.zeros_like(a)
+    idx = (np.arange(N, dtype=np.int64) * g) % (2 * N)
+    neg = idx >= N
+    dst = np.where(neg, idx - N, idx)
+    for l, q in enumerate(q_list):
+        src = a[..., l, :]
+        vals = np.where(neg, np.where(src == 0, np.uint64(0), np.uint64(q) - src), src)
+        o = out[..., l, :]
+        o[..., dst] = vals
+    return out
+
+
+def ext_params(prm: Params, P: int) -> Params:
+    """The extended basis q_0..q_{L-1}, P (P last) of the same ring."""
+    return Params(prm.N, prm.L + 1, prm.bits, prm.t, q=list(prm.q) + [int(P)])
+
+
+def galois_key(sk, g: int, a, e, prm: Params, P: int) -> np.ndarray:
+    """Key switching key from s(X^g) to s over Z_{QP}: for every digit l < L
+    a pair (k_a, k_b) with k_a = a[l] (uniform, [L+1][N] residues) and
+    k_b = k_a*s + e[l] + G_l*s(X^g), where G_l = P*Qhat_l*(Qhat_l^-1 mod q_l)
+    and Qhat_l = Q/q_l, all mod QP (per modulus).  Returns [L][2][L+1][N]
+    in coefficient form (k_a first, as a ciphertext's a component)."""
+    ext = ext_params(prm, P)
+    N, L = prm.N, prm.L
+    sk = np.asarray(sk, dtype=np.int64)
+    s_lift = np.array([[int(v) % q for v in sk.tolist()] for q in ext.q], dtype=np.uint64)  # [L+1][N]
+    sg = automorphism(s_lift, g, ext.q)
+    QP = prm.Q * P
+    out = np.zeros((L, 2, L + 1, N), dtype=np.uint64)
+    e = np.asarray(e, dtype=np.int64).reshape(L, N)
+    for l in range(L):
+        Qh = prm.Q // prm.q[l]
+        G = (P * Qh * pow(Qh % prm.q[l], -1, prm.q[l])) % QP
+        ka = _u64(a).reshape(L, L + 1, N)[l]
+        out[l, 0] = ka
+        for j, q in enumerate(ext.q):
+            prod = negacyclic_mul(ka[j], s_lift[j], q)
+            el = np.array([int(v) % q for v in e[l].tolist()], dtype=object)
+            gj = G % q
+            v = (prod.astype(object) + el + (gj * sg[j].astype(object))) % q
+            out[l, 1, j] = v.astype(np.uint64)
+    return out
+
+
+def key_switch(ct, ksk, prm: Params, P: int) -> np.ndarray:
+    """Key switching of ct [n][2][L][N] (coefficient form, phase b - a*s')
+    with a key from s' to s (galois_key): digits d_l = the limb-l residues
+    of a, as integers in [0, q_l); over Z_{QP}, A = sum_l d_l*k_a[l] and
+    B = sum_l d_l*k_b[l] (ring products per modulus); then division by P
+    with rounding, y = (x - [x]_P)/P with [x]_P the residue mod P centred
+    into (-P/2, P/2], computed on the integer x from the CRT of all L+1
+    residues; result (-A', b - B') mod Q, of phase b - a*s' up to a small
+    error."""
+    ext = ext_params(prm, P)
+    N, L = prm.N, prm.L
+    ct = _u64(ct).reshape(-1, 2, L, N)
+    n = ct.shape[0]
+    ksk = _u64(ksk).reshape(L, 2, L + 1, N)
+    QP = prm.Q * P
+    out = np.zeros_like(ct)
+    for i in range(n):
+        acc = np.zeros((2, L + 1, N), dtype=object)
+        for l in range(L):
+            d = ct[i, 0, l]  # digit l: integers below q_l
+            for j, q in enumerate(ext.q):
+                dj = (d % np.uint64(q)).astype(np.uint64)
+                for c in range(2):
+                    acc[c, j] = (acc[c, j] + negacyclic_mul(dj, ksk[l, c, j], q).astype(object)) % q
+        # exact division by P with rounding, coefficient by coefficient
+        crt_c = []
+        for j, q in enumerate(ext.q):
+            Mj = QP // q
+            crt_c.append(Mj * pow(Mj % q, -1, q))
+        for c in range(2):
+            X = sum(acc[c, j] * crt_c[j] for j in range(L + 1)) % QP  # [N] Python ints
+            xp = X % P
+            xp = np.where(xp > P // 2, xp - P, xp)
+            Y = (X - xp) // P
+            for j, q in enumerate(prm.q):
+                y = (Y % q).astype(np.uint64)
+                if c == 0:
+                    out[i, 0, j] = ((q - y.astype(object)) % q).astype(np.uint64)
+                else:
+                    out[i, 1, j] = ((ct[i, 1, j].astype(object) - y.astype(object)) % q).astype(np.uint64)
+    return out
+
+
+def rotate(ct, g: int, ksk, prm: Params, P: int) -> np.ndarray:
+    """Automorphism of both components, then key switching back to s."""
+    return key_switch(automorphism(_u64(ct), g, prm.q), ksk, prm, P)
