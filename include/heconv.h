@@ -291,6 +291,51 @@ he_status he_decrypt(const he_ctx* ctx, uint64_t n, const uint64_t* d_ct, const 
                      uint64_t* d_work, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Rotation for the Z_P variant (Sec. 2: a rotation is a Galois automorphism
+ * followed by key switching with an evaluation key; Sec. 6.1: the Z_P
+ * kernels rotate once per multiply-accumulate iteration).  Key switching is
+ * hybrid RNS key switching with one special prime P: the calls take an
+ * EXTENDED context created with the L ciphertext primes followed by P
+ * (ext->L = L + 1; P distinct and of about the size of the q's, which keeps
+ * the added noise near N*L*q*e/P).  Ciphertexts are [n][2][L][N] in
+ * coefficient form, canonical, of phase b - a*s.
+ * Key layout (d_ksk_ntt): [L][2][L+1][N] residues over q_0..q_{L-1}, P in
+ * NTT form (transform coefficient-form keys with he_ntt_fwd on the extended
+ * context, 2L RNS polynomials): for digit l the pair (k_a, k_b) with
+ * k_b = k_a*s + e_l + G_l*s' over Z_QP, G_l = P * Qhat_l * (Qhat_l^-1 mod q_l)
+ * and Qhat_l = Q/q_l, which switches from s' to s.  The caller makes keys.
+ * ------------------------------------------------------------------------ */
+
+/* Words of scratch that he_keyswitch and he_rotate need for n ciphertexts:
+ * n * (L+2) * (L+1) * N (digits [n][L][L+1][N], then [n][2][L+1][N]). */
+he_status he_keyswitch_work_words(const he_ctx* ext, uint64_t n, uint64_t* words);
+
+/* The automorphism a(X) -> a(X^g) of n RNS polynomials [n][L][N] of `ctx`
+ * (coefficient form, canonical): coefficient i moves to i*g mod 2N and is
+ * negated when that index is N or more.  g odd with 0 < g < 2N, else
+ * HE_EINVAL; out of place (d_in == d_out is HE_EINVAL).  Applied to both
+ * components of a ciphertext it gives one of phase m(X^g) under s(X^g). */
+he_status he_automorph(const he_ctx* ctx, uint64_t g, uint64_t n, const uint64_t* d_in, uint64_t* d_out,
+                       void* stream);
+
+/* Key switching of n ciphertexts from s' to s: digits d_l = limb l of a
+ * (integers below q_l), A = sum_l d_l*k_a[l] and B = sum_l d_l*k_b[l] over
+ * Z_QP, each divided by P with rounding (the residue mod P centred into
+ * (-P/2, P/2]); d_out = (-A', b - B') mod Q, [n][2][L][N] canonical, written
+ * completely; it may alias d_ct.  d_work: he_keyswitch_work_words words,
+ * clobbered.  HE_EPARAM if ext->L < 2; HE_ESHAPE if n is too large for one
+ * launch; n = 0 is a no-op. */
+he_status he_keyswitch(const he_ctx* ext, uint64_t n, const uint64_t* d_ct, const uint64_t* d_ksk_ntt,
+                       uint64_t* d_out, uint64_t* d_work, void* stream);
+
+/* Rotation: he_automorph of both components by g, then he_keyswitch with a
+ * key from s(X^g) to s; the automorphism is applied while the digits and b
+ * are read, so the rotated ciphertext is never stored.  Out of place
+ * (d_ct == d_out is HE_EINVAL); g as for he_automorph. */
+he_status he_rotate(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_ct, const uint64_t* d_ksk_ntt,
+                    uint64_t* d_out, uint64_t* d_work, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batch executor: many layer solves of uneven shape in one launch.
  * Each job is one he_conv_layer call's worth of work (same buffers, same
  * result).  A batch runs the forward NTT of every job's input limb

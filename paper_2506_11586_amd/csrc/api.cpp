@@ -594,4 +594,87 @@ he_status he_decrypt(const he_ctx* c, uint64_t n, const uint64_t* d_ct, const ui
   return HE_OK;
 }
 
+// ---- rotation for the Z_P variant (extended context: q_0..q_{L-1}, P) ----
+
+namespace {
+
+constexpr uint64_t ROT_MAX_BLOCKS = 0x7fffffffull;
+
+// g^-1 mod 2N for odd g (the odd residues mod 2N form a group).
+uint32_t inv_mod_2n(uint64_t g, uint32_t N) {
+  const uint64_t m = 2ull * N;
+  uint64_t r = 1;
+  for (uint64_t e = m / 2 - 1, b = g % m; e; e >>= 1, b = b * b % m)
+    if (e & 1) r = r * b % m;
+  return (uint32_t)r;
+}
+
+bool galois_ok(uint64_t g, uint32_t N) { return (g & 1) && g < 2ull * N; }
+
+// Shape checks shared by key switching and rotation; L = ext->L - 1.
+he_status ks_check(const he_ctx* ext, uint64_t n) {
+  if (check_ctx(ext)) return HE_EINVAL;
+  if (ext->L < 2) return HE_EPARAM;
+  const uint64_t L = ext->L - 1, per = ext->N / 256;
+  if (n > ROT_MAX_BLOCKS / (L * (L + 1) * per)) return HE_ESHAPE;
+  return HE_OK;
+}
+
+he_status ks_run(const he_ctx* ext, uint32_t ginv, uint64_t n, const uint64_t* ct, const uint64_t* ksk, uint64_t* out,
+                 uint64_t* work, hipStream_t st) {
+  const uint32_t L = ext->L - 1, N = ext->N;
+  const uint64_t P = ext->q[L];
+  heconv::PinvConst pc{};
+  for (uint32_t j = 0; j < L; j++) {
+    const uint64_t q = ext->q[j];
+    pc.v[j] = mpow(P % q, q - 2, q);
+    pc.sh[j] = shoup(pc.v[j], q);
+  }
+  uint64_t* digits = work;                                   // [n][L][L+1][N]
+  uint64_t* acc = work + n * L * (uint64_t)(L + 1) * N;      // [n][2][L+1][N]
+  he_status s = dev_err(heconv::modup_launch(ct, digits, n, N, L, ginv, ext->d_lc, st));
+  if (!s) s = dev_err(ntt_run(ext, false, digits, n * L, st));
+  if (!s) s = dev_err(heconv::ks_inner_launch(digits, ksk, acc, n, N, L, ext->d_lc, st));
+  if (!s) s = dev_err(ntt_run(ext, true, acc, 2 * n, st));
+  if (!s) s = dev_err(heconv::moddown_launch(acc, ct, out, n, N, L, ginv, pc, ext->d_lc, st));
+  return s;
+}
+
+}  // namespace
+
+he_status he_keyswitch_work_words(const he_ctx* ext, uint64_t n, uint64_t* words) {
+  if (!words) return HE_EINVAL;
+  if (he_status s = ks_check(ext, n)) return s;
+  const uint64_t L = ext->L - 1;
+  *words = n * (L + 2) * (L + 1) * ext->N;
+  return HE_OK;
+}
+
+he_status he_automorph(const he_ctx* c, uint64_t g, uint64_t n, const uint64_t* d_in, uint64_t* d_out, void* stream) {
+  if (check_ctx(c)) return HE_EINVAL;
+  if (!galois_ok(g, c->N)) return HE_EINVAL;
+  if (n > ROT_MAX_BLOCKS / ((uint64_t)c->L * (c->N / 256))) return HE_ESHAPE;
+  if (n == 0) return HE_OK;
+  if (!d_in || !d_out || d_in == d_out) return HE_EINVAL;
+  return dev_err(heconv::automorph_launch(d_in, d_out, n * c->L, c->N, c->L, inv_mod_2n(g, c->N), c->d_lc,
+                                          (hipStream_t)stream));
+}
+
+he_status he_keyswitch(const he_ctx* ext, uint64_t n, const uint64_t* d_ct, const uint64_t* d_ksk_ntt, uint64_t* d_out,
+                       uint64_t* d_work, void* stream) {
+  if (he_status s = ks_check(ext, n)) return s;
+  if (n == 0) return HE_OK;
+  if (!d_ct || !d_ksk_ntt || !d_out || !d_work) return HE_EINVAL;
+  return ks_run(ext, 1, n, d_ct, d_ksk_ntt, d_out, d_work, (hipStream_t)stream);
+}
+
+he_status he_rotate(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_ct, const uint64_t* d_ksk_ntt,
+                    uint64_t* d_out, uint64_t* d_work, void* stream) {
+  if (he_status s = ks_check(ext, n)) return s;
+  if (!galois_ok(g, ext->N)) return HE_EINVAL;
+  if (n == 0) return HE_OK;
+  if (!d_ct || !d_ksk_ntt || !d_out || !d_work || d_ct == d_out) return HE_EINVAL;
+  return ks_run(ext, inv_mod_2n(g, ext->N), n, d_ct, d_ksk_ntt, d_out, d_work, (hipStream_t)stream);
+}
+
 }  // extern "C"

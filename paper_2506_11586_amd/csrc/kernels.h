@@ -27,6 +27,19 @@ void f64_const_fill(void* out, double q, double qinv, double ninv, double ninv_w
 hipError_t ntt_f64_launch(bool inverse, uint32_t logN, uint32_t loge, uint64_t* polys, uint64_t n_rns_polys,
                           uint32_t L, const double* tw, const void* fc, hipStream_t st);
 
+// Rotation (automorphism + hybrid key switching with a special prime).
+struct PinvConst {
+  uint64_t v[7], sh[7];  // P^-1 mod q_j and its Shoup quotient, j < L (L <= 7)
+};
+hipError_t automorph_launch(const uint64_t* in, uint64_t* out, uint64_t rows, uint32_t N, uint32_t L, uint32_t ginv,
+                            const LimbConst* lc, hipStream_t st);
+hipError_t modup_launch(const uint64_t* ct, uint64_t* work, uint64_t n, uint32_t N, uint32_t L, uint32_t ginv,
+                        const LimbConst* ext, hipStream_t st);
+hipError_t ks_inner_launch(const uint64_t* work, const uint64_t* ksk, uint64_t* acc, uint64_t n, uint32_t N,
+                           uint32_t L, const LimbConst* ext, hipStream_t st);
+hipError_t moddown_launch(const uint64_t* acc, const uint64_t* ct, uint64_t* out, uint64_t n, uint32_t N, uint32_t L,
+                          uint32_t ginv, const PinvConst& pinv, const LimbConst* ext, hipStream_t st);
+
 // Geometry of a planned conv as the kernels need it.
 struct PackGeom {
   uint32_t M, C, kh, kw, Cw, Hw, Ww, CB, L, N, O;

@@ -98,6 +98,10 @@ def _lib_handle():
         L.he_decrypt.argtypes = [vp, u64, vp, vp, vp, vp, vp]
         L.he_add_share.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp]
         L.he_mask_extract.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp, vp]
+        L.he_keyswitch_work_words.argtypes = [vp, u64, P(u64)]
+        L.he_automorph.argtypes = [vp, u64, u64, vp, vp, vp]
+        L.he_keyswitch.argtypes = [vp, u64, vp, vp, vp, vp, vp]
+        L.he_rotate.argtypes = [vp, u64, u64, vp, vp, vp, vp, vp]
         L.he_batch_create.argtypes = [vp, P(_Job), u32, u32, P(vp)]
         L.he_batch_launch.argtypes = [vp, vp, i32]
         L.he_batch_status.argtypes = [vp, vp]
@@ -109,7 +113,8 @@ def _lib_handle():
         for name in ("he_gen_primes", "he_ctx_create", "he_ctx_psi", "he_ctx_get_tuning", "he_ctx_set_tuning", "he_plan_conv", "he_plan_conv_host", "he_min_root", "he_conv_sizes",
                      "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer",
                      "he_conv_mac_intt", "he_add_share", "he_mask_extract", "he_delta_host",
-                     "he_key_encode", "he_encrypt", "he_decrypt"):
+                     "he_key_encode", "he_encrypt", "he_decrypt", "he_keyswitch_work_words", "he_automorph",
+                     "he_keyswitch", "he_rotate"):
             getattr(L, name).restype = i32
         _LIB = L
     return _LIB
@@ -333,6 +338,38 @@ class Context:
         _check(lib().he_decrypt(self._h, int(n), _ptr(ct_dev, n * 2 * LN, "ct"), _ptr(sk_ntt_dev, LN, "sk_ntt"),
                                 _ptr(msgs_dev, n * self.N, "msgs"), _ptr(work_dev, n * LN, "work"),
                                 _stream(stream)), "he_decrypt")
+
+    # ---- rotation (this context is the extended one: L-1 ciphertext primes, then P) ----
+
+    def keyswitch_work_words(self, n: int) -> int:
+        """he_keyswitch_work_words: scratch words for n ciphertexts."""
+        w = ctypes.c_uint64()
+        _check(lib().he_keyswitch_work_words(self._h, int(n), ctypes.byref(w)), "he_keyswitch_work_words")
+        return int(w.value)
+
+    def automorph(self, g: int, n: int, in_dev, out_dev, stream=None):
+        """he_automorph: a(X) -> a(X^g) of n RNS polynomials [n][L][N]."""
+        LN = self.L * self.N
+        _check(lib().he_automorph(self._h, int(g), int(n), _ptr(in_dev, n * LN, "in"), _ptr(out_dev, n * LN, "out"),
+                                  _stream(stream)), "he_automorph")
+
+    def keyswitch(self, n: int, ct_dev, ksk_ntt_dev, out_dev, work_dev, stream=None):
+        """he_keyswitch on the extended context: ct [n][2][L-1][N] -> out."""
+        Lc = self.L - 1
+        ct = n * 2 * Lc * self.N
+        _check(lib().he_keyswitch(self._h, int(n), _ptr(ct_dev, ct, "ct"),
+                                  _ptr(ksk_ntt_dev, Lc * 2 * self.L * self.N, "ksk"), _ptr(out_dev, ct, "out"),
+                                  _ptr(work_dev, self.keyswitch_work_words(n), "work"), _stream(stream)),
+               "he_keyswitch")
+
+    def rotate(self, g: int, n: int, ct_dev, ksk_ntt_dev, out_dev, work_dev, stream=None):
+        """he_rotate on the extended context: automorphism by g, then key switching."""
+        Lc = self.L - 1
+        ct = n * 2 * Lc * self.N
+        _check(lib().he_rotate(self._h, int(g), int(n), _ptr(ct_dev, ct, "ct"),
+                               _ptr(ksk_ntt_dev, Lc * 2 * self.L * self.N, "ksk"), _ptr(out_dev, ct, "out"),
+                               _ptr(work_dev, self.keyswitch_work_words(n), "work"), _stream(stream)),
+               "he_rotate")
 
 
 class Batch:
