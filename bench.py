@@ -40,7 +40,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--workload", default="conv64_56x56", choices=["conv4_16x16", "conv64_56x56"],
                     help="single-layer workload of the main line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched fire-module CNN section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-client", action="store_true", help="skip the client-side encrypt/decrypt section")
+    ap.add_argument("--no-rotation", action="store_true", help="skip the ciphertext rotation section")
     ap.add_argument("--no-bottleneck", action="store_true",
                     help="skip the batch-16 bottleneck residual CNN section (about 230 GiB resident)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -238,6 +239,8 @@ def main():
         result["serving"] = run_serving(torch, heconv, args)
     if not args.no_client:
         result["client"] = run_client(torch, heconv)
+    if not args.no_rotation:
+        result["rotation"] = run_rotation(torch, heconv)
 
     if args.copy_probe:
         src = torch.ones(32 << 20, dtype=torch.int64, device="cuda")
@@ -253,10 +256,15 @@ def main():
     ctx.close()
 
 
-def _timed(torch, fn, reps, warm=2):
-    for _ in range(warm):
+def _timed(torch, fn, reps, warm=2, warm_s=0.1):
+    """Average ms of fn over reps calls, after at least `warm` calls and
+    warm_s seconds of calls: the GPU raises its clocks only under sustained
+    load, and a few milliseconds of warm-up time it while still ramping."""
+    t0, k = time.perf_counter(), 0
+    while k < warm or time.perf_counter() - t0 < warm_s:
         fn()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        k += 1
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(reps):
@@ -469,6 +477,67 @@ def run_client(torch, heconv):
     return {"workload": f"{n} ciphertexts, N={N}, L={L}", "encrypt_ms": t_enc, "decrypt_ms": t_dec,
             "encrypt_cts_per_s": n / t_enc * 1e3, "decrypt_cts_per_s": n / t_dec * 1e3,
             "roundtrip_exact": exact}
+
+
+def rotation_alg_bytes(N: int, L: int) -> int:
+    """HBM bytes one ciphertext's rotation must move through the five steps
+    (L ciphertext limbs, L+1 extended): digits written and transformed in
+    place, products summed into two polynomials, transformed back, divided
+    by P; the key (read once per launch) is not counted."""
+    w = 8 * N
+    modup = L * w + L * (L + 1) * w
+    ntt_fwd = 2 * L * (L + 1) * w
+    inner = L * (L + 1) * w + 2 * (L + 1) * w
+    ntt_inv = 2 * 2 * (L + 1) * w
+    moddown = 2 * (L + 1) * w + L * w + 2 * L * w
+    return modup + ntt_fwd + inner + ntt_inv + moddown
+
+
+def run_rotation(torch, heconv):
+    """Ciphertext rotation for the Z_P variant: 256 ciphertexts at N=8192,
+    L=3 (60-bit primes) with a 60-bit special prime, g = 5, one he_rotate
+    call; the key made on the GPU; every ciphertext decrypts to m(X^g)."""
+    cfg = synth.WORKLOADS["conv64_56x56"]
+    N, L, bits = cfg["N"], cfg["L"], cfg["bits"]
+    t = 2 ** synth.T_BITS
+    primes = heconv.gen_primes(N, bits, L + 1)
+    base, ext = heconv.Context(N, primes[:L], t), heconv.Context(N, primes, t)
+    n, g = 256, 5
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    dev = dict(dtype=torch.int64, device="cuda")
+    qx = torch.tensor(primes, **dev).view(1, L + 1, 1)
+    sk = torch.randint(-1, 2, (N,), generator=gen, **dev)
+    ka = torch.randint(0, 2 ** 62, (L, L + 1, N), generator=gen, **dev) % qx
+    ke = torch.randint(-21, 22, (L, N), generator=gen, **dev)
+    ksk = torch.empty(L * 2 * (L + 1) * N, **dev)
+    ext.galois_key(g, sk, ka.reshape(-1), ke.reshape(-1), ksk, torch.empty(ext.galois_key_work_words(), **dev))
+    skn = torch.empty(L * N, **dev)
+    base.key_encode(sk, skn)
+    msgs = torch.randint(0, t, (n, N), generator=gen, **dev)
+    a = torch.randint(0, 2 ** 62, (n, L, N), generator=gen, **dev) % qx[:, :L]
+    err = torch.randint(-21, 22, (n, N), generator=gen, **dev)
+    ct = torch.empty(n * 2 * L * N, **dev)
+    base.encrypt(n, msgs, a, err, skn, ct, torch.empty(n * L * N, **dev))
+    out = torch.empty_like(ct)
+    work = torch.empty(ext.keyswitch_work_words(n), **dev)
+    ext.rotate(g, n, ct, ksk, out, work)
+    dec = torch.empty(n * N, **dev)
+    base.decrypt(n, out, skn, dec, torch.empty(n * L * N, **dev))
+    ginv = pow(g, -1, 2 * N)
+    k = (torch.arange(N, **dev) * ginv) % (2 * N)
+    neg = k >= N
+    want = msgs[:, torch.where(neg, k - N, k)]
+    want = torch.where(neg, (t - want) % t, want)
+    want = torch.where(want >= t // 2, want - t, want).reshape(-1)
+    exact = bool(torch.equal(dec, want))
+    ms = _timed(torch, lambda: ext.rotate(g, n, ct, ksk, out, work), 20)
+    alg = rotation_alg_bytes(N, L) * n
+    base.close()
+    ext.close()
+    return {"workload": f"{n} ciphertexts, N={N}, L={L} + one special prime, g={g}", "ms": ms,
+            "rotations_per_s": n / ms * 1e3, "alg_bytes": alg, "GBps": alg / (ms * 1e-3) / 1e9,
+            "decrypts_to_automorphism": exact}
 
 
 def run_serving(torch, heconv, args):

@@ -129,7 +129,14 @@ void he_ctx_destroy(he_ctx* ctx);
  * products, two fused multiply-adds, a rounding and a conditional add, all
  * at the full fp64 rate, where the integer path's 32-bit multiplies run at
  * half rate.  0 = always the integer kernels.
- * Defaults: {3, 3, 512, 0, 0, 0, 1, 160, 1}: 8 words per thread was measured faster
+ * ks_fused: how key switching and rotation (N <= 2^13) run their steps.
+ * 1 = two fused kernels: digit extension (and the automorphism) in the
+ * forward transform's load, the inner product with the key in the inverse
+ * transform's load.  2 = one kernel extends, transforms and multiplies all
+ * digits of a (ciphertext, modulus) pair by the key and stores only the two
+ * sums (registers limit it to one workgroup per compute unit).  0 = the
+ * steps as separate kernels.  Results are the same words in every mode.
+ * Defaults: {3, 3, 512, 0, 0, 0, 1, 160, 1, 1}: 8 words per thread was measured faster
  * than 16 at every count at N = 8192 (768 limb polys: 47.7 against 51.4 us
  * inverse); N = 16384 always uses 16.  The channel pipeline (layer_split)
  * was measured slower than the plain order on 64->64, 128->128 and
@@ -143,6 +150,7 @@ typedef struct {
   uint32_t layer_split;
   uint32_t ntt_split_below;
   uint32_t ntt_fp64;
+  uint32_t ks_fused;
 } he_tuning;
 
 he_status he_ctx_get_tuning(const he_ctx* ctx, he_tuning* out);
@@ -309,6 +317,16 @@ he_status he_decrypt(const he_ctx* ctx, uint64_t n, const uint64_t* d_ct, const 
 /* Words of scratch that he_keyswitch and he_rotate need for n ciphertexts:
  * n * (L+2) * (L+1) * N (digits [n][L][L+1][N], then [n][2][L+1][N]). */
 he_status he_keyswitch_work_words(const he_ctx* ext, uint64_t n, uint64_t* words);
+
+/* Client side (takes the secret key): the Galois key for g, written in NTT
+ * form to d_ksk_ntt [L][2][L+1][N] as he_keyswitch and he_rotate read it:
+ * k_a[l] = a[l], k_b[l] = a[l]*s + e[l] + G_l*s(X^g) over Z_QP.  d_sk: the
+ * key's N integer coefficients (int64); d_a: [L][L+1][N] uniform residues
+ * over q_0..q_{L-1}, P (canonical); d_err: int64 [L][N] small errors (random
+ * values are the caller's).  d_work: (2L+2)*(L+1)*N words, clobbered.
+ * g as for he_automorph; HE_EPARAM if ext->L < 2. */
+he_status he_galois_key(const he_ctx* ext, uint64_t g, const int64_t* d_sk, const uint64_t* d_a, const int64_t* d_err,
+                        uint64_t* d_ksk_ntt, uint64_t* d_work, void* stream);
 
 /* The automorphism a(X) -> a(X^g) of n RNS polynomials [n][L][N] of `ctx`
  * (coefficient form, canonical): coefficient i moves to i*g mod 2N and is

@@ -321,7 +321,7 @@ he_status he_ctx_set_tuning(he_ctx* c, const he_tuning* t) {
   static const uint32_t tiles[][2] = {{0, 0}, {4, 4}, {4, 2}, {2, 4}, {8, 2}, {2, 8}, {8, 1}, {1, 8}, {2, 2}};
   bool ok = false;
   for (auto& p : tiles) ok |= (p[0] == t->mac_mt && p[1] == t->mac_rt);
-  if (!ok || t->layer_fused > 1 || t->ntt_fp64 > 1) return HE_EINVAL;
+  if (!ok || t->layer_fused > 1 || t->ntt_fp64 > 1 || t->ks_fused > 2) return HE_EINVAL;
   if (t->layer_split != 1 && t->layer_split != 2 && t->layer_split != 4) return HE_EINVAL;
   c->tune = *t;
   return HE_OK;
@@ -632,10 +632,21 @@ he_status ks_run(const he_ctx* ext, uint32_t ginv, uint64_t n, const uint64_t* c
   }
   uint64_t* digits = work;                                   // [n][L][L+1][N]
   uint64_t* acc = work + n * L * (uint64_t)(L + 1) * N;      // [n][2][L+1][N]
-  he_status s = dev_err(heconv::modup_launch(ct, digits, n, N, L, ginv, ext->d_lc, st));
-  if (!s) s = dev_err(ntt_run(ext, false, digits, n * L, st));
-  if (!s) s = dev_err(heconv::ks_inner_launch(digits, ksk, acc, n, N, L, ext->d_lc, st));
-  if (!s) s = dev_err(ntt_run(ext, true, acc, 2 * n, st));
+  he_status s = HE_OK;
+  const bool fusable = heconv::ks_fwd_supported(ext->logN);
+  if (ext->tune.ks_fused == 1 && fusable) {
+    s = dev_err(heconv::modup_ntt_launch(ext->logN, ct, digits, n, L, ginv, ext->d_fwd, ext->d_lc, st));
+    if (!s) s = dev_err(heconv::inner_intt_launch(ext->logN, digits, ksk, acc, n, L, ext->d_inv, ext->d_lc, st));
+  } else {
+    if (ext->tune.ks_fused == 2 && fusable) {
+      s = dev_err(heconv::ks_fwd_launch(ext->logN, ct, ksk, acc, n, L, ginv, ext->d_fwd, ext->d_lc, st));
+    } else {
+      s = dev_err(heconv::modup_launch(ct, digits, n, N, L, ginv, ext->d_lc, st));
+      if (!s) s = dev_err(ntt_run(ext, false, digits, n * L, st));
+      if (!s) s = dev_err(heconv::ks_inner_launch(digits, ksk, acc, n, N, L, ext->d_lc, st));
+    }
+    if (!s) s = dev_err(ntt_run(ext, true, acc, 2 * n, st));
+  }
   if (!s) s = dev_err(heconv::moddown_launch(acc, ct, out, n, N, L, ginv, pc, ext->d_lc, st));
   return s;
 }
@@ -648,6 +659,28 @@ he_status he_keyswitch_work_words(const he_ctx* ext, uint64_t n, uint64_t* words
   const uint64_t L = ext->L - 1;
   *words = n * (L + 2) * (L + 1) * ext->N;
   return HE_OK;
+}
+
+he_status he_galois_key(const he_ctx* ext, uint64_t g, const int64_t* d_sk, const uint64_t* d_a, const int64_t* d_err,
+                        uint64_t* d_ksk_ntt, uint64_t* d_work, void* stream) {
+  if (check_ctx(ext)) return HE_EINVAL;
+  if (ext->L < 2) return HE_EPARAM;
+  if (!galois_ok(g, ext->N)) return HE_EINVAL;
+  if (!d_sk || !d_a || !d_err || !d_ksk_ntt || !d_work) return HE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t L = ext->L - 1, L1 = ext->L, N = ext->N;
+  const uint64_t LN1 = (uint64_t)L1 * N;
+  uint64_t* w_a = d_work;               // [L][L+1][N]
+  uint64_t* w_e = d_work + L * LN1;     // [L][L+1][N]
+  uint64_t* w_s = d_work + 2 * L * LN1;  // [L+1][N], then s(X^g)
+  he_status s = dev_err(hipMemcpyAsync(w_a, d_a, sizeof(uint64_t) * L * LN1, hipMemcpyDeviceToDevice, st));
+  for (uint32_t l = 0; l < L && !s; l++)
+    s = dev_err(heconv::key_lift_launch(d_err + (uint64_t)l * N, w_e + l * LN1, N, L1, ext->d_lc, st));
+  if (!s) s = dev_err(heconv::key_lift_launch(d_sk, w_s, N, L1, ext->d_lc, st));
+  if (!s) s = dev_err(heconv::automorph_launch(w_s, w_s + LN1, L1, N, L1, inv_mod_2n(g, N), ext->d_lc, st));
+  if (!s) s = dev_err(ntt_run(ext, false, d_work, 2 * L + 2, st));
+  if (!s) s = dev_err(heconv::galois_key_launch(d_work, d_ksk_ntt, N, L, ext->d_lc, st));
+  return s;
 }
 
 he_status he_automorph(const he_ctx* c, uint64_t g, uint64_t n, const uint64_t* d_in, uint64_t* d_out, void* stream) {

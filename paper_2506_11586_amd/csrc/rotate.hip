@@ -16,6 +16,7 @@
 // kernel is elementwise over the N coefficients of a row; the transforms
 // are the library's NTT kernels on the extended context.
 #include "kernels.h"
+#include "ntt_impl.h"
 
 namespace heconv {
 
@@ -126,6 +127,226 @@ __global__ __launch_bounds__(ROT_THREADS) void moddown_kernel(const uint64_t* __
   out[((i * 2 + 1) * L + j) * N + k] = csub(b + (c.q - y[1]), c.q);
 }
 
+// Digit extension, forward transform and inner product fused: one workgroup
+// per (ciphertext i, extended modulus m) runs the L digits one after the
+// other.  Digit l is read from the ciphertext's a row (the automorphism
+// applied through LDS: the row is staged with coalesced loads, then each
+// thread gathers its permuted entries), reduced mod p_m, transformed in
+// registers, and multiplied by the key's transformed rows; the two sums stay
+// in registers and only they are stored.  The L+1 workgroups of one
+// ciphertext run on the same XCD (block b runs on XCD b % 8), so they share
+// its a rows in that XCD's L2.  Grid: ceil(n/8)*8*(L+1) workgroups.
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) >> 3) void ks_fwd_kernel(const uint64_t* __restrict__ ct,
+                                                                   const uint64_t* __restrict__ ksk,
+                                                                   uint64_t* __restrict__ acc, uint64_t n, uint32_t L,
+                                                                   uint32_t ginv, const Tw* __restrict__ tw_all,
+                                                                   const LimbConst* __restrict__ ext) {
+  constexpr int LOGE = 3, E = 1 << LOGE, N = 1 << LOGN, T = N / E, TOP = LOGN - LOGE;
+  __shared__ uint64_t lds[N + N / 16];
+  const uint32_t L1 = L + 1;
+  const uint32_t xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+  const uint64_t i = (uint64_t)(slot / L1) * 8 + xcd;
+  const uint32_t m = slot % L1;
+  if (i >= n) return;  // the whole workgroup leaves before any barrier
+  const LimbConst c = ext[m];
+  uint64_t sa[E], sb[E];
+#pragma unroll
+  for (int k = 0; k < E; k++) sa[k] = sb[k] = 0;
+  for (uint32_t l = 0; l < L; l++) {
+    // The thread index and twiddle offset pass through an empty asm
+    // statement each digit, so that the address arithmetic and twiddle loads
+    // (the same for every digit) are redone instead of hoisted out of the
+    // loop, where they would stay live across it and spill.
+    int tid = threadIdx.x;
+    uint32_t off = m * N;
+    asm volatile("" : "+v"(tid), "+v"(off));
+    const Tw* tw = tw_all + __builtin_amdgcn_readfirstlane(off);
+    const uint64_t* row = ct + (i * 2 * L + l) * N;
+    uint64_t x[E];
+    if (ginv == 1) {
+#pragma unroll
+      for (int k = 0; k < E; k++) x[k] = row[tid + k * T];
+    } else {
+      const uint64_t ql = ext[l].q;
+      __syncthreads();  // the previous digit's last LDS reads are done
+#pragma unroll
+      for (int k = 0; k < E; k++) lds[lds_pad(tid + k * T)] = row[tid + k * T];
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < E; k++) {
+        const uint32_t src = (uint32_t)(((uint64_t)(tid + k * T) * ginv) & (2 * N - 1));
+        const uint64_t v = lds[lds_pad(src & (N - 1))];
+        x[k] = src >= (uint32_t)N && v ? ql - v : v;
+      }
+    }
+    if (m != l) {
+#pragma unroll
+      for (int k = 0; k < E; k++) x[k] = red_word(x[k], c);
+    }
+    fwd_rest<LOGN, LOGE, 0>(x, lds, tid, tw, c);
+#pragma unroll
+    for (int k = 0; k < E; k++) x[k] = csub_neg(csub_neg(x[k], c.neg2q), c.negq);
+    exchange<LOGE, 0, TOP>(lds, x, tid);  // entry tid + k*T, as the key rows are read
+    // the key loads are addressed from a value defined here, so they are
+    // issued after the transform rather than held in registers through it
+    int tk = tid;
+    asm volatile("" : "+v"(tk));
+    const uint64_t* ka = ksk + ((uint64_t)(l * 2) * L1 + m) * N;
+    const uint64_t* kb = ka + (uint64_t)L1 * N;
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+      uint64_t hi, lo;
+      mul_wide(x[k], ka[tk + k * T], hi, lo);
+      sa[k] = csub(sa[k] + reduce128(hi, lo, c), c.q);
+      mul_wide(x[k], kb[tk + k * T], hi, lo);
+      sb[k] = csub(sb[k] + reduce128(hi, lo, c), c.q);
+    }
+  }
+  const int tid = threadIdx.x;
+  uint64_t* oa = acc + ((i * 2) * L1 + m) * N;
+  uint64_t* ob = oa + (uint64_t)L1 * N;
+#pragma unroll
+  for (int k = 0; k < E; k++) {
+    oa[tid + k * T] = sa[k];
+    ob[tid + k * T] = sb[k];
+  }
+}
+
+// Digit extension fused into the forward transform: one workgroup per
+// (ciphertext i, digit l, extended modulus m) reads limb l of a (through the
+// automorphism, staged in LDS as in ks_fwd_kernel), reduces it mod p_m and
+// stores its transform to digits[i][l][m].  The L+1 workgroups that read one
+// a row run on the same XCD.  Grid: ceil(n*L/8)*8*(L+1) workgroups.
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) >> 3) void modup_ntt_kernel(const uint64_t* __restrict__ ct,
+                                                                      uint64_t* __restrict__ digits, uint64_t n,
+                                                                      uint32_t L, uint32_t ginv,
+                                                                      const Tw* __restrict__ tw_all,
+                                                                      const LimbConst* __restrict__ ext) {
+  constexpr int LOGE = 3, E = 1 << LOGE, N = 1 << LOGN, T = N / E, TOP = LOGN - LOGE;
+  __shared__ uint64_t lds[N + N / 16];
+  const uint32_t L1 = L + 1;
+  const uint32_t xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+  const uint64_t il = (uint64_t)(slot / L1) * 8 + xcd;  // (i, l)
+  const uint32_t m = slot % L1;
+  if (il >= n * L) return;  // the whole workgroup leaves before any barrier
+  const uint32_t l = (uint32_t)(il % L);
+  const uint64_t i = il / L;
+  const int tid = threadIdx.x;
+  const LimbConst c = ext[m];
+  const uint64_t* row = ct + (i * 2 * L + l) * N;
+  uint64_t x[E];
+  if (ginv == 1) {
+#pragma unroll
+    for (int k = 0; k < E; k++) x[k] = row[tid + k * T];
+  } else {
+    const uint64_t ql = ext[l].q;
+#pragma unroll
+    for (int k = 0; k < E; k++) lds[lds_pad(tid + k * T)] = row[tid + k * T];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+      const uint32_t src = (uint32_t)(((uint64_t)(tid + k * T) * ginv) & (2 * N - 1));
+      const uint64_t v = lds[lds_pad(src & (N - 1))];
+      x[k] = src >= (uint32_t)N && v ? ql - v : v;
+    }
+  }
+  if (m != l) {
+#pragma unroll
+    for (int k = 0; k < E; k++) x[k] = red_word(x[k], c);
+  }
+  fwd_rest<LOGN, LOGE, 0>(x, lds, tid, tw_all + (size_t)m * N, c);
+#pragma unroll
+  for (int k = 0; k < E; k++) x[k] = csub_neg(csub_neg(x[k], c.neg2q), c.negq);
+  exchange<LOGE, 0, TOP>(lds, x, tid);
+  uint64_t* out = digits + (il * L1 + m) * N;
+#pragma unroll
+  for (int k = 0; k < E; k++) out[tid + k * T] = x[k];
+}
+
+// Inner product fused into the inverse transform: one workgroup per
+// (ciphertext i, component c, extended modulus m) sums the L products of the
+// transformed digits with the key row (c, m) in 128 bits as it loads them,
+// reduces once, transforms back in registers and stores acc[i][c][m].  The
+// two workgroups that read the same digit rows run on the same XCD.  Grid:
+// ceil(n*(L+1)/8)*8*2 workgroups.
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) >> 3) void inner_intt_kernel(const uint64_t* __restrict__ digits,
+                                                                       const uint64_t* __restrict__ ksk,
+                                                                       uint64_t* __restrict__ acc, uint64_t n,
+                                                                       uint32_t L, const Tw* __restrict__ tw_all,
+                                                                       const LimbConst* __restrict__ ext) {
+  constexpr int LOGE = 3, E = 1 << LOGE, N = 1 << LOGN, T = N / E;
+  __shared__ uint64_t lds[N + N / 16];
+  const uint32_t L1 = L + 1;
+  const uint32_t xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+  const uint64_t im = (uint64_t)(slot / 2) * 8 + xcd;  // (i, m)
+  const uint32_t comp = slot % 2;
+  if (im >= n * L1) return;  // the whole workgroup leaves before any barrier
+  const uint32_t m = (uint32_t)(im % L1);
+  const uint64_t i = im / L1;
+  const int tid = threadIdx.x;
+  const LimbConst c = ext[m];
+  uint64_t hi[E], lo[E];
+#pragma unroll
+  for (int k = 0; k < E; k++) hi[k] = lo[k] = 0;
+  for (uint32_t l = 0; l < L; l++) {
+    // an opaque copy of the thread index each digit keeps the compiler from
+    // turning the loads into per-lane 64-bit pointers carried across the loop
+    int tk = tid;
+    asm volatile("" : "+v"(tk));
+    const uint64_t* d = digits + ((i * L + l) * L1 + m) * N;
+    const uint64_t* kr = ksk + ((uint64_t)(l * 2 + comp) * L1 + m) * N;
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+      uint64_t ph, pl;
+      mul_wide(d[tk + k * T], kr[tk + k * T], ph, pl);
+      lo[k] += pl;
+      hi[k] += ph + (lo[k] < pl);  // L <= 7 products below 2^120: no overflow
+    }
+  }
+  uint64_t x[E];
+#pragma unroll
+  for (int k = 0; k < E; k++) x[k] = reduce128(hi[k], lo[k], c);
+  ntt_inv_regs<LOGN, LOGE>(x, tw_all + (size_t)m * N, c, lds, tid);
+  uint64_t* out = acc + ((i * 2 + comp) * L1 + m) * N;
+#pragma unroll
+  for (int k = 0; k < E; k++) out[tid + k * T] = x[k];
+}
+
+// Galois key for digit l and extended modulus m, in NTT form:
+//   ksk[l][0][m] = a[l][m],
+//   ksk[l][1][m] = a[l][m]*s + e[l] + (m == l ? P mod q_l : 0) * s(X^g)  (mod p_m),
+// since G_l = P * Qhat_l * (Qhat_l^-1 mod q_l) is P mod q_l in limb l and 0
+// in every other limb (Qhat_l holds every other q, P is a factor).  Inputs
+// are the transforms: work = [a: L][e: L][s][s(X^g)] RNS polynomials of L+1
+// limbs.
+__global__ __launch_bounds__(ROT_THREADS) void galois_key_kernel(const uint64_t* __restrict__ work,
+                                                                  uint64_t* __restrict__ ksk, uint32_t N,
+                                                                  uint32_t L, const LimbConst* __restrict__ ext) {
+  const uint32_t per_row = N / ROT_THREADS;
+  const uint64_t row = blockIdx.x / per_row;  // (l, m)
+  const uint32_t k = (blockIdx.x % per_row) * ROT_THREADS + threadIdx.x;
+  const uint32_t L1 = L + 1;
+  const uint32_t m = (uint32_t)(row % L1), l = (uint32_t)(row / L1);
+  const LimbConst c = ext[m];
+  const uint64_t LN1 = (uint64_t)L1 * N;
+  const uint64_t a = work[row * N + k];
+  const uint64_t e = work[L * LN1 + row * N + k];
+  const uint64_t sv = work[2 * L * LN1 + (uint64_t)m * N + k];
+  uint64_t hi, lo;
+  mul_wide(a, sv, hi, lo);
+  uint64_t v = csub(reduce128(hi, lo, c) + e, c.q);
+  if (m == l) {
+    const uint64_t sg = work[(2 * L + 1) * LN1 + (uint64_t)m * N + k];
+    mul_wide(red_word(ext[L].q, c), sg, hi, lo);
+    v = csub(v + reduce128(hi, lo, c), c.q);
+  }
+  ksk[((uint64_t)(l * 2 + 0) * L1 + m) * N + k] = a;
+  ksk[((uint64_t)(l * 2 + 1) * L1 + m) * N + k] = v;
+}
+
 namespace {
 
 hipError_t rows_grid(uint64_t rows, uint32_t N, uint32_t& blocks) {
@@ -170,6 +391,64 @@ hipError_t moddown_launch(const uint64_t* acc, const uint64_t* ct, uint64_t* out
   if (hipError_t e = rows_grid(n * L, N, blocks)) return e;
   if (!blocks) return hipSuccess;
   hipLaunchKernelGGL(moddown_kernel, dim3(blocks), dim3(ROT_THREADS), 0, st, acc, ct, out, N, L, ginv, pinv, ext);
+  return hipGetLastError();
+}
+
+bool ks_fwd_supported(uint32_t logN) { return logN >= 10 && logN <= 13; }
+
+hipError_t ks_fwd_launch(uint32_t logN, const uint64_t* ct, const uint64_t* ksk, uint64_t* acc, uint64_t n, uint32_t L,
+                         uint32_t ginv, const Tw* tw, const LimbConst* ext, hipStream_t st) {
+  const uint64_t blocks = (n + 7) / 8 * 8 * (L + 1);
+  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (!blocks) return hipSuccess;
+  const dim3 grid((uint32_t)blocks);
+  switch (logN) {
+    case 10: hipLaunchKernelGGL(ks_fwd_kernel<10>, grid, dim3(128), 0, st, ct, ksk, acc, n, L, ginv, tw, ext); break;
+    case 11: hipLaunchKernelGGL(ks_fwd_kernel<11>, grid, dim3(256), 0, st, ct, ksk, acc, n, L, ginv, tw, ext); break;
+    case 12: hipLaunchKernelGGL(ks_fwd_kernel<12>, grid, dim3(512), 0, st, ct, ksk, acc, n, L, ginv, tw, ext); break;
+    case 13: hipLaunchKernelGGL(ks_fwd_kernel<13>, grid, dim3(1024), 0, st, ct, ksk, acc, n, L, ginv, tw, ext); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t modup_ntt_launch(uint32_t logN, const uint64_t* ct, uint64_t* digits, uint64_t n, uint32_t L, uint32_t ginv,
+                            const Tw* tw, const LimbConst* ext, hipStream_t st) {
+  const uint64_t blocks = (n * L + 7) / 8 * 8 * (L + 1);
+  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (!blocks) return hipSuccess;
+  const dim3 grid((uint32_t)blocks);
+  switch (logN) {
+    case 10: hipLaunchKernelGGL(modup_ntt_kernel<10>, grid, dim3(128), 0, st, ct, digits, n, L, ginv, tw, ext); break;
+    case 11: hipLaunchKernelGGL(modup_ntt_kernel<11>, grid, dim3(256), 0, st, ct, digits, n, L, ginv, tw, ext); break;
+    case 12: hipLaunchKernelGGL(modup_ntt_kernel<12>, grid, dim3(512), 0, st, ct, digits, n, L, ginv, tw, ext); break;
+    case 13: hipLaunchKernelGGL(modup_ntt_kernel<13>, grid, dim3(1024), 0, st, ct, digits, n, L, ginv, tw, ext); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t inner_intt_launch(uint32_t logN, const uint64_t* digits, const uint64_t* ksk, uint64_t* acc, uint64_t n,
+                             uint32_t L, const Tw* tw_inv, const LimbConst* ext, hipStream_t st) {
+  const uint64_t blocks = (n * (L + 1) + 7) / 8 * 8 * 2;
+  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (!blocks) return hipSuccess;
+  const dim3 grid((uint32_t)blocks);
+  switch (logN) {
+    case 10: hipLaunchKernelGGL(inner_intt_kernel<10>, grid, dim3(128), 0, st, digits, ksk, acc, n, L, tw_inv, ext); break;
+    case 11: hipLaunchKernelGGL(inner_intt_kernel<11>, grid, dim3(256), 0, st, digits, ksk, acc, n, L, tw_inv, ext); break;
+    case 12: hipLaunchKernelGGL(inner_intt_kernel<12>, grid, dim3(512), 0, st, digits, ksk, acc, n, L, tw_inv, ext); break;
+    case 13: hipLaunchKernelGGL(inner_intt_kernel<13>, grid, dim3(1024), 0, st, digits, ksk, acc, n, L, tw_inv, ext); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t galois_key_launch(const uint64_t* work, uint64_t* ksk, uint32_t N, uint32_t L, const LimbConst* ext,
+                             hipStream_t st) {
+  uint32_t blocks = 0;
+  if (hipError_t e = rows_grid((uint64_t)L * (L + 1), N, blocks)) return e;
+  hipLaunchKernelGGL(galois_key_kernel, dim3(blocks), dim3(ROT_THREADS), 0, st, work, ksk, N, L, ext);
   return hipGetLastError();
 }
 

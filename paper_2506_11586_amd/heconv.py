@@ -29,7 +29,7 @@ class Tuning(ctypes.Structure):
 
     _fields_ = [(n, ctypes.c_uint32) for n in ("ntt_loge_small", "ntt_loge_large", "ntt_small_below",
                                                "mac_mt", "mac_rt", "layer_fused", "layer_split",
-                                               "ntt_split_below", "ntt_fp64")]
+                                               "ntt_split_below", "ntt_fp64", "ks_fused")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -100,6 +100,7 @@ def _lib_handle():
         L.he_mask_extract.argtypes = [vp, P(ConvDesc), u32, vp, vp, vp, vp, vp]
         L.he_keyswitch_work_words.argtypes = [vp, u64, P(u64)]
         L.he_automorph.argtypes = [vp, u64, u64, vp, vp, vp]
+        L.he_galois_key.argtypes = [vp, u64, vp, vp, vp, vp, vp, vp]
         L.he_keyswitch.argtypes = [vp, u64, vp, vp, vp, vp, vp]
         L.he_rotate.argtypes = [vp, u64, u64, vp, vp, vp, vp, vp]
         L.he_batch_create.argtypes = [vp, P(_Job), u32, u32, P(vp)]
@@ -113,7 +114,7 @@ def _lib_handle():
         for name in ("he_gen_primes", "he_ctx_create", "he_ctx_psi", "he_ctx_get_tuning", "he_ctx_set_tuning", "he_plan_conv", "he_plan_conv_host", "he_min_root", "he_conv_sizes",
                      "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer",
                      "he_conv_mac_intt", "he_add_share", "he_mask_extract", "he_delta_host",
-                     "he_key_encode", "he_encrypt", "he_decrypt", "he_keyswitch_work_words", "he_automorph",
+                     "he_key_encode", "he_encrypt", "he_decrypt", "he_keyswitch_work_words", "he_automorph", "he_galois_key",
                      "he_keyswitch", "he_rotate"):
             getattr(L, name).restype = i32
         _LIB = L
@@ -346,6 +347,18 @@ class Context:
         w = ctypes.c_uint64()
         _check(lib().he_keyswitch_work_words(self._h, int(n), ctypes.byref(w)), "he_keyswitch_work_words")
         return int(w.value)
+
+    def galois_key_work_words(self) -> int:
+        """Scratch words of galois_key: (2L+2)*(L+1)*N for L = self.L - 1."""
+        return 2 * self.L * self.L * self.N
+
+    def galois_key(self, g: int, sk_dev, a_dev, err_dev, ksk_ntt_dev, work_dev, stream=None):
+        """he_galois_key (client side): the key for g in NTT form [L][2][L+1][N]."""
+        Lc, N = self.L - 1, self.N
+        _check(lib().he_galois_key(self._h, int(g), _ptr(sk_dev, N, "sk"), _ptr(a_dev, Lc * self.L * N, "a"),
+                                   _ptr(err_dev, Lc * N, "err"), _ptr(ksk_ntt_dev, Lc * 2 * self.L * N, "ksk"),
+                                   _ptr(work_dev, self.galois_key_work_words(), "work"), _stream(stream)),
+               "he_galois_key")
 
     def automorph(self, g: int, n: int, in_dev, out_dev, stream=None):
         """he_automorph: a(X) -> a(X^g) of n RNS polynomials [n][L][N]."""

@@ -59,11 +59,14 @@ def test_automorph_matches_oracle(N, L, bits, g):
     assert np.array_equal(to_host(out).reshape(n, L, N), oracle.automorphism(x, g, prm.q))
 
 
+@pytest.mark.parametrize("fused", [1, 2, 0])
 @pytest.mark.parametrize("N,L,bits", PARAMS)
-def test_keyswitch_matches_oracle(N, L, bits):
+def test_keyswitch_matches_oracle(N, L, bits, fused):
     """Arbitrary words as the ciphertext (every digit value range): the
-    output equals the oracle's exact CRT key switching word for word."""
+    output equals the oracle's exact CRT key switching word for word, with
+    the digit steps fused into one kernel and as separate steps."""
     _, ext, prm, P = contexts(N, L, bits)
+    ext.set_tuning(ks_fused=fused)
     n = 2 if N == 4096 else 1
     sk = wl.secret_key(71, N)
     ksk = make_key(prm, P, sk, 5, 72)
@@ -81,9 +84,11 @@ def test_keyswitch_matches_oracle(N, L, bits):
     assert np.array_equal(to_host(dct).reshape(want.shape), want)
 
 
+@pytest.mark.parametrize("fused", [1, 2, 0])
 @pytest.mark.parametrize("N,L,bits", PARAMS)
-def test_rotate_matches_oracle_and_decrypts(N, L, bits):
+def test_rotate_matches_oracle_and_decrypts(N, L, bits, fused):
     base, ext, prm, P = contexts(N, L, bits)
+    ext.set_tuning(ks_fused=fused)
     g = 3
     n = 2 if N == 4096 else 1
     sk = wl.secret_key(74, N)
@@ -106,32 +111,65 @@ def test_rotate_matches_oracle_and_decrypts(N, L, bits):
     assert np.array_equal(dec.cpu().numpy().reshape(n, N), oracle.centre_mod(m_rot.astype(object), prm.t).astype(np.int64))
 
 
-def test_rotate_equals_automorph_then_keyswitch():
-    """The fused rotation equals the two library steps run one after the
-    other, for several g (N=4096, L=2)."""
+@pytest.mark.parametrize("N,L,bits", PARAMS)
+def test_galois_key_matches_oracle_and_rotates(N, L, bits):
+    """The library's key generation equals the oracle's key in NTT form word
+    for word, and a rotation with it decrypts to m(X^g)."""
+    base, ext, prm, P = contexts(N, L, bits)
+    g, seed = 2 * N - 3, 90
+    eprm = oracle.ext_params(prm, P)
+    sk = wl.secret_key(seed, N)
+    a = synth.uniform_mod(Stream(seed, synth.UNIFORM), (L, L + 1, N), eprm.q)
+    e = Stream(seed, synth.ERROR).cbd(L * N, wl.ETA).reshape(L, N)
+    want = oracle.ntt(oracle.galois_key(sk, g, a, e, prm, P), eprm)
+    dk = empty_words(L * 2 * (L + 1) * N)
+    ext.galois_key(g, to_dev(np.asarray(sk, dtype=np.int64)), to_dev(a), to_dev(e.astype(np.int64)), dk,
+                   empty_words(ext.galois_key_work_words()))
+    assert np.array_equal(to_host(dk).reshape(want.shape), want)
+    n = 2
+    msgs = Stream(seed + 1, synth.INPUT).below(n * N, prm.t).reshape(n, N)
+    ct = wl.encrypt_polys(msgs, prm, seed + 1, sk)
+    out = empty_words(ct.size)
+    ext.rotate(g, n, to_dev(ct), dk, out, empty_words(ext.keyswitch_work_words(n)))
+    skn = empty_words(L * N)
+    base.key_encode(to_dev(np.asarray(sk, dtype=np.int64)), skn)
+    dec = empty_words(n * N)
+    base.decrypt(n, out, skn, dec, empty_words(n * L * N))
+    m_rot = oracle.automorphism(msgs.astype(np.uint64)[:, None, :], g, [prm.t])[:, 0, :]
+    assert np.array_equal(dec.cpu().numpy().reshape(n, N), oracle.centre_mod(m_rot.astype(object), prm.t).astype(np.int64))
+
+
+@pytest.mark.parametrize("fused", [1, 2, 0])
+def test_rotate_equals_automorph_then_keyswitch(fused):
+    """The rotation equals the two library steps run one after the other,
+    for several g (N=4096, L=2), with 4 and with 13 ciphertexts (a partial
+    group of eight in the fused kernel's XCD mapping)."""
     base, ext, prm, P = contexts(4096, 2, 50)
-    N, L, n = prm.N, prm.L, 4
+    ext.set_tuning(ks_fused=fused)
+    N, L = prm.N, prm.L
     sk = wl.secret_key(77, N)
     ksk = to_dev(make_key(prm, P, sk, 7, 78))  # any key: both paths use the same words
     ext.ntt_fwd(ksk, 2 * L)
-    ct = synth.uniform_mod(Stream(79, synth.UNIFORM), (n, 2, L, N), prm.q)
-    work = empty_words(ext.keyswitch_work_words(n))
-    for g in (3, 7, 2 * N - 1, 1):
-        fused = empty_words(ct.size)
-        ext.rotate(g, n, to_dev(ct), ksk, fused, work)
+    for n, g in ((4, 3), (4, 7), (4, 2 * N - 1), (4, 1), (13, 3), (13, 1)):
+        ct = synth.uniform_mod(Stream(79 + n, synth.UNIFORM), (n, 2, L, N), prm.q)
+        work = empty_words(ext.keyswitch_work_words(n))
+        one = empty_words(ct.size)
+        ext.rotate(g, n, to_dev(ct), ksk, one, work)
         rot = empty_words(ct.size)
         base.automorph(g, 2 * n, to_dev(ct), rot)
         two = empty_words(ct.size)
         ext.keyswitch(n, rot, ksk, two, work)
-        assert np.array_equal(to_host(fused), to_host(two)), g
+        assert np.array_equal(to_host(one), to_host(two)), (n, g)
 
 
 def test_rotate_full_size_batch():
     """N=8192, L=3 (60-bit q's and P), 64 ciphertexts in one call, the
     launch shape the bench times: every ciphertext decrypts to m(X^g) with
     the library's decryption, one sampled ciphertext equals the oracle word
-    for word, and each ciphertext's result does not depend on the batch."""
+    for word, and each ciphertext's result does not depend on the batch;
+    the unfused steps give the same words."""
     base, ext, prm, P = contexts(8192, 3, 60)
+    ext.set_tuning(ks_fused=1)
     N, L, n, g = prm.N, prm.L, 64, 5
     sk = wl.secret_key(80, N)
     ksk = make_key(prm, P, sk, g, 81)
@@ -157,6 +195,17 @@ def test_rotate_full_size_batch():
     one = empty_words(2 * L * N)
     ext.rotate(g, 1, to_dev(cts[i:i + 1]), dk, one, work)
     assert np.array_equal(to_host(one).reshape(1, 2, L, N), got[i:i + 1])
+    for mode in (2, 0):
+        ext.set_tuning(ks_fused=mode)
+        other = empty_words(ct.numel())
+        ext.rotate(g, n, ct, dk, other, work)
+        assert bool(torch_equal(other, out)), mode
+    ext.set_tuning(ks_fused=1)
+
+
+def torch_equal(a, b):
+    import torch
+    return torch.equal(a, b)
 
 
 def test_rotation_argument_errors_and_empty():
@@ -170,6 +219,9 @@ def test_rotation_argument_errors_and_empty():
     for g in (0, 2, 2 * N, 2 * N + 1):
         with pytest.raises(heconv.HeError) as e:
             base.automorph(g, 1, x, y)
+        assert e.value.status == heconv.HE_EINVAL
+        with pytest.raises(heconv.HeError) as e:
+            ext.galois_key(g, x, ksk, x, ksk, empty_words(ext.galois_key_work_words()))
         assert e.value.status == heconv.HE_EINVAL
         with pytest.raises(heconv.HeError) as e:
             ext.rotate(g, 1, x, ksk, y, work)
