@@ -440,7 +440,7 @@ def bfv_decode(v: np.ndarray, prm: Params, with_noise: bool = False):
     V = crt(v, prm)
     t, Q = prm.t, prm.Q
     m = ((t * V + Q // 2) // Q) % t
-    mc = np.where(m >= t // 2, m - t, m).astype(np.int64)
+    mc = np.where(2 * m >= t, m - t, m).astype(np.int64)
     if not with_noise:
         return mc
     noise = (V - prm.delta * (m % t)) % Q
@@ -507,7 +507,7 @@ def plain_conv(x: np.ndarray, K: np.ndarray, stride: int, pad: int) -> np.ndarra
 def centre_mod(y: np.ndarray, t: int) -> np.ndarray:
     """y mod t, centred into [-t/2, t/2)."""
     r = np.mod(y, t)
-    return np.where(r >= t // 2, r - t, r).astype(np.int64)
+    return np.where(2 * r >= t, r - t, r).astype(np.int64)
 
 
 # --------------------------------------------------------------------------

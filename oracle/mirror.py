@@ -58,7 +58,7 @@ def bfv_decrypt(ct: tuple[list[int], list[int]], sk: list[int], Q: int, t: int) 
     for k in range(len(a)):
         v = (b[k] - as_[k]) % Q
         m = ((t * v + Q // 2) // Q) % t
-        out.append(m - t if m >= t // 2 else m)
+        out.append(m - t if 2 * m >= t else m)
     return out
 
 

@@ -118,3 +118,21 @@ def test_cfg2_layer_decrypts_to_conv(prm8192):
     assert np.abs(want).max() < p.t // 2
     assert np.array_equal(y, want)
     assert bits < 100
+
+
+def test_odd_plaintext_modulus_centres_symmetrically(prm4096):
+    """For an odd t the centred range [-t/2, t/2) is -(t-1)/2 .. (t-1)/2:
+    (t-1)/2 stays positive and (t+1)/2 becomes -(t-1)/2, through decryption
+    and through centre_mod alike (t = 7 written out)."""
+    assert list(oracle.centre_mod(np.arange(7), 7)) == [0, 1, 2, 3, -3, -2, -1]
+    assert list(oracle.centre_mod(np.arange(8), 8)) == [0, 1, 2, 3, -4, -3, -2, -1]
+    N = prm4096.N
+    t = oracle.find_primes(N, 37, 1)[0]  # a prime plaintext modulus, t = 1 mod 2N
+    p = oracle.Params(N, prm4096.L, prm4096.bits, t, q=prm4096.q)
+    sk = wl.secret_key(10, N)
+    msgs = Stream(10, synth.INPUT).below(N, t).reshape(1, N)
+    msgs[0, :4] = [(t - 1) // 2, (t + 1) // 2, 0, t - 1]
+    dec = oracle.bfv_decrypt(wl.encrypt_polys(msgs, p, 10, sk), sk, p)
+    assert list(dec[0, :4]) == [(t - 1) // 2, -(t - 1) // 2, 0, -1]
+    m = msgs.astype(object)
+    assert np.array_equal(dec, np.where(2 * m >= t, m - t, m).astype(np.int64))
