@@ -19,6 +19,9 @@ Paper passages (SecONNds, arXiv 2506.11586):
                                      key switching with evaluation keys),
                                      Sec. 6.1 (iterative MAC + rotation);
                                      the key-switching method is a reading
+  Z_P slots and the multiply-
+  accumulate-rotate kernel .......... Sec. 6.1 (HE kernels); the slot order
+                                     and diagonal layout are readings
 The paper gives no formula for the packing, no HE parameters and no tiling
 rule; the readings used (packing layout, largest primes, smallest root,
 bytes-objective planner, round-half-up decode) are listed with the design
@@ -676,3 +679,129 @@ def key_switch(ct, ksk, prm: Params, P: int) -> np.ndarray:
 def rotate(ct, g: int, ksk, prm: Params, P: int) -> np.ndarray:
     """Automorphism of both components, then key switching back to s."""
     return key_switch(automorphism(_u64(ct), g, prm.q), ksk, prm, P)
+
+
+# --------------------------------------------------------------------------
+# Z_P variant: batched (SIMD) plaintext slots and the iterative
+# multiply-accumulate-rotate linear kernel (Sec. 6.1: the Z_P kernels
+# multiply the input by NTT-preprocessed weights, accumulate, and rotate the
+# accumulated result once per iteration; Sec. 2, HE operations).
+# --------------------------------------------------------------------------
+def _brv(i: int, logn: int) -> int:
+    return int(format(i, f"0{logn}b")[::-1], 2) if logn else 0
+
+
+def simd_exponents(N: int) -> np.ndarray:
+    """Odd exponent e_s of slot s: a plaintext m in Z_t[X]/(X^N+1), t prime
+    with t = 1 mod 2N, holds in slot s the value m(zeta^e_s), zeta a
+    primitive 2N-th root of unity mod t.  Slot r*N/2 + j (row r < 2, column
+    j < N/2) takes e = 5^j mod 2N in row 0 and -5^j mod 2N in row 1: 5
+    generates a cyclic group of order N/2 in the odd residues mod 2N and -1
+    lies outside it, so every odd residue occurs once."""
+    h = N // 2
+    e = np.zeros(N, dtype=np.int64)
+    p = 1
+    for j in range(h):
+        e[j] = p
+        e[h + j] = (2 * N - p) % (2 * N)
+        p = p * 5 % (2 * N)
+    return e
+
+
+def _t_params(N: int, t: int) -> Params:
+    return Params(N, 1, max(int(t).bit_length(), 2), t, q=[int(t)])
+
+
+def simd_decode(m, t: int) -> np.ndarray:
+    """Slots of the plaintexts m [..., N] (coefficients mod t): the forward
+    NTT over the single prime t evaluates at psi^(2 brv(i) + 1) at index i,
+    psi the transforms' root of t; slot s reads the index i with
+    2 brv(i) + 1 = e_s."""
+    a = np.mod(np.asarray(m, dtype=object), t).astype(np.uint64)
+    N = a.shape[-1]
+    logn = N.bit_length() - 1
+    tp = _t_params(N, t)
+    ev = ntt(a.reshape(-1, 1, N), tp).reshape(a.shape)
+    idx = np.array([_brv(int((e - 1) // 2), logn) for e in simd_exponents(N)], dtype=np.int64)
+    return ev[..., idx]
+
+
+def simd_encode(v, t: int) -> np.ndarray:
+    """Plaintexts [..., N] (coefficients in [0, t)) whose slots are v [..., N]
+    (values mod t): the inverse of simd_decode."""
+    a = np.mod(np.asarray(v, dtype=object), t).astype(np.uint64)
+    N = a.shape[-1]
+    logn = N.bit_length() - 1
+    idx = np.array([_brv(int((e - 1) // 2), logn) for e in simd_exponents(N)], dtype=np.int64)
+    ev = np.zeros_like(a)
+    ev[..., idx] = a
+    return intt(ev.reshape(-1, 1, N), _t_params(N, t)).reshape(a.shape)
+
+
+def zp_diagonals(W: np.ndarray, n: int, N: int, t: int) -> np.ndarray:
+    """Slot vectors [n][N] of the weight matrix W [rows][cols] (rows, cols
+    <= n, n a power of two dividing N/2; zero padding to n x n): diagonal i
+    holds W[(k - i) mod n][k mod n] in slot k of each row (period n), the
+    factor that meets input x[k] in u_i = d_i * x before u_i is rotated
+    left by i."""
+    rows, cols = W.shape
+    Wp = np.zeros((n, n), dtype=object)
+    Wp[:rows, :cols] = np.mod(W.astype(object), t)
+    h = N // 2
+    k = np.arange(h) % n
+    out = np.zeros((n, N), dtype=object)
+    for i in range(n):
+        row = Wp[(k - i) % n, k]
+        out[i, :h] = row
+        out[i, h:] = row
+    return out
+
+
+def zp_input_slots(x: np.ndarray, n: int, N: int, t: int) -> np.ndarray:
+    """Slot vector [N] of the input x (length <= n): x repeated with period n
+    in both rows, so that a left rotation of a row by one slot is a cyclic
+    shift of x mod n."""
+    xp = np.zeros(n, dtype=object)
+    xp[:len(x)] = np.mod(np.asarray(x, dtype=object), t)
+    return np.tile(xp, N // n)
+
+
+def centred_lift(m, t: int) -> np.ndarray:
+    """Coefficients mod t as integers in [-t/2, t/2) (int64)."""
+    return centre_mod(np.asarray(m, dtype=object), t)
+
+
+def ct_mul_plain(ct, w, prm: Params) -> np.ndarray:
+    """ct [n][2][L][N] times the plaintext with integer coefficients w [N]
+    (lifted mod every q_l): both components multiplied in Z_q[X]/(X^N+1)."""
+    ct = _u64(ct).reshape(-1, 2, prm.L, prm.N)
+    out = np.zeros_like(ct)
+    w = np.asarray(w, dtype=object)
+    for l, q in enumerate(prm.q):
+        wl = np.mod(w, q).astype(np.uint64)
+        for i in range(ct.shape[0]):
+            for c in range(2):
+                out[i, c, l] = negacyclic_mul(ct[i, c, l], wl, q)
+    return out
+
+
+def ct_add(x, y, prm: Params) -> np.ndarray:
+    x = _u64(x)
+    y = _u64(y)
+    out = np.zeros_like(x)
+    for l, q in enumerate(prm.q):
+        out[..., l, :] = ((x[..., l, :].astype(object) + y[..., l, :].astype(object)) % q).astype(np.uint64)
+    return out
+
+
+def zp_matvec_ct(ct_x, diag_polys, g: int, ksk, prm: Params, P: int) -> np.ndarray:
+    """The iterative kernel on ciphertexts: acc = ct_x * d_{n-1}; then for
+    i = n-2 down to 0, acc = rotate(acc, g) + ct_x * d_i, with diag_polys
+    [n][N] the plaintexts of the diagonals (integer coefficients).  With
+    g = 5 (one slot left per rotation) the slots of the result hold
+    sum_i rot^i(d_i * x), i.e. W x."""
+    n = len(diag_polys)
+    acc = ct_mul_plain(ct_x, diag_polys[n - 1], prm)
+    for i in range(n - 2, -1, -1):
+        acc = ct_add(rotate(acc, g, ksk, prm, P), ct_mul_plain(ct_x, diag_polys[i], prm), prm)
+    return acc
