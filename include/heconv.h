@@ -293,8 +293,10 @@ he_status he_encrypt(const he_ctx* ctx, uint64_t n, const int64_t* d_msgs, const
  * from fixed-point constants (128-bit fractions, total error below
  * L * 2^-68); it equals exact rounding whenever t*V/Q is not within that of
  * a half-integer, which holds for every ciphertext whose noise is below
- * delta/2 by a margin of a few units.  Needs t a power of two (HE_EPARAM
- * otherwise).  d_work: [n][L][N] scratch. */
+ * delta/2 by a margin of a few units.  Any t with 2 <= t < 2^62 (a power
+ * of two, or the prime plaintext modulus of the Z_P variant; for odd t the
+ * range is -(t-1)/2 .. (t-1)/2), HE_EPARAM otherwise.  d_work: [n][L][N]
+ * scratch. */
 he_status he_decrypt(const he_ctx* ctx, uint64_t n, const uint64_t* d_ct, const uint64_t* d_sk_ntt, int64_t* d_msgs,
                      uint64_t* d_work, void* stream);
 
@@ -352,6 +354,59 @@ he_status he_keyswitch(const he_ctx* ext, uint64_t n, const uint64_t* d_ct, cons
  * (d_ct == d_out is HE_EINVAL); g as for he_automorph. */
 he_status he_rotate(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_ct, const uint64_t* d_ksk_ntt,
                     uint64_t* d_out, uint64_t* d_work, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Z_P variant: batched plaintext slots over a prime t and the linear kernel
+ * (Sec. 6.1: each iteration multiplies the input by NTT-preprocessed
+ * weights, adds the product to the accumulated result and rotates it).
+ * Slots: with t prime, t = 1 mod 2N, a plaintext m in Z_t[X]/(X^N+1) holds
+ * in slot s = r*N/2 + j (row r < 2, column j < N/2) the value m(zeta^e),
+ * e = 5^j mod 2N in row 0 and -5^j mod 2N in row 1, zeta = psi of t (the
+ * transforms' root); X -> X^5 moves every row left by one slot.  Slot calls
+ * take a T-CONTEXT: he_ctx_create with the single prime t (L = 1); other
+ * contexts give HE_EPARAM.
+ * ------------------------------------------------------------------------ */
+
+/* Slots [n][N] (values in [0, t)) -> plaintext coefficients [n][N] as
+ * integers centred into [-t/2, t/2) (int64), ready for he_encrypt (which
+ * reduces them mod t) or he_zp_encode_plain.  d_slots != d_coeffs. */
+he_status he_simd_encode(const he_ctx* tctx, uint64_t n, const uint64_t* d_slots, int64_t* d_coeffs, void* stream);
+
+/* Plaintext coefficients [n][N] (any int64, e.g. he_decrypt's output) ->
+ * slots [n][N] in [0, t).  d_work: [n][N] scratch. */
+he_status he_simd_decode(const he_ctx* tctx, uint64_t n, const int64_t* d_coeffs, uint64_t* d_slots, uint64_t* d_work,
+                         void* stream);
+
+/* The n diagonals of the matrix W (int64 [rows][cols], row-major, rows,
+ * cols <= n, zero-padded to n x n) as slot vectors [n][N] mod t: diagonal i
+ * holds W[(k - i) mod n][k mod n] in slot k of each row.  n a power of two,
+ * n <= N/2 (HE_ESHAPE otherwise).  With the input x repeated with period n
+ * in the slots, sum_i rot^i(d_i * x) = W x in slots 0 .. rows-1. */
+he_status he_zp_diagonals(const he_ctx* tctx, const int64_t* d_w, uint32_t rows, uint32_t cols, uint32_t n,
+                          uint64_t* d_slots, void* stream);
+
+/* Weight plaintexts for he_zp_matvec: coefficients [n][N] (centred int64,
+ * from he_simd_encode) lifted to the L ciphertext primes of the EXTENDED
+ * context (q_0..q_{L-1}, P), multiplied by -P mod q_l and transformed:
+ * d_w [n][L][N] NTT form.  The factor -P lets the product enter key
+ * switching's sums before the division by P. */
+he_status he_zp_encode_plain(const he_ctx* ext, uint64_t n, const int64_t* d_coeffs, uint64_t* d_w, void* stream);
+
+/* Words of scratch he_zp_matvec needs for n ciphertexts:
+ * 2*n*2*L*N + n*(L+2)*(L+1)*N. */
+he_status he_zp_work_words(const he_ctx* ext, uint64_t n, uint64_t* words);
+
+/* The linear kernel on n input ciphertexts x (d_x_ntt: [n][2][L][N], NTT
+ * form, e.g. he_ntt_fwd on the base context): acc = x * w_{D-1}; then for
+ * i = D-2 down to 0, acc = rotate(acc, g) + x * w_i (D = n_diag, d_w from
+ * he_zp_encode_plain, d_ksk_ntt the Galois key for g as for he_rotate).
+ * Each iteration is one key switching whose inner product also takes the
+ * plaintext term, so the product is never stored.  d_out: [n][2][L][N]
+ * coefficient form (canonical).  With g = 5 and the diagonals of
+ * he_zp_diagonals the slots of the result hold W x.  N <= 2^13 (HE_EPARAM
+ * otherwise); d_work: he_zp_work_words words. */
+he_status he_zp_matvec(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_x_ntt, const uint64_t* d_w,
+                       uint32_t n_diag, const uint64_t* d_ksk_ntt, uint64_t* d_out, uint64_t* d_work, void* stream);
 
 /* ------------------------------------------------------------------------
  * Batch executor: many layer solves of uneven shape in one launch.

@@ -229,7 +229,13 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
   }
   // client-side decoding constants (power-of-two t only)
   std::vector<heconv::DecodeConst> dc(L);
-  c->decode_ok = c->proto_ok && pow2(c->t);
+  c->decode_ok = c->proto_ok && c->t >= 2 && c->t < (1ull << 62);
+  if (c->decode_ok) {
+    const uint64_t t = c->t;
+    c->tlc.q = t, c->tlc.two_q = 2 * t;
+    c->tlc.r64 = (uint64_t)(((u128)1 << 64) % t), c->tlc.r64_sh = shoup(c->tlc.r64, t);
+    c->tlc.mu64 = (uint64_t)(((u128)1 << 64) / t);
+  }
   for (uint32_t l = 0; l < L && c->decode_ok; l++) {
     const uint64_t q = c->q[l];
     uint64_t qh = 1;
@@ -587,7 +593,7 @@ he_status he_decrypt(const he_ctx* c, uint64_t n, const uint64_t* d_ct, const ui
     const uint64_t* ct = d_ct + i0 * 2 * LN;
     he_status s = key_product(c, m, ct, 2 * LN, nullptr, d_sk_ntt, d_work, st);
     if (!s)
-      s = dev_err(heconv::decrypt_finish_launch(ct, d_work, d_msgs + i0 * c->N, m, c->N, c->L, c->t, c->d_dc,
+      s = dev_err(heconv::decrypt_finish_launch(ct, d_work, d_msgs + i0 * c->N, m, c->N, c->L, c->tlc, c->d_dc,
                                                 c->d_lc, st));
     if (s) return s;
   }
@@ -636,7 +642,8 @@ he_status ks_run(const he_ctx* ext, uint32_t ginv, uint64_t n, const uint64_t* c
   const bool fusable = heconv::ks_fwd_supported(ext->logN);
   if (ext->tune.ks_fused == 1 && fusable) {
     s = dev_err(heconv::modup_ntt_launch(ext->logN, ct, digits, n, L, ginv, ext->d_fwd, ext->d_lc, st));
-    if (!s) s = dev_err(heconv::inner_intt_launch(ext->logN, digits, ksk, acc, n, L, ext->d_inv, ext->d_lc, st));
+    if (!s) s = dev_err(heconv::inner_intt_launch(ext->logN, digits, ksk, acc, n, L, L, nullptr, nullptr, ext->d_inv,
+                                                  ext->d_lc, st));
   } else {
     if (ext->tune.ks_fused == 2 && fusable) {
       s = dev_err(heconv::ks_fwd_launch(ext->logN, ct, ksk, acc, n, L, ginv, ext->d_fwd, ext->d_lc, st));
@@ -708,6 +715,124 @@ he_status he_rotate(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d
   if (n == 0) return HE_OK;
   if (!d_ct || !d_ksk_ntt || !d_out || !d_work || d_ct == d_out) return HE_EINVAL;
   return ks_run(ext, inv_mod_2n(g, ext->N), n, d_ct, d_ksk_ntt, d_out, d_work, (hipStream_t)stream);
+}
+
+// ---- Z_P variant: slots over a prime t, plaintexts, the linear kernel ----
+
+namespace {
+
+he_status t_ctx_check(const he_ctx* tc) {
+  if (check_ctx(tc)) return HE_EINVAL;
+  return tc->L == 1 ? HE_OK : HE_EPARAM;
+}
+
+}  // namespace
+
+he_status he_simd_encode(const he_ctx* tctx, uint64_t n, const uint64_t* d_slots, int64_t* d_coeffs, void* stream) {
+  if (he_status s = t_ctx_check(tctx)) return s;
+  if (n == 0) return HE_OK;
+  if (!d_slots || !d_coeffs || (const void*)d_slots == (const void*)d_coeffs) return HE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  uint64_t* out = reinterpret_cast<uint64_t*>(d_coeffs);
+  for (uint64_t i0 = 0; i0 < n; i0 += CLIENT_CHUNK) {
+    const uint64_t m = n - i0 < CLIENT_CHUNK ? n - i0 : CLIENT_CHUNK;
+    he_status s = dev_err(heconv::slot_permute_launch(d_slots + i0 * tctx->N, out + i0 * tctx->N, m, tctx->logN,
+                                                      true, st));
+    if (s) return s;
+  }
+  he_status s = dev_err(ntt_run(tctx, true, out, n, st));
+  if (!s) s = dev_err(heconv::centre_launch(out, n * tctx->N, tctx->q[0], st));
+  return s;
+}
+
+he_status he_simd_decode(const he_ctx* tctx, uint64_t n, const int64_t* d_coeffs, uint64_t* d_slots, uint64_t* d_work,
+                         void* stream) {
+  if (he_status s = t_ctx_check(tctx)) return s;
+  if (n == 0) return HE_OK;
+  if (!d_coeffs || !d_slots || !d_work || d_work == d_slots) return HE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  he_status s = dev_err(heconv::reduce_t_launch(d_coeffs, d_work, n * tctx->N, tctx->lc[0], st));
+  if (!s) s = dev_err(ntt_run(tctx, false, d_work, n, st));
+  for (uint64_t i0 = 0; i0 < n && !s; i0 += CLIENT_CHUNK) {
+    const uint64_t m = n - i0 < CLIENT_CHUNK ? n - i0 : CLIENT_CHUNK;
+    s = dev_err(heconv::slot_permute_launch(d_work + i0 * tctx->N, d_slots + i0 * tctx->N, m, tctx->logN, false, st));
+  }
+  return s;
+}
+
+he_status he_zp_diagonals(const he_ctx* tctx, const int64_t* d_w, uint32_t rows, uint32_t cols, uint32_t n,
+                          uint64_t* d_slots, void* stream) {
+  if (he_status s = t_ctx_check(tctx)) return s;
+  if (!pow2(n) || n > tctx->N / 2 || n > 65535 || rows == 0 || cols == 0 || rows > n || cols > n) return HE_ESHAPE;
+  if (!d_w || !d_slots) return HE_EINVAL;
+  return dev_err(heconv::diagonals_launch(d_w, rows, cols, n, tctx->N, d_slots, tctx->lc[0], (hipStream_t)stream));
+}
+
+he_status he_zp_encode_plain(const he_ctx* ext, uint64_t n, const int64_t* d_coeffs, uint64_t* d_w, void* stream) {
+  if (check_ctx(ext)) return HE_EINVAL;
+  if (ext->L < 2) return HE_EPARAM;
+  if (n == 0) return HE_OK;
+  if (!d_coeffs || !d_w) return HE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t L = ext->L - 1;
+  const uint64_t P = ext->q[L];
+  heconv::ScaleConst sc{};
+  for (uint32_t l = 0; l < L; l++) {
+    const uint64_t q = ext->q[l], pm = P % q;
+    sc.v[l] = pm ? q - pm : 0;
+    sc.sh[l] = shoup(sc.v[l], q);
+  }
+  for (uint64_t i0 = 0; i0 < n; i0 += CLIENT_CHUNK) {
+    const uint64_t m = n - i0 < CLIENT_CHUNK ? n - i0 : CLIENT_CHUNK;
+    he_status s = dev_err(heconv::lift_scaled_launch(d_coeffs + i0 * ext->N, d_w + i0 * L * ext->N, m, ext->N, L, sc,
+                                                     ext->d_lc, st));
+    if (s) return s;
+  }
+  return dev_err(heconv::ntt_launch(false, ext->logN, ntt_loge(ext, n), d_w, n, L, ext->d_fwd, ext->d_lc, st));
+}
+
+he_status he_zp_work_words(const he_ctx* ext, uint64_t n, uint64_t* words) {
+  if (!words) return HE_EINVAL;
+  if (he_status s = ks_check(ext, n)) return s;
+  const uint64_t L = ext->L - 1;
+  *words = 2 * n * 2 * L * ext->N + n * (L + 2) * (L + 1) * ext->N;
+  return HE_OK;
+}
+
+he_status he_zp_matvec(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_x_ntt, const uint64_t* d_w,
+                       uint32_t n_diag, const uint64_t* d_ksk_ntt, uint64_t* d_out, uint64_t* d_work, void* stream) {
+  if (he_status s = ks_check(ext, n)) return s;
+  if (!heconv::ks_fwd_supported(ext->logN)) return HE_EPARAM;
+  if (!galois_ok(g, ext->N) || n_diag == 0) return HE_EINVAL;
+  if (n == 0) return HE_OK;
+  if (!d_x_ntt || !d_w || !d_ksk_ntt || !d_out || !d_work) return HE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t L = ext->L - 1, N = ext->N, ginv = inv_mod_2n(g, N);
+  const uint64_t P = ext->q[L], ctw = n * 2 * L * N;
+  heconv::PinvConst pc{};
+  for (uint32_t j = 0; j < L; j++) {
+    const uint64_t q = ext->q[j];
+    pc.v[j] = mpow(P % q, q - 2, q);
+    pc.sh[j] = shoup(pc.v[j], q);
+  }
+  uint64_t* accb[2] = {d_work, d_work + ctw};
+  uint64_t* digits = d_work + 2 * ctw;                  // [n][L][L+1][N]
+  uint64_t* sums = digits + n * L * (uint64_t)(L + 1) * N;  // [n][2][L+1][N]
+  const uint64_t* prev = nullptr;                      // the accumulator (null: zero)
+  for (uint32_t step = 0; step < n_diag; step++) {
+    const uint32_t i = n_diag - 1 - step;
+    uint64_t* next = step + 1 == n_diag ? d_out : accb[step & 1];
+    const uint64_t* w = d_w + (uint64_t)i * L * N;
+    he_status s = HE_OK;
+    if (prev) s = dev_err(heconv::modup_ntt_launch(ext->logN, prev, digits, n, L, ginv, ext->d_fwd, ext->d_lc, st));
+    if (!s)
+      s = dev_err(heconv::inner_intt_launch(ext->logN, digits, d_ksk_ntt, sums, n, L, prev ? L : 0, d_x_ntt, w,
+                                            ext->d_inv, ext->d_lc, st));
+    if (!s) s = dev_err(heconv::moddown_launch(sums, prev, next, n, N, L, ginv, pc, ext->d_lc, st));
+    if (s) return s;
+    prev = next;
+  }
+  return HE_OK;
 }
 
 }  // extern "C"

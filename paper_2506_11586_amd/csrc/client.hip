@@ -10,8 +10,8 @@
 // integer k, so m = round(sum_l v_l * (I_l + F_l)) mod t with
 // I_l = floor(t*y_l/q_l) and F_l its fraction.  F_l is held as a 128-bit
 // fixed-point fraction (truncation error below L * 2^60 * 2^-128 in total);
-// t is a power of two, so the integer part is summed in wrapping 64-bit
-// arithmetic and masked.
+// the integer part is summed in 128 bits and reduced mod t at the end, so t
+// may be any modulus below 2^62 (a power of two or a prime).
 #include "kernels.h"
 
 namespace heconv {
@@ -86,20 +86,23 @@ __global__ __launch_bounds__(CLIENT_THREADS) void encrypt_finish_kernel(const ui
 __global__ __launch_bounds__(CLIENT_THREADS) void decrypt_finish_kernel(const uint64_t* __restrict__ ct,
                                                                          const uint64_t* __restrict__ as,
                                                                          int64_t* __restrict__ out, uint32_t N,
-                                                                         uint32_t L, uint64_t t,
+                                                                         uint32_t L, LimbConst tc,
                                                                          const DecodeConst* __restrict__ dcs,
                                                                          const LimbConst* __restrict__ lcs) {
   const uint64_t i = blockIdx.y;
   const uint32_t k = blockIdx.x * CLIENT_THREADS + threadIdx.x;
   if (k >= N) return;
-  uint64_t ipart = 0;            // sum v_l * I_l, mod 2^64
+  uint64_t ih = 0, il = 0;           // sum v_l * I_l as a 128-bit number (each term below 2^122, L <= 8)
   uint64_t w2 = 0, w1 = 0, w0 = 0;  // sum v_l * F_l * 2^128 as a 192-bit number
   for (uint32_t l = 0; l < L; l++) {
     const LimbConst c = lcs[l];
     const DecodeConst d = dcs[l];
     const uint64_t b = ct[((i * 2 + 1) * L + l) * N + k], a = as[(i * L + l) * N + k];
     const uint64_t v = csub(b + (c.q - a), c.q);
-    ipart += v * d.ipart;
+    uint64_t ph, pl;
+    mul_wide(v, d.ipart, ph, pl);
+    il += pl;
+    ih += ph + (il < pl);
     uint64_t h1, l1, h2, l2;
     mul_wide(v, d.frac_hi, h1, l1);  // v * F_hi: weight 2^64 in the 2^128 scale
     mul_wide(v, d.frac_lo, h2, l2);  // v * F_lo: weight 1
@@ -114,8 +117,12 @@ __global__ __launch_bounds__(CLIENT_THREADS) void decrypt_finish_kernel(const ui
     c1 += s1b < c0;
     w0 = s0, w1 = s1b, w2 += h1 + c1;
   }
-  const uint64_t m = (ipart + w2 + (w1 >> 63)) & (t - 1);
-  out[i * N + k] = m >= t / 2 ? (int64_t)m - (int64_t)t : (int64_t)m;
+  // integer part plus the rounded fraction sum, reduced mod t
+  const uint64_t r = w2 + (w1 >> 63);
+  il += r;
+  ih += il < r;
+  const uint64_t m = reduce128(ih, il, tc);
+  out[i * N + k] = m >= tc.q / 2 + (tc.q & 1) ? (int64_t)m - (int64_t)tc.q : (int64_t)m;
 }
 
 static dim3 grid_of(uint64_t words, uint64_t n) { return dim3((uint32_t)((words + CLIENT_THREADS - 1) / CLIENT_THREADS), (uint32_t)n); }
@@ -149,8 +156,9 @@ hipError_t encrypt_finish_launch(const uint64_t* as, const int64_t* msg, const i
 }
 
 hipError_t decrypt_finish_launch(const uint64_t* ct, const uint64_t* as, int64_t* out, uint64_t n, uint32_t N,
-                                 uint32_t L, uint64_t t, const DecodeConst* dc, const LimbConst* lc, hipStream_t st) {
-  hipLaunchKernelGGL(decrypt_finish_kernel, grid_of(N, n), dim3(CLIENT_THREADS), 0, st, ct, as, out, N, L, t, dc,
+                                 uint32_t L, const LimbConst& tc, const DecodeConst* dc, const LimbConst* lc,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(decrypt_finish_kernel, grid_of(N, n), dim3(CLIENT_THREADS), 0, st, ct, as, out, N, L, tc, dc,
                      lc);
   return hipGetLastError();
 }

@@ -45,9 +45,23 @@ hipError_t ks_fwd_launch(uint32_t logN, const uint64_t* ct, const uint64_t* ksk,
 hipError_t modup_ntt_launch(uint32_t logN, const uint64_t* ct, uint64_t* digits, uint64_t n, uint32_t L, uint32_t ginv,
                             const Tw* tw, const LimbConst* ext, hipStream_t st);
 hipError_t inner_intt_launch(uint32_t logN, const uint64_t* digits, const uint64_t* ksk, uint64_t* acc, uint64_t n,
-                             uint32_t L, const Tw* tw_inv, const LimbConst* ext, hipStream_t st);
+                             uint32_t L, uint32_t nd, const uint64_t* xp, const uint64_t* wp, const Tw* tw_inv,
+                             const LimbConst* ext, hipStream_t st);
 hipError_t galois_key_launch(const uint64_t* work, uint64_t* ksk, uint32_t N, uint32_t L, const LimbConst* ext,
                              hipStream_t st);
+
+// Z_P variant: slots, diagonals, scaled plaintext lift.
+struct ScaleConst {
+  uint64_t v[7], sh[7];  // a per-limb factor mod q_l and its Shoup quotient
+};
+hipError_t slot_permute_launch(const uint64_t* in, uint64_t* out, uint64_t n, uint32_t logN, bool encode,
+                               hipStream_t st);
+hipError_t centre_launch(uint64_t* v, uint64_t words, uint64_t t, hipStream_t st);
+hipError_t reduce_t_launch(const int64_t* in, uint64_t* out, uint64_t words, const LimbConst& tc, hipStream_t st);
+hipError_t diagonals_launch(const int64_t* W, uint32_t rows, uint32_t cols, uint32_t n, uint32_t N, uint64_t* slots,
+                            const LimbConst& tc, hipStream_t st);
+hipError_t lift_scaled_launch(const int64_t* c, uint64_t* out, uint64_t n, uint32_t N, uint32_t L,
+                              const ScaleConst& sc, const LimbConst* lc, hipStream_t st);
 
 // Geometry of a planned conv as the kernels need it.
 struct PackGeom {
@@ -107,6 +121,7 @@ hipError_t pointwise_key_launch(uint64_t* work, const uint64_t* sk_ntt, uint64_t
 hipError_t encrypt_finish_launch(const uint64_t* as, const int64_t* msg, const int64_t* err, uint64_t* ct, uint64_t n,
                                  uint32_t N, uint32_t L, uint64_t t, const LimbConst* lc, hipStream_t st);
 hipError_t decrypt_finish_launch(const uint64_t* ct, const uint64_t* as, int64_t* out, uint64_t n, uint32_t N,
-                                 uint32_t L, uint64_t t, const DecodeConst* dc, const LimbConst* lc, hipStream_t st);
+                                 uint32_t L, const LimbConst& tc, const DecodeConst* dc, const LimbConst* lc,
+                                 hipStream_t st);
 
 }  // namespace heconv

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(ROT_THREADS) void moddown_kernel(const uint64_t* __
     y[comp] = csub(mul_shoup_lazy(d, pinv.v[j], pinv.sh[j], c.q), c.q);
   }
   out[((i * 2 + 0) * L + j) * N + k] = y[0] ? c.q - y[0] : 0;
-  const uint64_t b = perm_load(ct + ((i * 2 + 1) * L + j) * N, k, ginv, N, c.q);
+  const uint64_t b = ct ? perm_load(ct + ((i * 2 + 1) * L + j) * N, k, ginv, N, c.q) : 0;  // null: a zero ciphertext
   out[((i * 2 + 1) * L + j) * N + k] = csub(b + (c.q - y[1]), c.q);
 }
 
@@ -271,11 +271,21 @@ __global__ __launch_bounds__((1 << LOGN) >> 3) void modup_ntt_kernel(const uint6
 // reduces once, transforms back in registers and stores acc[i][c][m].  The
 // two workgroups that read the same digit rows run on the same XCD.  Grid:
 // ceil(n*(L+1)/8)*8*2 workgroups.
+//
+// With a plaintext term (xp, wp non-null; the Z_P multiply-accumulate-rotate
+// step), the sum for a ciphertext modulus m < L also takes
+// xp[i][c][m] * wp[m]: the input ciphertext times a plaintext already
+// multiplied by -P mod q_m.  The term is 0 mod P, so the division by P in
+// moddown_kernel leaves the rotated ciphertext plus (x * plaintext) exactly.
+// nd digits are summed (L, or 0 when the rotated ciphertext is zero).
 template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) >> 3) void inner_intt_kernel(const uint64_t* __restrict__ digits,
                                                                        const uint64_t* __restrict__ ksk,
                                                                        uint64_t* __restrict__ acc, uint64_t n,
-                                                                       uint32_t L, const Tw* __restrict__ tw_all,
+                                                                       uint32_t L, uint32_t nd,
+                                                                       const uint64_t* __restrict__ xp,
+                                                                       const uint64_t* __restrict__ wp,
+                                                                       const Tw* __restrict__ tw_all,
                                                                        const LimbConst* __restrict__ ext) {
   constexpr int LOGE = 3, E = 1 << LOGE, N = 1 << LOGN, T = N / E;
   __shared__ uint64_t lds[N + N / 16];
@@ -291,19 +301,22 @@ __global__ __launch_bounds__((1 << LOGN) >> 3) void inner_intt_kernel(const uint
   uint64_t hi[E], lo[E];
 #pragma unroll
   for (int k = 0; k < E; k++) hi[k] = lo[k] = 0;
-  for (uint32_t l = 0; l < L; l++) {
-    // an opaque copy of the thread index each digit keeps the compiler from
+  // L <= 7 digit products and one plaintext product, each below 2^120: the
+  // 128-bit sums do not overflow
+  const bool plain = xp && m < L;
+  for (uint32_t l = 0; l < nd + (plain ? 1 : 0); l++) {
+    // an opaque copy of the thread index each term keeps the compiler from
     // turning the loads into per-lane 64-bit pointers carried across the loop
     int tk = tid;
     asm volatile("" : "+v"(tk));
-    const uint64_t* d = digits + ((i * L + l) * L1 + m) * N;
-    const uint64_t* kr = ksk + ((uint64_t)(l * 2 + comp) * L1 + m) * N;
+    const uint64_t* d = l < nd ? digits + ((i * L + l) * L1 + m) * N : xp + ((i * 2 + comp) * L + m) * N;
+    const uint64_t* kr = l < nd ? ksk + ((uint64_t)(l * 2 + comp) * L1 + m) * N : wp + (uint64_t)m * N;
 #pragma unroll
     for (int k = 0; k < E; k++) {
       uint64_t ph, pl;
       mul_wide(d[tk + k * T], kr[tk + k * T], ph, pl);
       lo[k] += pl;
-      hi[k] += ph + (lo[k] < pl);  // L <= 7 products below 2^120: no overflow
+      hi[k] += ph + (lo[k] < pl);
     }
   }
   uint64_t x[E];
@@ -429,16 +442,25 @@ hipError_t modup_ntt_launch(uint32_t logN, const uint64_t* ct, uint64_t* digits,
 }
 
 hipError_t inner_intt_launch(uint32_t logN, const uint64_t* digits, const uint64_t* ksk, uint64_t* acc, uint64_t n,
-                             uint32_t L, const Tw* tw_inv, const LimbConst* ext, hipStream_t st) {
+                             uint32_t L, uint32_t nd, const uint64_t* xp, const uint64_t* wp, const Tw* tw_inv,
+                             const LimbConst* ext, hipStream_t st) {
   const uint64_t blocks = (n * (L + 1) + 7) / 8 * 8 * 2;
   if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
   if (!blocks) return hipSuccess;
   const dim3 grid((uint32_t)blocks);
   switch (logN) {
-    case 10: hipLaunchKernelGGL(inner_intt_kernel<10>, grid, dim3(128), 0, st, digits, ksk, acc, n, L, tw_inv, ext); break;
-    case 11: hipLaunchKernelGGL(inner_intt_kernel<11>, grid, dim3(256), 0, st, digits, ksk, acc, n, L, tw_inv, ext); break;
-    case 12: hipLaunchKernelGGL(inner_intt_kernel<12>, grid, dim3(512), 0, st, digits, ksk, acc, n, L, tw_inv, ext); break;
-    case 13: hipLaunchKernelGGL(inner_intt_kernel<13>, grid, dim3(1024), 0, st, digits, ksk, acc, n, L, tw_inv, ext); break;
+    case 10:
+      hipLaunchKernelGGL(inner_intt_kernel<10>, grid, dim3(128), 0, st, digits, ksk, acc, n, L, nd, xp, wp, tw_inv, ext);
+      break;
+    case 11:
+      hipLaunchKernelGGL(inner_intt_kernel<11>, grid, dim3(256), 0, st, digits, ksk, acc, n, L, nd, xp, wp, tw_inv, ext);
+      break;
+    case 12:
+      hipLaunchKernelGGL(inner_intt_kernel<12>, grid, dim3(512), 0, st, digits, ksk, acc, n, L, nd, xp, wp, tw_inv, ext);
+      break;
+    case 13:
+      hipLaunchKernelGGL(inner_intt_kernel<13>, grid, dim3(1024), 0, st, digits, ksk, acc, n, L, nd, xp, wp, tw_inv, ext);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -103,6 +103,12 @@ def _lib_handle():
         L.he_galois_key.argtypes = [vp, u64, vp, vp, vp, vp, vp, vp]
         L.he_keyswitch.argtypes = [vp, u64, vp, vp, vp, vp, vp]
         L.he_rotate.argtypes = [vp, u64, u64, vp, vp, vp, vp, vp]
+        L.he_simd_encode.argtypes = [vp, u64, vp, vp, vp]
+        L.he_simd_decode.argtypes = [vp, u64, vp, vp, vp, vp]
+        L.he_zp_diagonals.argtypes = [vp, vp, u32, u32, u32, vp, vp]
+        L.he_zp_encode_plain.argtypes = [vp, u64, vp, vp, vp]
+        L.he_zp_work_words.argtypes = [vp, u64, P(u64)]
+        L.he_zp_matvec.argtypes = [vp, u64, u64, vp, vp, u32, vp, vp, vp, vp]
         L.he_batch_create.argtypes = [vp, P(_Job), u32, u32, P(vp)]
         L.he_batch_launch.argtypes = [vp, vp, i32]
         L.he_batch_status.argtypes = [vp, vp]
@@ -115,7 +121,8 @@ def _lib_handle():
                      "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer",
                      "he_conv_mac_intt", "he_add_share", "he_mask_extract", "he_delta_host",
                      "he_key_encode", "he_encrypt", "he_decrypt", "he_keyswitch_work_words", "he_automorph", "he_galois_key",
-                     "he_keyswitch", "he_rotate"):
+                     "he_keyswitch", "he_rotate", "he_simd_encode", "he_simd_decode", "he_zp_diagonals",
+                     "he_zp_encode_plain", "he_zp_work_words", "he_zp_matvec"):
             getattr(L, name).restype = i32
         _LIB = L
     return _LIB
@@ -383,6 +390,45 @@ class Context:
                                _ptr(ksk_ntt_dev, Lc * 2 * self.L * self.N, "ksk"), _ptr(out_dev, ct, "out"),
                                _ptr(work_dev, self.keyswitch_work_words(n), "work"), _stream(stream)),
                "he_rotate")
+
+    # ---- Z_P variant (slot calls on a one-prime context over t) ----
+
+    def simd_encode(self, n: int, slots_dev, coeffs_dev, stream=None):
+        """he_simd_encode: slots [n][N] -> centred plaintext coefficients [n][N]."""
+        _check(lib().he_simd_encode(self._h, int(n), _ptr(slots_dev, n * self.N, "slots"),
+                                    _ptr(coeffs_dev, n * self.N, "coeffs"), _stream(stream)), "he_simd_encode")
+
+    def simd_decode(self, n: int, coeffs_dev, slots_dev, work_dev, stream=None):
+        """he_simd_decode: plaintext coefficients [n][N] -> slots [n][N]."""
+        _check(lib().he_simd_decode(self._h, int(n), _ptr(coeffs_dev, n * self.N, "coeffs"),
+                                    _ptr(slots_dev, n * self.N, "slots"), _ptr(work_dev, n * self.N, "work"),
+                                    _stream(stream)), "he_simd_decode")
+
+    def zp_diagonals(self, w_dev, rows: int, cols: int, n: int, slots_dev, stream=None):
+        """he_zp_diagonals: W [rows][cols] -> n diagonal slot vectors [n][N]."""
+        _check(lib().he_zp_diagonals(self._h, _ptr(w_dev, rows * cols, "W"), int(rows), int(cols), int(n),
+                                     _ptr(slots_dev, n * self.N, "slots"), _stream(stream)), "he_zp_diagonals")
+
+    def zp_encode_plain(self, n: int, coeffs_dev, w_dev, stream=None):
+        """he_zp_encode_plain (extended context): coefficients [n][N] -> [n][L-1][N]."""
+        _check(lib().he_zp_encode_plain(self._h, int(n), _ptr(coeffs_dev, n * self.N, "coeffs"),
+                                        _ptr(w_dev, n * (self.L - 1) * self.N, "w"), _stream(stream)),
+               "he_zp_encode_plain")
+
+    def zp_work_words(self, n: int) -> int:
+        w = ctypes.c_uint64()
+        _check(lib().he_zp_work_words(self._h, int(n), ctypes.byref(w)), "he_zp_work_words")
+        return int(w.value)
+
+    def zp_matvec(self, g: int, n: int, x_ntt_dev, w_dev, n_diag: int, ksk_ntt_dev, out_dev, work_dev,
+                  stream=None):
+        """he_zp_matvec (extended context): the multiply-accumulate-rotate kernel."""
+        Lc, N = self.L - 1, self.N
+        ct = n * 2 * Lc * N
+        _check(lib().he_zp_matvec(self._h, int(g), int(n), _ptr(x_ntt_dev, ct, "x_ntt"),
+                                  _ptr(w_dev, n_diag * Lc * N, "w"), int(n_diag),
+                                  _ptr(ksk_ntt_dev, Lc * 2 * self.L * N, "ksk"), _ptr(out_dev, ct, "out"),
+                                  _ptr(work_dev, self.zp_work_words(n), "work"), _stream(stream)), "he_zp_matvec")
 
 
 class Batch:

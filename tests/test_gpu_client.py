@@ -122,12 +122,43 @@ def test_decrypt_arbitrary_words_matches_exact_rounding():
     assert np.array_equal(msgs.cpu().numpy().reshape(n, prm.N), oracle.bfv_decrypt(ct, sk, prm))
 
 
+@pytest.mark.parametrize("N,L,bits", [(4096, 2, 50), (8192, 3, 60)])
+@pytest.mark.parametrize("t", ["prime", 3])
+def test_odd_plaintext_modulus_roundtrip(N, L, bits, t):
+    """An odd t (the Z_P variant's prime, t = 1 mod 2N, or t = 3): encryption
+    word for word against the oracle; decryption of those encryptions and of
+    arbitrary words against the oracle's exact decoding, centred into
+    -(t-1)/2 .. (t-1)/2."""
+    if t == "prime":
+        t = oracle.find_primes(N, 37, 1)[0]
+    ctx, prm = ctx_and_prm(N, L, bits, t)
+    n = 2
+    sk = wl.secret_key(66, N)
+    msgs = Stream(66, synth.INPUT).below(n * N, t).reshape(n, N)
+    msgs[0, :2] = [(t - 1) // 2, (t + 1) // 2]
+    a = synth.uniform_mod(Stream(66, synth.UNIFORM), (n, L, N), prm.q)
+    e = Stream(66, synth.ERROR).cbd(n * N, wl.ETA).reshape(n, N)
+    want = oracle.bfv_encrypt(msgs, sk, a, e, prm)
+    skn = key_ntt(ctx, prm, sk)
+    ct, work = empty_words(n * 2 * L * N), empty_words(n * L * N)
+    ctx.encrypt(n, to_dev(msgs.astype(np.int64)), to_dev(a), to_dev(e), skn, ct, work)
+    assert np.array_equal(to_host(ct).reshape(want.shape), want)
+    out = empty_words(n * N)
+    ctx.decrypt(n, ct, skn, out, work)
+    dec = out.cpu().numpy().reshape(n, N)
+    assert np.array_equal(dec, oracle.centre_mod(msgs.astype(object), t))
+    assert list(dec[0, :2]) == [(t - 1) // 2, -((t - 1) // 2)]
+    rand = synth.uniform_mod(Stream(67, synth.UNIFORM), (n, 2, L, N), prm.q)
+    ctx.decrypt(n, to_dev(rand), skn, out, work)
+    assert np.array_equal(out.cpu().numpy().reshape(n, N), oracle.bfv_decrypt(rand, sk, prm))
+
+
 def test_client_errors():
     from paper_2506_11586_amd import heconv
-    ctx3, _ = ctx_and_prm(4096, 2, 50, t=3)  # t not a power of two: encryption works, decryption refuses
+    ctx1, _ = ctx_and_prm(4096, 2, 50, t=1)  # t = 1: delta = Q, no usable plaintext space
     L = heconv.lib()
-    assert L.he_decrypt(ctx3.handle, 1, None, None, None, None, None) == heconv.HE_EPARAM
-    assert L.he_encrypt(ctx3.handle, 0, None, None, None, None, None, None, None) == heconv.HE_OK
+    assert L.he_decrypt(ctx1.handle, 1, None, None, None, None, None) == heconv.HE_EPARAM
+    assert L.he_encrypt(ctx1.handle, 1, None, None, None, None, None, None, None) == heconv.HE_EPARAM
     ctx, _ = ctx_and_prm(4096, 2, 50)
     assert L.he_encrypt(ctx.handle, 1, None, None, None, None, None, None, None) == heconv.HE_EINVAL
     assert L.he_decrypt(ctx.handle, 0, None, None, None, None, None) == heconv.HE_OK
