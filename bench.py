@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-client", action="store_true", help="skip the client-side encrypt/decrypt section")
     ap.add_argument("--no-rotation", action="store_true", help="skip the ciphertext rotation section")
+    ap.add_argument("--no-zp", action="store_true", help="skip the Z_P linear-kernel section")
     ap.add_argument("--no-bottleneck", action="store_true",
                     help="skip the batch-16 bottleneck residual CNN section (about 230 GiB resident)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -241,6 +242,8 @@ def main():
         result["client"] = run_client(torch, heconv)
     if not args.no_rotation:
         result["rotation"] = run_rotation(torch, heconv)
+    if not args.no_zp:
+        result["zp_fc"] = run_zp(torch, heconv)
 
     if args.copy_probe:
         src = torch.ones(32 << 20, dtype=torch.int64, device="cuda")
@@ -538,6 +541,69 @@ def run_rotation(torch, heconv):
     return {"workload": f"{n} ciphertexts, N={N}, L={L} + one special prime, g={g}", "ms": ms,
             "rotations_per_s": n / ms * 1e3, "alg_bytes": alg, "GBps": alg / (ms * 1e-3) / 1e9,
             "decrypts_to_automorphism": exact}
+
+
+def run_zp(torch, heconv):
+    """The Z_P variant's linear kernel on a fully connected layer of
+    ResNet-50's classifier shape, 2048 -> 1000, 16 images in one call:
+    N=8192, L=3 (60-bit) plus a 60-bit special prime, t the largest 37-bit
+    prime = 1 mod 2N; 2048 diagonals, so 2048 iterations (2047 rotations of
+    16 ciphertexts each).  Inputs and weights are uniform mod t; four images
+    are decrypted and decoded on the GPU and checked against W x mod t."""
+    cfg = synth.WORKLOADS["conv64_56x56"]
+    N, L, bits = cfg["N"], cfg["L"], cfg["bits"]
+    rows, cols, B, g = 1000, 2048, 16, 5
+    n = cols
+    t = heconv.gen_primes(N, 37, 1)[0]  # the largest prime = 1 mod 2N below 2^37
+    primes = heconv.gen_primes(N, bits, L + 1)
+    base, ext, tctx = heconv.Context(N, primes[:L], t), heconv.Context(N, primes, t), heconv.Context(N, [t])
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(13)
+    dev = dict(dtype=torch.int64, device="cuda")
+    qx = torch.tensor(primes, **dev).view(1, L + 1, 1)
+    sk = torch.randint(-1, 2, (N,), generator=gen, **dev)
+    ka = torch.randint(0, 2 ** 62, (L, L + 1, N), generator=gen, **dev) % qx
+    ke = torch.randint(-21, 22, (L, N), generator=gen, **dev)
+    ksk = torch.empty(L * 2 * (L + 1) * N, **dev)
+    ext.galois_key(g, sk, ka.reshape(-1), ke.reshape(-1), ksk, torch.empty(ext.galois_key_work_words(), **dev))
+    # weights: diagonals -> slots -> plaintexts -> scaled NTT form (offline)
+    W = torch.randint(0, t, (rows, cols), generator=gen, **dev)
+    slots = torch.empty(n * N, **dev)
+    tctx.zp_diagonals(W.reshape(-1), rows, cols, n, slots)
+    coeffs = torch.empty(n * N, **dev)
+    tctx.simd_encode(n, slots, coeffs)
+    w = torch.empty(n * L * N, **dev)
+    ext.zp_encode_plain(n, coeffs, w)
+    del slots, coeffs
+    # inputs: x repeated with period 2048 in both slot rows, encoded, encrypted
+    x = torch.randint(0, t, (B, cols), generator=gen, **dev)
+    xs = x.repeat(1, N // cols).contiguous()
+    xc = torch.empty(B * N, **dev)
+    tctx.simd_encode(B, xs.reshape(-1), xc)
+    skn = torch.empty(L * N, **dev)
+    base.key_encode(sk, skn)
+    a = torch.randint(0, 2 ** 62, (B, L, N), generator=gen, **dev) % qx[:, :L]
+    err = torch.randint(-21, 22, (B, N), generator=gen, **dev)
+    ct = torch.empty(B * 2 * L * N, **dev)
+    base.encrypt(B, xc, a, err, skn, ct, torch.empty(B * L * N, **dev))
+    base.ntt_fwd(ct, 2 * B)
+    out = torch.empty_like(ct)
+    work = torch.empty(ext.zp_work_words(B), **dev)
+    ext.zp_matvec(g, B, ct, w, n, ksk, out, work)
+    dec = torch.empty(B * N, **dev)
+    base.decrypt(B, out, skn, dec, torch.empty(B * L * N, **dev))
+    ys = torch.empty(B * N, **dev)
+    tctx.simd_decode(B, dec, ys, torch.empty(B * N, **dev))
+    ys = ys.view(B, N)[:, :rows].cpu().numpy()
+    Wh, xh = W.cpu().numpy().astype(object), x.cpu().numpy().astype(object)
+    exact = all(np.array_equal(ys[b].astype(object), (Wh @ xh[b]) % t) for b in range(4))
+    ms = _timed(torch, lambda: ext.zp_matvec(g, B, ct, w, n, ksk, out, work), 3)
+    for c in (base, ext, tctx):
+        c.close()
+    return {"workload": f"FC {cols}->{rows}, {B} images, N={N}, L={L} + one special prime, t={t} (37-bit prime), "
+                        f"{n} diagonals", "ms": ms, "fc_layers_per_s": B / ms * 1e3,
+            "zp_macs_per_s": B * rows * cols / (ms * 1e-3), "rotations_per_s": B * (n - 1) / (ms * 1e-3),
+            "decrypts_to_Wx": exact}
 
 
 def run_serving(torch, heconv, args):
