@@ -545,14 +545,15 @@ def run_rotation(torch, heconv):
 
 def run_zp(torch, heconv):
     """The Z_P variant's linear kernel on a fully connected layer of
-    ResNet-50's classifier shape, 2048 -> 1000, 16 images in one call:
-    N=8192, L=3 (60-bit) plus a 60-bit special prime, t the largest 37-bit
-    prime = 1 mod 2N; 2048 diagonals, so 2048 iterations (2047 rotations of
-    16 ciphertexts each).  Inputs and weights are uniform mod t; four images
-    are decrypted and decoded on the GPU and checked against W x mod t."""
+    ResNet-50's classifier shape, 2048 -> 1000, at 16 and at 64 images per
+    call: N=8192, L=3 (60-bit) plus a 60-bit special prime, t the largest
+    37-bit prime = 1 mod 2N; 2048 diagonals, so 2048 iterations (2047
+    rotations of every ciphertext).  Inputs and weights are uniform mod t;
+    the first images of each batch are decrypted and decoded on the GPU and
+    checked against W x mod t."""
     cfg = synth.WORKLOADS["conv64_56x56"]
     N, L, bits = cfg["N"], cfg["L"], cfg["bits"]
-    rows, cols, B, g = 1000, 2048, 16, 5
+    rows, cols, g = 1000, 2048, 5
     n = cols
     t = heconv.gen_primes(N, 37, 1)[0]  # the largest prime = 1 mod 2N below 2^37
     primes = heconv.gen_primes(N, bits, L + 1)
@@ -566,6 +567,8 @@ def run_zp(torch, heconv):
     ke = torch.randint(-21, 22, (L, N), generator=gen, **dev)
     ksk = torch.empty(L * 2 * (L + 1) * N, **dev)
     ext.galois_key(g, sk, ka.reshape(-1), ke.reshape(-1), ksk, torch.empty(ext.galois_key_work_words(), **dev))
+    skn = torch.empty(L * N, **dev)
+    base.key_encode(sk, skn)
     # weights: diagonals -> slots -> plaintexts -> scaled NTT form (offline)
     W = torch.randint(0, t, (rows, cols), generator=gen, **dev)
     slots = torch.empty(n * N, **dev)
@@ -575,35 +578,39 @@ def run_zp(torch, heconv):
     w = torch.empty(n * L * N, **dev)
     ext.zp_encode_plain(n, coeffs, w)
     del slots, coeffs
-    # inputs: x repeated with period 2048 in both slot rows, encoded, encrypted
-    x = torch.randint(0, t, (B, cols), generator=gen, **dev)
-    xs = x.repeat(1, N // cols).contiguous()
-    xc = torch.empty(B * N, **dev)
-    tctx.simd_encode(B, xs.reshape(-1), xc)
-    skn = torch.empty(L * N, **dev)
-    base.key_encode(sk, skn)
-    a = torch.randint(0, 2 ** 62, (B, L, N), generator=gen, **dev) % qx[:, :L]
-    err = torch.randint(-21, 22, (B, N), generator=gen, **dev)
-    ct = torch.empty(B * 2 * L * N, **dev)
-    base.encrypt(B, xc, a, err, skn, ct, torch.empty(B * L * N, **dev))
-    base.ntt_fwd(ct, 2 * B)
-    out = torch.empty_like(ct)
-    work = torch.empty(ext.zp_work_words(B), **dev)
-    ext.zp_matvec(g, B, ct, w, n, ksk, out, work)
-    dec = torch.empty(B * N, **dev)
-    base.decrypt(B, out, skn, dec, torch.empty(B * L * N, **dev))
-    ys = torch.empty(B * N, **dev)
-    tctx.simd_decode(B, dec, ys, torch.empty(B * N, **dev))
-    ys = ys.view(B, N)[:, :rows].cpu().numpy()
-    Wh, xh = W.cpu().numpy().astype(object), x.cpu().numpy().astype(object)
-    exact = all(np.array_equal(ys[b].astype(object), (Wh @ xh[b]) % t) for b in range(4))
-    ms = _timed(torch, lambda: ext.zp_matvec(g, B, ct, w, n, ksk, out, work), 3)
+    Wh = W.cpu().numpy().astype(object)
+    res = {"workload": f"FC {cols}->{rows}, N={N}, L={L} + one special prime, t={t} (37-bit prime), "
+                       f"{n} diagonals", "by_batch": {}}
+    for B, checked in ((16, 4), (64, 2)):
+        # inputs: x repeated with period 2048 in both slot rows, encoded, encrypted
+        x = torch.randint(0, t, (B, cols), generator=gen, **dev)
+        xc = torch.empty(B * N, **dev)
+        tctx.simd_encode(B, x.repeat(1, N // cols).contiguous().reshape(-1), xc)
+        a = torch.randint(0, 2 ** 62, (B, L, N), generator=gen, **dev) % qx[:, :L]
+        err = torch.randint(-21, 22, (B, N), generator=gen, **dev)
+        ct = torch.empty(B * 2 * L * N, **dev)
+        base.encrypt(B, xc, a, err, skn, ct, torch.empty(B * L * N, **dev))
+        base.ntt_fwd(ct, 2 * B)
+        out = torch.empty_like(ct)
+        work = torch.empty(ext.zp_work_words(B), **dev)
+        ext.zp_matvec(g, B, ct, w, n, ksk, out, work)
+        dec = torch.empty(B * N, **dev)
+        base.decrypt(B, out, skn, dec, torch.empty(B * L * N, **dev))
+        ys = torch.empty(B * N, **dev)
+        tctx.simd_decode(B, dec, ys, torch.empty(B * N, **dev))
+        ys = ys.view(B, N)[:, :rows].cpu().numpy()
+        xh = x.cpu().numpy().astype(object)
+        exact = all(np.array_equal(ys[b].astype(object), (Wh @ xh[b]) % t) for b in range(checked))
+        ms = _timed(torch, lambda: ext.zp_matvec(g, B, ct, w, n, ksk, out, work), 3)
+        res["by_batch"][str(B)] = {"ms": ms, "fc_layers_per_s": B / ms * 1e3,
+                                   "zp_macs_per_s": B * rows * cols / (ms * 1e-3),
+                                   "ct_iterations_per_s": B * n / (ms * 1e-3),
+                                   "us_per_iteration": ms * 1e3 / n, "decrypts_to_Wx": exact,
+                                   "images_checked": checked}
+        del ct, out, work
     for c in (base, ext, tctx):
         c.close()
-    return {"workload": f"FC {cols}->{rows}, {B} images, N={N}, L={L} + one special prime, t={t} (37-bit prime), "
-                        f"{n} diagonals", "ms": ms, "fc_layers_per_s": B / ms * 1e3,
-            "zp_macs_per_s": B * rows * cols / (ms * 1e-3), "rotations_per_s": B * (n - 1) / (ms * 1e-3),
-            "decrypts_to_Wx": exact}
+    return res
 
 
 def run_serving(torch, heconv, args):

@@ -808,21 +808,26 @@ he_status he_zp_matvec(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t
   if (!d_x_ntt || !d_w || !d_ksk_ntt || !d_out || !d_work) return HE_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const uint32_t L = ext->L - 1, N = ext->N, ginv = inv_mod_2n(g, N);
-  const uint64_t P = ext->q[L], ctw = n * 2 * L * N;
+  const uint64_t P = ext->q[L], ctw = 2ull * L * N;  // words per ciphertext
   heconv::PinvConst pc{};
   for (uint32_t j = 0; j < L; j++) {
     const uint64_t q = ext->q[j];
     pc.v[j] = mpow(P % q, q - 2, q);
     pc.sh[j] = shoup(pc.v[j], q);
   }
-  uint64_t* accb[2] = {d_work, d_work + ctw};
-  uint64_t* digits = d_work + 2 * ctw;                  // [n][L][L+1][N]
-  uint64_t* sums = digits + n * L * (uint64_t)(L + 1) * N;  // [n][2][L+1][N]
-  const uint64_t* prev = nullptr;                      // the accumulator (null: zero)
+  // work: two accumulators of n ciphertexts, digits [n][L][L+1][N], sums
+  // [n][2][L+1][N].  The iterations depend on each other, so at a small
+  // batch each runs at one workgroup's transform latency; running the
+  // batch's two halves on two streams was measured slower (B = 16: 61.8
+  // against 50.8 us per iteration).
+  uint64_t* accb[2] = {d_work, d_work + n * ctw};
+  uint64_t* digits = d_work + 2 * n * ctw;
+  uint64_t* sums = digits + n * L * (uint64_t)(L + 1) * N;
+  const uint64_t* prev = nullptr;  // the accumulator (null: zero)
   for (uint32_t step = 0; step < n_diag; step++) {
     const uint32_t i = n_diag - 1 - step;
-    uint64_t* next = step + 1 == n_diag ? d_out : accb[step & 1];
     const uint64_t* w = d_w + (uint64_t)i * L * N;
+    uint64_t* next = step + 1 == n_diag ? d_out : accb[step & 1];
     he_status s = HE_OK;
     if (prev) s = dev_err(heconv::modup_ntt_launch(ext->logN, prev, digits, n, L, ginv, ext->d_fwd, ext->d_lc, st));
     if (!s)

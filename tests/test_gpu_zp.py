@@ -130,6 +130,7 @@ def decrypt_slots(base, tctx, prm, out, skn, B):
 
 
 @pytest.mark.parametrize("N,L,bits,tbits,rows,cols,n,B", [(4096, 2, 50, 20, 3, 4, 4, 2),
+                                                          (4096, 2, 50, 20, 5, 8, 8, 3),
                                                           (8192, 3, 60, 37, 2, 2, 2, 1)])
 def test_matvec_matches_oracle_word_for_word(N, L, bits, tbits, rows, cols, n, B):
     base, ext, tctx, prm, P, t = setup(N, L, bits, tbits)
