@@ -243,3 +243,25 @@ def test_rotation_argument_errors_and_empty():
     ext.keyswitch(0, x, ksk, y, work)
     ext.rotate(3, 0, x, ksk, y, work)
     assert bool((y == -1).all())
+
+
+@pytest.mark.parametrize("N,L,bits", [(2048, 7, 40), (1024, 2, 30), (16384, 2, 60)])
+def test_rotate_edge_rings_match_oracle(N, L, bits):
+    """The largest digit count (7 ciphertext primes plus P: 7 products and
+    their 128-bit sums), the smallest ring, and N=2^14 (where every mode
+    runs the separate steps): rotation word for word against the oracle."""
+    base, ext, prm, P = contexts(N, L, bits)
+    g = 2 * N - 3
+    sk = wl.secret_key(120, N)
+    ksk = make_key(prm, P, sk, g, 121)
+    ct = synth.uniform_mod(Stream(122, synth.UNIFORM), (1, 2, L, N), prm.q)
+    ct[0, 0, :, :2] = np.array(prm.q, dtype=np.uint64)[:, None] - 1
+    want = oracle.rotate(ct, g, ksk, prm, P)
+    dk = key_to_dev(ext, prm, ksk)
+    work = empty_words(ext.keyswitch_work_words(1))
+    for mode in (1, 2, 0):
+        ext.set_tuning(ks_fused=mode)
+        out = empty_words(ct.size)
+        ext.rotate(g, 1, to_dev(ct), dk, out, work)
+        assert np.array_equal(to_host(out).reshape(want.shape), want), mode
+    ext.set_tuning(ks_fused=1)

@@ -209,3 +209,19 @@ def test_zp_argument_errors():
     with pytest.raises(heconv.HeError) as e:
         ext.zp_matvec(4, 1, ct, w, 1, ksk, ct, work)
     assert e.value.status == heconv.HE_EINVAL
+
+
+def test_zp_matvec_needs_n_at_most_8192():
+    from paper_2506_11586_amd import heconv
+    require_gpu()
+    ensure_built()
+    N = 16384
+    primes = oracle.find_primes(N, 60, 3)
+    ext = heconv.Context(N, primes)
+    L = 2
+    ct = empty_words(2 * L * N)
+    with pytest.raises(heconv.HeError) as e:
+        ext.zp_matvec(5, 1, ct, empty_words(L * N), 1, empty_words(L * 2 * 3 * N), empty_words(2 * L * N),
+                      empty_words(ext.zp_work_words(1)))
+    assert e.value.status == heconv.HE_EPARAM
+    ext.close()
