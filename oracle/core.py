@@ -22,6 +22,9 @@ Paper passages (SecONNds, arXiv 2506.11586):
   Z_P slots and the multiply-
   accumulate-rotate kernel .......... Sec. 6.1 (HE kernels); the slot order
                                      and diagonal layout are readings
+  polyphase form of strided convs ... a restatement of the layer (the same
+                                     outputs, Sec. 9.1 on composite-op
+                                     overheads); pinned by the plain conv
 The paper gives no formula for the packing, no HE parameters and no tiling
 rule; the readings used (packing layout, largest primes, smallest root,
 bytes-objective planner, round-half-up decode) are listed with the design
@@ -805,3 +808,48 @@ def zp_matvec_ct(ct_x, diag_polys, g: int, ksk, prm: Params, P: int) -> np.ndarr
     for i in range(n - 2, -1, -1):
         acc = ct_add(rotate(acc, g, ksk, prm, P), ct_mul_plain(ct_x, diag_polys[i], prm), prm)
     return acc
+
+
+# --------------------------------------------------------------------------
+# Polyphase form of a strided convolution (a fusion variant: the same layer,
+# fewer output ciphertexts when the packing keeps a full window per
+# channel).  A stride-s conv equals a stride-1, pad-0 conv on s*s*C phase
+# channels with a ceil(k/s) kernel: with u = s*i + a, v = s*j + b,
+# xpad[c][s*y + u][s*x + v] = X_(c,a,b)[y + i][x + j].
+# --------------------------------------------------------------------------
+def polyphase_conv(cv: Conv) -> Conv:
+    """The stride-1, pad-0 conv on the phases of cv's padded input; its
+    first Ho x Wo outputs are cv's outputs (its output is never smaller)."""
+    s = cv.stride
+    assert s >= 2
+    return Conv(s * s * cv.C, -(-(cv.H + 2 * cv.pad) // s), -(-(cv.W + 2 * cv.pad) // s), cv.M,
+                -(-cv.kh // s), -(-cv.kw // s), 1, 0)
+
+
+def polyphase_input(x: np.ndarray, cv: Conv) -> np.ndarray:
+    """X[c*s*s + a*s + b][y][x'] = xpad[c][s*y + a][s*x' + b] (zero outside
+    the padded input); x [C][H][W] -> [s*s*C][H'][W']."""
+    s, pc = cv.stride, polyphase_conv(cv)
+    C, H, W = x.shape
+    xp = np.zeros((C, pc.H * s, pc.W * s), dtype=np.int64)
+    xp[:, cv.pad:cv.pad + H, cv.pad:cv.pad + W] = x
+    out = np.zeros((pc.C, pc.H, pc.W), dtype=np.int64)
+    for c in range(C):
+        for a in range(s):
+            for b in range(s):
+                out[c * s * s + a * s + b] = xp[c, a::s, b::s]
+    return out
+
+
+def polyphase_weights(K: np.ndarray, cv: Conv) -> np.ndarray:
+    """K'[m][c*s*s + a*s + b][i][j] = K[m][c][s*i + a][s*j + b] (zero where
+    s*i + a >= kh or s*j + b >= kw)."""
+    s, pc = cv.stride, polyphase_conv(cv)
+    M, C = K.shape[0], K.shape[1]
+    Kp = np.zeros((M, pc.C, pc.kh, pc.kw), dtype=K.dtype)
+    for c in range(C):
+        for a in range(s):
+            for b in range(s):
+                sub = K[:, c, a::s, b::s]
+                Kp[:, c * s * s + a * s + b, :sub.shape[1], :sub.shape[2]] = sub
+    return Kp
