@@ -409,6 +409,31 @@ he_status he_zp_matvec(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t
                        uint32_t n_diag, const uint64_t* d_ksk_ntt, uint64_t* d_out, uint64_t* d_work, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Polyphase form of a strided convolution (a fusion variant of the layer:
+ * the same outputs with fewer output ciphertexts when the packing keeps a
+ * whole window per channel).  A stride-s conv (s >= 2) equals a stride-1,
+ * pad-0 conv on s*s*C phase channels of the padded input, of size
+ * ceil((H+2pad)/s) x ceil((W+2pad)/s), with a ceil(kh/s) x ceil(kw/s)
+ * kernel; its first Ho x Wo outputs are the strided conv's (it may have a
+ * few more rows or columns, which the caller ignores).  Phase channel
+ * c*s*s + a*s + b holds xpad[c][s*y + a][s*x + b].  The layer itself runs
+ * through the ordinary calls on the polyphase descriptor.
+ * ------------------------------------------------------------------------ */
+
+/* The polyphase descriptor of a strided conv (packing fields zero: plan it
+ * with he_plan_conv).  HE_ESHAPE if stride < 2 or the shape is empty. */
+he_status he_polyphase_desc(const he_conv_desc* in, he_conv_desc* out);
+
+/* Weights int64 [M][C][kh][kw] of the strided conv -> the polyphase conv's
+ * [M][s*s*C][ceil(kh/s)][ceil(kw/s)]: Kp[m][c*s*s + a*s + b][i][j] =
+ * K[m][c][s*i + a][s*j + b], zero outside the kernel (device buffers). */
+he_status he_polyphase_weights(const he_conv_desc* desc, const int64_t* d_w, int64_t* d_wp, void* stream);
+
+/* Inputs int64 [B][C][H][W] (e.g. the server's input share) -> the phase
+ * channels [B][s*s*C][H'][W'], zero where the padded input is zero. */
+he_status he_polyphase_input(const he_conv_desc* desc, uint32_t B, const int64_t* d_x, int64_t* d_xp, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batch executor: many layer solves of uneven shape in one launch.
  * Each job is one he_conv_layer call's worth of work (same buffers, same
  * result).  A batch runs the forward NTT of every job's input limb

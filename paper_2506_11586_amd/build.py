@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libheconv.so")
-SOURCES = ["api.cpp", "batch_api.cpp", "ntt.hip", "mac.hip", "batch.hip", "fused.hip", "protocol.hip", "client.hip", "ntt_split.hip", "ntt_fp64.hip", "rotate.hip", "zp.hip"]
+SOURCES = ["api.cpp", "batch_api.cpp", "ntt.hip", "mac.hip", "batch.hip", "fused.hip", "protocol.hip", "client.hip", "ntt_split.hip", "ntt_fp64.hip", "rotate.hip", "zp.hip", "polyphase.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

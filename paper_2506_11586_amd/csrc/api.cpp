@@ -840,4 +840,45 @@ he_status he_zp_matvec(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t
   return HE_OK;
 }
 
+// ---- polyphase form of strided convolutions ----
+
+namespace {
+
+bool poly_geom(const he_conv_desc* d, heconv::PolyGeom& g) {
+  if (!d || d->stride < 2 || !d->C || !d->H || !d->W || !d->M || !d->kh || !d->kw) return false;
+  const uint64_t s = d->stride, Cp = s * s * d->C;
+  const uint64_t Hp = (d->H + 2ull * d->pad + s - 1) / s, Wp = (d->W + 2ull * d->pad + s - 1) / s;
+  const uint64_t khp = (d->kh + s - 1) / s, kwp = (d->kw + s - 1) / s;
+  if (Cp > 0xffffffffull || Hp < khp || Wp < kwp || d->H + 2ull * d->pad < d->kh || d->W + 2ull * d->pad < d->kw)
+    return false;
+  g = heconv::PolyGeom{d->C, d->H, d->W, d->M, d->kh, d->kw, d->stride, d->pad, (uint32_t)Cp, (uint32_t)Hp,
+                       (uint32_t)Wp, (uint32_t)khp, (uint32_t)kwp};
+  return true;
+}
+
+}  // namespace
+
+he_status he_polyphase_desc(const he_conv_desc* in, he_conv_desc* out) {
+  if (!in || !out) return HE_EINVAL;
+  heconv::PolyGeom g;
+  if (!poly_geom(in, g)) return HE_ESHAPE;
+  *out = he_conv_desc{g.Cp, g.Hp, g.Wp, g.M, g.khp, g.kwp, 1, 0, 0, 0, 0};
+  return HE_OK;
+}
+
+he_status he_polyphase_weights(const he_conv_desc* d, const int64_t* d_w, int64_t* d_wp, void* stream) {
+  heconv::PolyGeom g;
+  if (!poly_geom(d, g)) return HE_ESHAPE;
+  if (!d_w || !d_wp) return HE_EINVAL;
+  return dev_err(heconv::polyphase_weights_launch(d_w, d_wp, g, (hipStream_t)stream));
+}
+
+he_status he_polyphase_input(const he_conv_desc* d, uint32_t B, const int64_t* d_x, int64_t* d_xp, void* stream) {
+  heconv::PolyGeom g;
+  if (!poly_geom(d, g)) return HE_ESHAPE;
+  if (B == 0) return HE_OK;
+  if (!d_x || !d_xp) return HE_EINVAL;
+  return dev_err(heconv::polyphase_input_launch(d_x, d_xp, g, B, (hipStream_t)stream));
+}
+
 }  // extern "C"

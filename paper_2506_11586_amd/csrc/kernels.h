@@ -63,6 +63,14 @@ hipError_t diagonals_launch(const int64_t* W, uint32_t rows, uint32_t cols, uint
 hipError_t lift_scaled_launch(const int64_t* c, uint64_t* out, uint64_t n, uint32_t N, uint32_t L,
                               const ScaleConst& sc, const LimbConst* lc, hipStream_t st);
 
+// Polyphase form of a strided conv: the original (C, H, W, M, kh, kw, s,
+// pad) and the phase conv's channels, size and kernel.
+struct PolyGeom {
+  uint32_t C, H, W, M, kh, kw, s, pad, Cp, Hp, Wp, khp, kwp;
+};
+hipError_t polyphase_weights_launch(const int64_t* K, int64_t* Kp, const PolyGeom& g, hipStream_t st);
+hipError_t polyphase_input_launch(const int64_t* x, int64_t* X, const PolyGeom& g, uint64_t B, hipStream_t st);
+
 // Geometry of a planned conv as the kernels need it.
 struct PackGeom {
   uint32_t M, C, kh, kw, Cw, Hw, Ww, CB, L, N, O;

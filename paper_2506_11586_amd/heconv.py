@@ -109,6 +109,9 @@ def _lib_handle():
         L.he_zp_encode_plain.argtypes = [vp, u64, vp, vp, vp]
         L.he_zp_work_words.argtypes = [vp, u64, P(u64)]
         L.he_zp_matvec.argtypes = [vp, u64, u64, vp, vp, u32, vp, vp, vp, vp]
+        L.he_polyphase_desc.argtypes = [P(ConvDesc), P(ConvDesc)]
+        L.he_polyphase_weights.argtypes = [P(ConvDesc), vp, vp, vp]
+        L.he_polyphase_input.argtypes = [P(ConvDesc), u32, vp, vp, vp]
         L.he_batch_create.argtypes = [vp, P(_Job), u32, u32, P(vp)]
         L.he_batch_launch.argtypes = [vp, vp, i32]
         L.he_batch_status.argtypes = [vp, vp]
@@ -122,7 +125,8 @@ def _lib_handle():
                      "he_conv_mac_intt", "he_add_share", "he_mask_extract", "he_delta_host",
                      "he_key_encode", "he_encrypt", "he_decrypt", "he_keyswitch_work_words", "he_automorph", "he_galois_key",
                      "he_keyswitch", "he_rotate", "he_simd_encode", "he_simd_decode", "he_zp_diagonals",
-                     "he_zp_encode_plain", "he_zp_work_words", "he_zp_matvec"):
+                     "he_zp_encode_plain", "he_zp_work_words", "he_zp_matvec", "he_polyphase_desc",
+                     "he_polyphase_weights", "he_polyphase_input"):
             getattr(L, name).restype = i32
         _LIB = L
     return _LIB
@@ -198,6 +202,35 @@ class Sizes:
     in_cts: int
     out_cts: int
     w_words: int
+
+
+def polyphase_shape(shape) -> tuple:
+    """he_polyphase_desc: the stride-1, pad-0 conv shape on the phase
+    channels equal to the strided conv `shape` (C, H, W, M, kh, kw, stride, pad)."""
+    d_in = ConvDesc(*[int(v) for v in shape], 0, 0, 0)
+    d_out = ConvDesc()
+    _check(lib().he_polyphase_desc(ctypes.byref(d_in), ctypes.byref(d_out)), "he_polyphase_desc")
+    return d_out.shape()
+
+
+def polyphase_weights(shape, w_dev, wp_dev, stream=None):
+    """he_polyphase_weights: int64 [M][C][kh][kw] -> the polyphase conv's weights."""
+    C, H, W, M, kh, kw, s, pad = shape
+    pc = polyphase_shape(shape)
+    d = ConvDesc(*[int(v) for v in shape], 0, 0, 0)
+    _check(lib().he_polyphase_weights(ctypes.byref(d), _ptr(w_dev, M * C * kh * kw, "w"),
+                                      _ptr(wp_dev, pc[3] * pc[0] * pc[4] * pc[5], "wp"), _stream(stream)),
+           "he_polyphase_weights")
+
+
+def polyphase_input(shape, B: int, x_dev, xp_dev, stream=None):
+    """he_polyphase_input: int64 [B][C][H][W] -> the phase channels [B][s*s*C][H'][W']."""
+    C, H, W = shape[:3]
+    pc = polyphase_shape(shape)
+    d = ConvDesc(*[int(v) for v in shape], 0, 0, 0)
+    _check(lib().he_polyphase_input(ctypes.byref(d), int(B), _ptr(x_dev, B * C * H * W, "x"),
+                                    _ptr(xp_dev, B * pc[0] * pc[1] * pc[2], "xp"), _stream(stream)),
+           "he_polyphase_input")
 
 
 class Context:

@@ -96,3 +96,17 @@ def test_delta_rejects_unusable_t():
         with pytest.raises(heconv.HeError) as e:
             heconv.delta_host(q, t)
         assert e.value.status == heconv.HE_EPARAM
+
+
+def test_polyphase_descriptor_matches_oracle():
+    """he_polyphase_desc (host only) equals the oracle's polyphase conv for
+    strides 2 and 3 and several kernels; stride 1 is HE_ESHAPE."""
+    import oracle
+    from paper_2506_11586_amd import heconv
+    for shape in [(3, 224, 224, 64, 3, 3, 2, 1), (3, 224, 224, 64, 7, 7, 2, 3), (128, 56, 56, 128, 3, 3, 2, 1),
+                  (2, 9, 11, 3, 5, 5, 2, 2), (3, 17, 17, 2, 3, 3, 3, 1), (4, 12, 12, 2, 1, 1, 2, 0)]:
+        pc = oracle.polyphase_conv(oracle.Conv(*shape))
+        assert heconv.polyphase_shape(shape) == (pc.C, pc.H, pc.W, pc.M, pc.kh, pc.kw, pc.stride, pc.pad)
+    with pytest.raises(heconv.HeError) as e:
+        heconv.polyphase_shape((3, 16, 16, 4, 3, 3, 1, 1))
+    assert e.value.status == heconv.HE_ESHAPE
