@@ -232,6 +232,8 @@ def main():
 
     if not args.no_batched:
         result["batched"] = run_batched(torch, heconv)
+        result["batched_polyphase"] = run_batched(torch, heconv, polyphase=True)
+        result["stem_polyphase_b16"] = run_stem_polyphase(torch, heconv)
     if not args.no_bottleneck:
         torch.cuda.empty_cache()
         result["bottleneck_b16"] = run_bottleneck(torch, heconv)
@@ -277,23 +279,32 @@ def _timed(torch, fn, reps, warm=2, warm_s=0.1):
     return a.elapsed_time(b) / reps
 
 
-def run_batched(torch, heconv):
+def run_batched(torch, heconv, polyphase=False):
     """Fire-module CNN (26 convs at 224 input, B=1, N=8192, L=3): the 26 layer
     solves one after another through he_conv_layer (plain) vs one batch (two
     chains of three grids, one hipGraph launch).  Outputs compared word for
-    word."""
+    word.  With polyphase, the strided first layer runs as its polyphase
+    stride-1 layer (the same outputs, fewer output ciphertexts)."""
     cfg = synth.WORKLOADS["fire_cnn"]
     N, L, bits = cfg["N"], cfg["L"], cfg["bits"]
     ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), 2 ** synth.T_BITS)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64).copy()).cuda()
-    jobs, pristine, macs = [], [], 0
+    jobs, pristine, macs, out_cts = [], [], 0, 0
     for i, shape in enumerate(cfg["layers"]):
         C, H, W, M, kh, kw, stride, pad = shape
+        K = Stream(cfg["seed"] * 1000 + i, synth.WEIGHT).ints(M * C * kh * kw, *cfg["w_range"])
+        Kd = dev(K)
+        if polyphase and stride > 1 and kh > 1:
+            shape = heconv.polyphase_shape(shape)
+            Kp = torch.empty(shape[3] * shape[0] * shape[4] * shape[5], dtype=torch.int64, device="cuda")
+            heconv.polyphase_weights((C, H, W, M, kh, kw, stride, pad), Kd, Kp)
+            Kd = Kp
+            C, H, W, M, kh, kw, stride, pad = shape
         d = ctx.plan(shape)
         s = ctx.sizes(d)
-        K = Stream(cfg["seed"] * 1000 + i, synth.WEIGHT).ints(M * C * kh * kw, *cfg["w_range"])
         wntt = torch.empty(s.w_words, dtype=torch.int64, device="cuda")
-        ctx.encode_weights(d, dev(K), wntt)
+        ctx.encode_weights(d, Kd, wntt)
+        out_cts += s.out_cts
         x = synth.uniform_mod(Stream(cfg["seed"] * 1000 + i, synth.UNIFORM), (s.in_cts * 2, L, N), ctx.q)
         pristine.append(dev(x))
         jobs.append((d, 1, pristine[-1].clone(), wntt, torch.empty(s.out_cts * 2 * L * N, dtype=torch.int64,
@@ -318,12 +329,51 @@ def run_batched(torch, heconv):
     n = len(jobs)
     b.close()
     ctx.close()
-    return {"workload": cfg["name"], "layers": n, "ctpt_macs_per_pass": macs,
+    if polyphase:
+        return {"workload": cfg["name"] + ", first layer in polyphase form", "out_cts_per_pass": out_cts,
+                "ctpt_macs_per_pass": macs, "plain_ms": t_plain, "batched_ms": t_batch,
+                "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_batch * 1e3,
+                "bit_exact_vs_plain": bool(exact)}
+    return {"workload": cfg["name"], "layers": n, "ctpt_macs_per_pass": macs, "out_cts_per_pass": out_cts,
             "plain_ms": t_plain, "batched_ms": t_batch,
             "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_batch * 1e3,
             "plain_ctpt_macs_per_s": macs / t_plain * 1e3, "batched_ctpt_macs_per_s": macs / t_batch * 1e3,
             "speedup": t_plain / t_batch, "bit_exact_vs_plain": bool(exact),
             "batched_form": "two chains of three grids (forward NTTs, MAC tiles, inverse NTTs), one hipGraph"}
+
+
+def run_stem_polyphase(torch, heconv):
+    """The bottleneck CNN's stem (7x7 stride 2, 3 -> 64 at 224, batch 16) as
+    he_conv_layer on the strided layer (stride 1 + subsample) vs on its
+    polyphase stride-1 layer (12 phase channels, 4x4 kernel); inputs uniform
+    mod q_l (the kernels' work does not depend on the values)."""
+    cfg = synth.WORKLOADS["bottleneck_cnn_b16"]
+    N, L, bits, B = cfg["N"], cfg["L"], cfg["bits"], cfg["batch"]
+    ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), 2 ** synth.T_BITS)
+    shape = cfg["layers"][0]
+    assert shape[6] == 2 and shape[4] == 7
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(17)
+    qx = torch.tensor(ctx.q, dtype=torch.int64, device="cuda").view(1, L, 1)
+    res = {"workload": f"stem {shape}, batch {B}"}
+    for form in ("strided", "polyphase"):
+        lshape = heconv.polyphase_shape(shape) if form == "polyphase" else shape
+        d = ctx.plan(lshape, batch=B)
+        s = ctx.sizes(d)
+        C, H, W, M, kh, kw = lshape[:6]
+        K = torch.randint(-2 ** 12, 2 ** 12, (M * C * kh * kw,), generator=gen, dtype=torch.int64, device="cuda")
+        wntt = torch.empty(s.w_words, dtype=torch.int64, device="cuda")
+        ctx.encode_weights(d, K, wntt)
+        x = (torch.randint(0, 2 ** 62, (B * s.in_cts * 2, L, N), generator=gen, dtype=torch.int64,
+                           device="cuda") % qx).reshape(-1)
+        out = torch.empty(B * s.out_cts * 2 * L * N, dtype=torch.int64, device="cuda")
+        ms = _timed(torch, lambda: ctx.conv_layer(d, B, x, wntt, out), 5)
+        res[form] = {"ms": ms, "in_cts_per_image": s.in_cts, "out_cts_per_image": s.out_cts,
+                     "packing": [d.Cw, d.Hw, d.Ww]}
+        del x, out, wntt
+    res["speedup"] = res["strided"]["ms"] / res["polyphase"]["ms"]
+    ctx.close()
+    return res
 
 
 def run_bottleneck(torch, heconv):
