@@ -853,3 +853,20 @@ def polyphase_weights(K: np.ndarray, cv: Conv) -> np.ndarray:
                 sub = K[:, c, a::s, b::s]
                 Kp[:, c * s * s + a * s + b, :sub.shape[1], :sub.shape[2]] = sub
     return Kp
+
+
+def zp_matvec_grouped_ct(ct_x, diag_polys, G: int, g: int, ksk, g2: int, ksk2, prm: Params, P: int) -> np.ndarray:
+    """The same kernel as G independent chains: chain c runs the iteration
+    over diagonals c*n/G .. (c+1)*n/G - 1 (acc = x*d_last, then
+    acc = rotate(acc, g) + x*d_i), and the chains are combined by
+    acc = chain_{G-1}, then acc = rotate(acc, g2) + chain_c for c = G-2 .. 0,
+    g2 the Galois element of a rotation by n/G slots (5^(n/G) mod 2N).
+    The slots hold sum_c rot^(c n/G)(sum_i rot^i(d_(c n/G + i) * x)) = W x."""
+    n = len(diag_polys)
+    assert n % G == 0
+    h = n // G
+    chains = [zp_matvec_ct(ct_x, diag_polys[c * h:(c + 1) * h], g, ksk, prm, P) for c in range(G)]
+    acc = chains[G - 1]
+    for c in range(G - 2, -1, -1):
+        acc = ct_add(rotate(acc, g2, ksk2, prm, P), chains[c], prm)
+    return acc

@@ -103,3 +103,47 @@ def test_encrypted_kernel_decrypts_to_the_matrix_product():
     y = oracle.simd_decode(dec[0], t)
     assert np.array_equal(y[:3], (W.astype(object) @ x.astype(object)) % t)
     assert bits_used < prm.delta.bit_length() - 2
+
+
+def test_grouped_iteration_decrypts_to_the_matrix_product():
+    """The iteration as G = 2 chains of n/G diagonals combined by one
+    rotation by n/G slots (N=4096, 20-bit t, a 5 x 8 matrix at n = 8) also
+    decrypts to W x; on plain slot vectors the grouped schedule equals W x
+    for G = 1, 2, 4, 8."""
+    N, L, bits, n = 4096, 2, 50, 8
+    t = oracle.find_primes(N, 20, 1)[0]
+    W = Stream(150, synth.WEIGHT).below(40, t).reshape(5, 8)
+    x = Stream(150, synth.INPUT).below(8, t)
+    d = oracle.zp_diagonals(W, n, N, t)
+    xs = oracle.zp_input_slots(x, n, N, t)
+    h = N // 2
+    rot = lambda v, k: np.concatenate([np.roll(v[:h], -k), np.roll(v[h:], -k)])
+    want = (W.astype(object) @ x.astype(object)) % t
+    for G in (1, 2, 4, 8):
+        per = n // G
+        chains = []
+        for c in range(G):
+            acc = (d[c * per + per - 1] * xs) % t
+            for i in range(per - 2, -1, -1):
+                acc = (rot(acc, 1) + d[c * per + i] * xs) % t
+            chains.append(acc)
+        acc = chains[-1]
+        for c in range(G - 2, -1, -1):
+            acc = (rot(acc, per) + chains[c]) % t
+        assert np.array_equal(acc[:5], want), G
+    primes = oracle.find_primes(N, bits, L + 1)
+    prm = oracle.Params(N, L, bits, t, q=primes[:L])
+    P = primes[L]
+    ext = oracle.ext_params(prm, P)
+    sk = wl.secret_key(151, N)
+    keys = []
+    for gg, seed in ((5, 152), (pow(5, n // 2, 2 * N), 153)):
+        a = synth.uniform_mod(Stream(seed, synth.UNIFORM), (L, L + 1, N), ext.q)
+        e = Stream(seed, synth.ERROR).cbd(L * N, wl.ETA).reshape(L, N)
+        keys.append((gg, oracle.galois_key(sk, gg, a, e, prm, P)))
+    msg = oracle.simd_encode(xs, t).astype(np.uint64)
+    ct = wl.encrypt_polys(msg[None], prm, 154, sk)
+    diags = [oracle.centred_lift(oracle.simd_encode(dv, t), t) for dv in d]
+    out = oracle.zp_matvec_grouped_ct(ct, diags, 2, keys[0][0], keys[0][1], keys[1][0], keys[1][1], prm, P)
+    y = oracle.simd_decode(oracle.bfv_decrypt(out, sk, prm)[0], t)
+    assert np.array_equal(y[:5], want)
