@@ -408,6 +408,24 @@ he_status he_zp_work_words(const he_ctx* ext, uint64_t n, uint64_t* words);
 he_status he_zp_matvec(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_x_ntt, const uint64_t* d_w,
                        uint32_t n_diag, const uint64_t* d_ksk_ntt, uint64_t* d_out, uint64_t* d_work, void* stream);
 
+/* Words of scratch he_zp_matvec_grouped needs: as he_zp_work_words for
+ * groups*n ciphertexts. */
+he_status he_zp_grouped_work_words(const he_ctx* ext, uint64_t n, uint32_t groups, uint64_t* words);
+
+/* The same kernel scheduled as `groups` independent chains run as one
+ * batch of groups*n ciphertexts: chain c takes the diagonals
+ * c*per .. (c+1)*per - 1 (per = n_diag/groups) through the iteration above;
+ * then acc = chain_{G-1} and acc = rotate(acc, g2) + chain_c for
+ * c = G-2 .. 0, with g2 the Galois element of a rotation by per slots
+ * (5^per mod 2N) and d_ksk2_ntt its key.  The same number of rotations in
+ * per + groups - 1 dependent steps instead of n_diag, so a small batch
+ * fills more of the GPU; the slots hold the same W x (the ciphertext words
+ * differ from he_zp_matvec's).  n_diag % groups != 0 is HE_EINVAL; groups = 1
+ * is he_zp_matvec. */
+he_status he_zp_matvec_grouped(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_x_ntt, const uint64_t* d_w,
+                               uint32_t n_diag, uint32_t groups, const uint64_t* d_ksk_ntt, uint64_t g2,
+                               const uint64_t* d_ksk2_ntt, uint64_t* d_out, uint64_t* d_work, void* stream);
+
 /* ------------------------------------------------------------------------
  * Polyphase form of a strided convolution (a fusion variant of the layer:
  * the same outputs with fewer output ciphertexts when the packing keeps a

@@ -642,7 +642,7 @@ he_status ks_run(const he_ctx* ext, uint32_t ginv, uint64_t n, const uint64_t* c
   const bool fusable = heconv::ks_fwd_supported(ext->logN);
   if (ext->tune.ks_fused == 1 && fusable) {
     s = dev_err(heconv::modup_ntt_launch(ext->logN, ct, digits, n, L, ginv, ext->d_fwd, ext->d_lc, st));
-    if (!s) s = dev_err(heconv::inner_intt_launch(ext->logN, digits, ksk, acc, n, L, L, nullptr, nullptr, ext->d_inv,
+    if (!s) s = dev_err(heconv::inner_intt_launch(ext->logN, digits, ksk, acc, n, L, L, nullptr, nullptr, 0, 0, ext->d_inv,
                                                   ext->d_lc, st));
   } else {
     if (ext->tune.ks_fused == 2 && fusable) {
@@ -792,21 +792,26 @@ he_status he_zp_encode_plain(const he_ctx* ext, uint64_t n, const int64_t* d_coe
 }
 
 he_status he_zp_work_words(const he_ctx* ext, uint64_t n, uint64_t* words) {
-  if (!words) return HE_EINVAL;
-  if (he_status s = ks_check(ext, n)) return s;
-  const uint64_t L = ext->L - 1;
-  *words = 2 * n * 2 * L * ext->N + n * (L + 2) * (L + 1) * ext->N;
+  return he_zp_grouped_work_words(ext, n, 1, words);
+}
+
+he_status he_zp_grouped_work_words(const he_ctx* ext, uint64_t n, uint32_t groups, uint64_t* words) {
+  if (!words || groups == 0) return HE_EINVAL;
+  if (he_status s = ks_check(ext, n * groups)) return s;
+  const uint64_t L = ext->L - 1, nc = n * groups;
+  *words = 2 * nc * 2 * L * ext->N + nc * (L + 2) * (L + 1) * ext->N;
   return HE_OK;
 }
 
-he_status he_zp_matvec(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_x_ntt, const uint64_t* d_w,
-                       uint32_t n_diag, const uint64_t* d_ksk_ntt, uint64_t* d_out, uint64_t* d_work, void* stream) {
-  if (he_status s = ks_check(ext, n)) return s;
-  if (!heconv::ks_fwd_supported(ext->logN)) return HE_EPARAM;
-  if (!galois_ok(g, ext->N) || n_diag == 0) return HE_EINVAL;
-  if (n == 0) return HE_OK;
-  if (!d_x_ntt || !d_w || !d_ksk_ntt || !d_out || !d_work) return HE_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
+namespace {
+
+// The multiply-accumulate-rotate kernel as `groups` chains of n_diag/groups
+// iterations (chain c takes diagonals c*per .. (c+1)*per - 1), run as one
+// batch of groups*n ciphertexts, then acc = chain_{G-1} and
+// acc = rotate(acc, g2) + chain_c for c = G-2 .. 0.
+he_status zp_run(const he_ctx* ext, uint32_t g, uint64_t n, const uint64_t* d_x_ntt, const uint64_t* d_w,
+                 uint32_t n_diag, uint32_t groups, const uint64_t* ksk, uint32_t g2, const uint64_t* ksk2,
+                 uint64_t* d_out, uint64_t* d_work, hipStream_t st) {
   const uint32_t L = ext->L - 1, N = ext->N, ginv = inv_mod_2n(g, N);
   const uint64_t P = ext->q[L], ctw = 2ull * L * N;  // words per ciphertext
   heconv::PinvConst pc{};
@@ -815,29 +820,80 @@ he_status he_zp_matvec(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t
     pc.v[j] = mpow(P % q, q - 2, q);
     pc.sh[j] = shoup(pc.v[j], q);
   }
-  // work: two accumulators of n ciphertexts, digits [n][L][L+1][N], sums
-  // [n][2][L+1][N].  The iterations depend on each other, so at a small
+  const uint64_t nc = n * groups;
+  const uint32_t per = n_diag / groups;
+  // work: two accumulators of nc ciphertexts, digits [nc][L][L+1][N], sums
+  // [nc][2][L+1][N].  The iterations depend on each other, so at a small
   // batch each runs at one workgroup's transform latency; running the
   // batch's two halves on two streams was measured slower (B = 16: 61.8
-  // against 50.8 us per iteration).
-  uint64_t* accb[2] = {d_work, d_work + n * ctw};
-  uint64_t* digits = d_work + 2 * n * ctw;
-  uint64_t* sums = digits + n * L * (uint64_t)(L + 1) * N;
-  const uint64_t* prev = nullptr;  // the accumulator (null: zero)
-  for (uint32_t step = 0; step < n_diag; step++) {
-    const uint32_t i = n_diag - 1 - step;
-    const uint64_t* w = d_w + (uint64_t)i * L * N;
-    uint64_t* next = step + 1 == n_diag ? d_out : accb[step & 1];
+  // against 50.8 us per iteration), which is why chains are batched instead.
+  uint64_t* accb[2] = {d_work, d_work + nc * ctw};
+  uint64_t* digits = d_work + 2 * nc * ctw;
+  uint64_t* sums = digits + nc * L * (uint64_t)(L + 1) * N;
+  const uint64_t* prev = nullptr;  // the chains' accumulators (null: zero)
+  uint32_t cur = 0;
+  for (uint32_t step = 0; step < per; step++) {
+    const uint32_t i = per - 1 - step;
+    uint64_t* next = groups == 1 && step + 1 == per ? d_out : accb[cur];
     he_status s = HE_OK;
-    if (prev) s = dev_err(heconv::modup_ntt_launch(ext->logN, prev, digits, n, L, ginv, ext->d_fwd, ext->d_lc, st));
+    if (prev) s = dev_err(heconv::modup_ntt_launch(ext->logN, prev, digits, nc, L, ginv, ext->d_fwd, ext->d_lc, st));
     if (!s)
-      s = dev_err(heconv::inner_intt_launch(ext->logN, digits, d_ksk_ntt, sums, n, L, prev ? L : 0, d_x_ntt, w,
-                                            ext->d_inv, ext->d_lc, st));
-    if (!s) s = dev_err(heconv::moddown_launch(sums, prev, next, n, N, L, ginv, pc, ext->d_lc, st));
+      s = dev_err(heconv::inner_intt_launch(ext->logN, digits, ksk, sums, nc, L, prev ? L : 0, d_x_ntt,
+                                            d_w + (uint64_t)i * L * N, n, (uint64_t)per * L * N, ext->d_inv,
+                                            ext->d_lc, st));
+    if (!s) s = dev_err(heconv::moddown_launch(sums, prev, next, nc, N, L, ginv, pc, ext->d_lc, st));
     if (s) return s;
     prev = next;
+    cur ^= 1;
+  }
+  if (groups == 1) return HE_OK;
+  // combine the chains: the other accumulator buffer holds two n-ciphertext
+  // ping-pong slots (nc >= 2n)
+  const uint32_t g2inv = inv_mod_2n(g2, N);
+  uint64_t* tmp[2] = {accb[cur], accb[cur] + n * ctw};
+  const uint64_t* acc = prev + (uint64_t)(groups - 1) * n * ctw;
+  for (uint32_t c = groups - 1; c-- > 0;) {
+    uint64_t* next = c == 0 ? d_out : tmp[c & 1];
+    he_status s = dev_err(heconv::modup_ntt_launch(ext->logN, acc, digits, n, L, g2inv, ext->d_fwd, ext->d_lc, st));
+    if (!s)
+      s = dev_err(heconv::inner_intt_launch(ext->logN, digits, ksk2, sums, n, L, L, nullptr, nullptr, 0, 0,
+                                            ext->d_inv, ext->d_lc, st));
+    if (!s)
+      s = dev_err(heconv::moddown_launch(sums, acc, next, n, N, L, g2inv, pc, ext->d_lc, st,
+                                         prev + (uint64_t)c * n * ctw));
+    if (s) return s;
+    acc = next;
   }
   return HE_OK;
+}
+
+he_status zp_check(const he_ctx* ext, uint64_t g, uint64_t n, uint32_t n_diag, uint32_t groups) {
+  if (he_status s = ks_check(ext, n * (groups ? groups : 1))) return s;
+  if (!heconv::ks_fwd_supported(ext->logN)) return HE_EPARAM;
+  if (!galois_ok(g, ext->N) || n_diag == 0 || groups == 0 || n_diag % groups) return HE_EINVAL;
+  return HE_OK;
+}
+
+}  // namespace
+
+he_status he_zp_matvec(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_x_ntt, const uint64_t* d_w,
+                       uint32_t n_diag, const uint64_t* d_ksk_ntt, uint64_t* d_out, uint64_t* d_work, void* stream) {
+  if (he_status s = zp_check(ext, g, n, n_diag, 1)) return s;
+  if (n == 0) return HE_OK;
+  if (!d_x_ntt || !d_w || !d_ksk_ntt || !d_out || !d_work) return HE_EINVAL;
+  return zp_run(ext, (uint32_t)g, n, d_x_ntt, d_w, n_diag, 1, d_ksk_ntt, 1, nullptr, d_out, d_work,
+                (hipStream_t)stream);
+}
+
+he_status he_zp_matvec_grouped(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_x_ntt, const uint64_t* d_w,
+                               uint32_t n_diag, uint32_t groups, const uint64_t* d_ksk_ntt, uint64_t g2,
+                               const uint64_t* d_ksk2_ntt, uint64_t* d_out, uint64_t* d_work, void* stream) {
+  if (he_status s = zp_check(ext, g, n, n_diag, groups)) return s;
+  if (groups > 1 && !galois_ok(g2, ext->N)) return HE_EINVAL;
+  if (n == 0) return HE_OK;
+  if (!d_x_ntt || !d_w || !d_ksk_ntt || !d_out || !d_work || (groups > 1 && !d_ksk2_ntt)) return HE_EINVAL;
+  return zp_run(ext, (uint32_t)g, n, d_x_ntt, d_w, n_diag, groups, d_ksk_ntt, (uint32_t)g2, d_ksk2_ntt, d_out, d_work,
+                (hipStream_t)stream);
 }
 
 // ---- polyphase form of strided convolutions ----

@@ -38,15 +38,16 @@ hipError_t modup_launch(const uint64_t* ct, uint64_t* work, uint64_t n, uint32_t
 hipError_t ks_inner_launch(const uint64_t* work, const uint64_t* ksk, uint64_t* acc, uint64_t n, uint32_t N,
                            uint32_t L, const LimbConst* ext, hipStream_t st);
 hipError_t moddown_launch(const uint64_t* acc, const uint64_t* ct, uint64_t* out, uint64_t n, uint32_t N, uint32_t L,
-                          uint32_t ginv, const PinvConst& pinv, const LimbConst* ext, hipStream_t st);
+                          uint32_t ginv, const PinvConst& pinv, const LimbConst* ext, hipStream_t st,
+                          const uint64_t* addp = nullptr);
 bool ks_fwd_supported(uint32_t logN);
 hipError_t ks_fwd_launch(uint32_t logN, const uint64_t* ct, const uint64_t* ksk, uint64_t* acc, uint64_t n, uint32_t L,
                          uint32_t ginv, const Tw* tw, const LimbConst* ext, hipStream_t st);
 hipError_t modup_ntt_launch(uint32_t logN, const uint64_t* ct, uint64_t* digits, uint64_t n, uint32_t L, uint32_t ginv,
                             const Tw* tw, const LimbConst* ext, hipStream_t st);
 hipError_t inner_intt_launch(uint32_t logN, const uint64_t* digits, const uint64_t* ksk, uint64_t* acc, uint64_t n,
-                             uint32_t L, uint32_t nd, const uint64_t* xp, const uint64_t* wp, const Tw* tw_inv,
-                             const LimbConst* ext, hipStream_t st);
+                             uint32_t L, uint32_t nd, const uint64_t* xp, const uint64_t* wp, uint64_t chain_cts,
+                             uint64_t w_stride, const Tw* tw_inv, const LimbConst* ext, hipStream_t st);
 hipError_t galois_key_launch(const uint64_t* work, uint64_t* ksk, uint32_t N, uint32_t L, const LimbConst* ext,
                              hipStream_t st);
 

@@ -94,10 +94,12 @@ __global__ __launch_bounds__(ROT_THREADS) void ks_inner_kernel(const uint64_t* _
 }
 
 // out[i] = (-A', b(X^g) - B') with y = (x_j - ([x]_P mod q_j)) * P^-1 mod q_j
+// With addp non-null, the ciphertext addp[i] is added to the result.
 __global__ __launch_bounds__(ROT_THREADS) void moddown_kernel(const uint64_t* __restrict__ acc,
                                                                const uint64_t* __restrict__ ct,
                                                                uint64_t* __restrict__ out, uint32_t N, uint32_t L,
                                                                uint32_t ginv, PinvConst pinv,
+                                                               const uint64_t* __restrict__ addp,
                                                                const LimbConst* __restrict__ ext) {
   const uint32_t per_row = N / ROT_THREADS;
   const uint64_t row = blockIdx.x / per_row;  // (i, j), j < L
@@ -122,9 +124,14 @@ __global__ __launch_bounds__(ROT_THREADS) void moddown_kernel(const uint64_t* __
     const uint64_t d = csub(xj + (c.q - cm), c.q);
     y[comp] = csub(mul_shoup_lazy(d, pinv.v[j], pinv.sh[j], c.q), c.q);
   }
-  out[((i * 2 + 0) * L + j) * N + k] = y[0] ? c.q - y[0] : 0;
   const uint64_t b = ct ? perm_load(ct + ((i * 2 + 1) * L + j) * N, k, ginv, N, c.q) : 0;  // null: a zero ciphertext
-  out[((i * 2 + 1) * L + j) * N + k] = csub(b + (c.q - y[1]), c.q);
+  uint64_t oa = y[0] ? c.q - y[0] : 0, ob = csub(b + (c.q - y[1]), c.q);
+  if (addp) {
+    oa = csub(oa + addp[((i * 2 + 0) * L + j) * N + k], c.q);
+    ob = csub(ob + addp[((i * 2 + 1) * L + j) * N + k], c.q);
+  }
+  out[((i * 2 + 0) * L + j) * N + k] = oa;
+  out[((i * 2 + 1) * L + j) * N + k] = ob;
 }
 
 // Digit extension, forward transform and inner product fused: one workgroup
@@ -277,7 +284,10 @@ __global__ __launch_bounds__((1 << LOGN) >> 3) void modup_ntt_kernel(const uint6
 // xp[i][c][m] * wp[m]: the input ciphertext times a plaintext already
 // multiplied by -P mod q_m.  The term is 0 mod P, so the division by P in
 // moddown_kernel leaves the rotated ciphertext plus (x * plaintext) exactly.
-// nd digits are summed (L, or 0 when the rotated ciphertext is zero).
+// nd digits are summed (L, or 0 when the rotated ciphertext is zero).  The
+// batch may hold several chains of chain_cts ciphertexts that share the
+// input x but take different weights: ciphertext i uses x[i % chain_cts]
+// and the plaintext at wp + (i / chain_cts) * w_stride.
 template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) >> 3) void inner_intt_kernel(const uint64_t* __restrict__ digits,
                                                                        const uint64_t* __restrict__ ksk,
@@ -285,6 +295,7 @@ __global__ __launch_bounds__((1 << LOGN) >> 3) void inner_intt_kernel(const uint
                                                                        uint32_t L, uint32_t nd,
                                                                        const uint64_t* __restrict__ xp,
                                                                        const uint64_t* __restrict__ wp,
+                                                                       uint64_t chain_cts, uint64_t w_stride,
                                                                        const Tw* __restrict__ tw_all,
                                                                        const LimbConst* __restrict__ ext) {
   constexpr int LOGE = 3, E = 1 << LOGE, N = 1 << LOGN, T = N / E;
@@ -309,8 +320,10 @@ __global__ __launch_bounds__((1 << LOGN) >> 3) void inner_intt_kernel(const uint
     // turning the loads into per-lane 64-bit pointers carried across the loop
     int tk = tid;
     asm volatile("" : "+v"(tk));
-    const uint64_t* d = l < nd ? digits + ((i * L + l) * L1 + m) * N : xp + ((i * 2 + comp) * L + m) * N;
-    const uint64_t* kr = l < nd ? ksk + ((uint64_t)(l * 2 + comp) * L1 + m) * N : wp + (uint64_t)m * N;
+    const uint64_t* d =
+        l < nd ? digits + ((i * L + l) * L1 + m) * N : xp + (((i % chain_cts) * 2 + comp) * L + m) * N;
+    const uint64_t* kr =
+        l < nd ? ksk + ((uint64_t)(l * 2 + comp) * L1 + m) * N : wp + (i / chain_cts) * w_stride + (uint64_t)m * N;
 #pragma unroll
     for (int k = 0; k < E; k++) {
       uint64_t ph, pl;
@@ -399,11 +412,12 @@ hipError_t ks_inner_launch(const uint64_t* work, const uint64_t* ksk, uint64_t* 
 }
 
 hipError_t moddown_launch(const uint64_t* acc, const uint64_t* ct, uint64_t* out, uint64_t n, uint32_t N, uint32_t L,
-                          uint32_t ginv, const PinvConst& pinv, const LimbConst* ext, hipStream_t st) {
+                          uint32_t ginv, const PinvConst& pinv, const LimbConst* ext, hipStream_t st,
+                          const uint64_t* addp) {
   uint32_t blocks = 0;
   if (hipError_t e = rows_grid(n * L, N, blocks)) return e;
   if (!blocks) return hipSuccess;
-  hipLaunchKernelGGL(moddown_kernel, dim3(blocks), dim3(ROT_THREADS), 0, st, acc, ct, out, N, L, ginv, pinv, ext);
+  hipLaunchKernelGGL(moddown_kernel, dim3(blocks), dim3(ROT_THREADS), 0, st, acc, ct, out, N, L, ginv, pinv, addp, ext);
   return hipGetLastError();
 }
 
@@ -442,24 +456,29 @@ hipError_t modup_ntt_launch(uint32_t logN, const uint64_t* ct, uint64_t* digits,
 }
 
 hipError_t inner_intt_launch(uint32_t logN, const uint64_t* digits, const uint64_t* ksk, uint64_t* acc, uint64_t n,
-                             uint32_t L, uint32_t nd, const uint64_t* xp, const uint64_t* wp, const Tw* tw_inv,
-                             const LimbConst* ext, hipStream_t st) {
+                             uint32_t L, uint32_t nd, const uint64_t* xp, const uint64_t* wp, uint64_t chain_cts,
+                             uint64_t w_stride, const Tw* tw_inv, const LimbConst* ext, hipStream_t st) {
+  if (chain_cts == 0) chain_cts = n ? n : 1;
   const uint64_t blocks = (n * (L + 1) + 7) / 8 * 8 * 2;
   if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
   if (!blocks) return hipSuccess;
   const dim3 grid((uint32_t)blocks);
   switch (logN) {
     case 10:
-      hipLaunchKernelGGL(inner_intt_kernel<10>, grid, dim3(128), 0, st, digits, ksk, acc, n, L, nd, xp, wp, tw_inv, ext);
+      hipLaunchKernelGGL(inner_intt_kernel<10>, grid, dim3(128), 0, st, digits, ksk, acc, n, L, nd, xp, wp, chain_cts,
+                         w_stride, tw_inv, ext);
       break;
     case 11:
-      hipLaunchKernelGGL(inner_intt_kernel<11>, grid, dim3(256), 0, st, digits, ksk, acc, n, L, nd, xp, wp, tw_inv, ext);
+      hipLaunchKernelGGL(inner_intt_kernel<11>, grid, dim3(256), 0, st, digits, ksk, acc, n, L, nd, xp, wp, chain_cts,
+                         w_stride, tw_inv, ext);
       break;
     case 12:
-      hipLaunchKernelGGL(inner_intt_kernel<12>, grid, dim3(512), 0, st, digits, ksk, acc, n, L, nd, xp, wp, tw_inv, ext);
+      hipLaunchKernelGGL(inner_intt_kernel<12>, grid, dim3(512), 0, st, digits, ksk, acc, n, L, nd, xp, wp, chain_cts,
+                         w_stride, tw_inv, ext);
       break;
     case 13:
-      hipLaunchKernelGGL(inner_intt_kernel<13>, grid, dim3(1024), 0, st, digits, ksk, acc, n, L, nd, xp, wp, tw_inv, ext);
+      hipLaunchKernelGGL(inner_intt_kernel<13>, grid, dim3(1024), 0, st, digits, ksk, acc, n, L, nd, xp, wp, chain_cts,
+                         w_stride, tw_inv, ext);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -109,6 +109,8 @@ def _lib_handle():
         L.he_zp_encode_plain.argtypes = [vp, u64, vp, vp, vp]
         L.he_zp_work_words.argtypes = [vp, u64, P(u64)]
         L.he_zp_matvec.argtypes = [vp, u64, u64, vp, vp, u32, vp, vp, vp, vp]
+        L.he_zp_grouped_work_words.argtypes = [vp, u64, u32, P(u64)]
+        L.he_zp_matvec_grouped.argtypes = [vp, u64, u64, vp, vp, u32, u32, vp, u64, vp, vp, vp, vp]
         L.he_polyphase_desc.argtypes = [P(ConvDesc), P(ConvDesc)]
         L.he_polyphase_weights.argtypes = [P(ConvDesc), vp, vp, vp]
         L.he_polyphase_input.argtypes = [P(ConvDesc), u32, vp, vp, vp]
@@ -125,7 +127,8 @@ def _lib_handle():
                      "he_conv_mac_intt", "he_add_share", "he_mask_extract", "he_delta_host",
                      "he_key_encode", "he_encrypt", "he_decrypt", "he_keyswitch_work_words", "he_automorph", "he_galois_key",
                      "he_keyswitch", "he_rotate", "he_simd_encode", "he_simd_decode", "he_zp_diagonals",
-                     "he_zp_encode_plain", "he_zp_work_words", "he_zp_matvec", "he_polyphase_desc",
+                     "he_zp_encode_plain", "he_zp_work_words", "he_zp_matvec", "he_zp_grouped_work_words",
+                     "he_zp_matvec_grouped", "he_polyphase_desc",
                      "he_polyphase_weights", "he_polyphase_input"):
             getattr(L, name).restype = i32
         _LIB = L
@@ -462,6 +465,26 @@ class Context:
                                   _ptr(w_dev, n_diag * Lc * N, "w"), int(n_diag),
                                   _ptr(ksk_ntt_dev, Lc * 2 * self.L * N, "ksk"), _ptr(out_dev, ct, "out"),
                                   _ptr(work_dev, self.zp_work_words(n), "work"), _stream(stream)), "he_zp_matvec")
+
+    def zp_grouped_work_words(self, n: int, groups: int) -> int:
+        w = ctypes.c_uint64()
+        _check(lib().he_zp_grouped_work_words(self._h, int(n), int(groups), ctypes.byref(w)),
+               "he_zp_grouped_work_words")
+        return int(w.value)
+
+    def zp_matvec_grouped(self, g: int, n: int, x_ntt_dev, w_dev, n_diag: int, groups: int, ksk_ntt_dev, g2: int,
+                          ksk2_ntt_dev, out_dev, work_dev, stream=None):
+        """he_zp_matvec_grouped (extended context): the kernel as `groups` chains."""
+        Lc, N = self.L - 1, self.N
+        ct = n * 2 * Lc * N
+        kw = Lc * 2 * self.L * N
+        _check(lib().he_zp_matvec_grouped(self._h, int(g), int(n), _ptr(x_ntt_dev, ct, "x_ntt"),
+                                          _ptr(w_dev, n_diag * Lc * N, "w"), int(n_diag), int(groups),
+                                          _ptr(ksk_ntt_dev, kw, "ksk"), int(g2),
+                                          _ptr(ksk2_ntt_dev, kw, "ksk2") if ksk2_ntt_dev is not None else None,
+                                          _ptr(out_dev, ct, "out"),
+                                          _ptr(work_dev, self.zp_grouped_work_words(n, groups), "work"),
+                                          _stream(stream)), "he_zp_matvec_grouped")
 
 
 class Batch:

@@ -225,3 +225,62 @@ def test_zp_matvec_needs_n_at_most_8192():
                       empty_words(ext.zp_work_words(1)))
     assert e.value.status == heconv.HE_EPARAM
     ext.close()
+
+
+@pytest.mark.parametrize("G", [2, 4])
+def test_grouped_matvec_matches_oracle_word_for_word(G):
+    """The chains schedule (N=4096, 20-bit t, 5 x 8 matrix at n = 8, two
+    ciphertexts) against the oracle's grouped kernel word for word, and
+    decrypting to W x."""
+    base, ext, tctx, prm, P, t = setup(4096, 2, 50, 20)
+    N, L, n, B = prm.N, prm.L, 8, 2
+    sk = wl.secret_key(155, N)
+    eprm = oracle.ext_params(prm, P)
+    keys = []
+    for gg, seed in ((5, 156), (pow(5, n // G, 2 * N), 157)):
+        dk, _ = galois_key_dev(ext, prm, P, sk, gg, seed)
+        a = synth.uniform_mod(Stream(seed, synth.UNIFORM), (L, L + 1, N), eprm.q)
+        e = Stream(seed, synth.ERROR).cbd(L * N, wl.ETA).reshape(L, N)
+        keys.append((gg, dk, oracle.galois_key(sk, gg, a, e, prm, P)))
+    W = Stream(158, synth.WEIGHT).below(40, t).reshape(5, 8)
+    xv = Stream(159, synth.INPUT).below(B * 8, t).reshape(B, 8)
+    xs = np.stack([oracle.zp_input_slots(x, n, N, t) for x in xv]).astype(np.uint64)
+    ct, ct_ntt, skn = encrypted_inputs(base, tctx, prm, t, xs, sk, 160)
+    w, diag_coeffs = weights_dev(tctx, ext, prm, W, n)
+    out = empty_words(B * 2 * L * N)
+    ext.zp_matvec_grouped(5, B, ct_ntt, w, n, G, keys[0][1], keys[1][0], keys[1][1], out,
+                          empty_words(ext.zp_grouped_work_words(B, G)))
+    want = oracle.zp_matvec_grouped_ct(to_host(ct).reshape(B, 2, L, N), list(diag_coeffs), G, 5, keys[0][2],
+                                       keys[1][0], keys[1][2], prm, P)
+    assert np.array_equal(to_host(out).reshape(want.shape), want)
+    y = decrypt_slots(base, tctx, prm, out, skn, B)
+    for b in range(B):
+        assert np.array_equal(y[b, :5].astype(object), (W.astype(object) @ xv[b].astype(object)) % t)
+
+
+def test_grouped_fc_2048_to_1000_decrypts():
+    """N=8192, L=3, 37-bit t, the 1000 x 2048 matrix as 8 chains of 256
+    iterations combined by 7 rotations of 256 slots: every output decrypts
+    to W x mod t; groups = 1 gives he_zp_matvec's words."""
+    base, ext, tctx, prm, P, t = setup(8192, 3, 60, 37)
+    N, L, rows, cols, n, B, G = prm.N, prm.L, 1000, 2048, 2048, 3, 8
+    sk = wl.secret_key(161, N)
+    dk, _ = galois_key_dev(ext, prm, P, sk, 5, 162)
+    dk2, _ = galois_key_dev(ext, prm, P, sk, pow(5, n // G, 2 * N), 163)
+    W = Stream(164, synth.WEIGHT).below(rows * cols, t).reshape(rows, cols)
+    xv = Stream(165, synth.INPUT).below(B * cols, t).reshape(B, cols)
+    xs = np.stack([np.tile(x, N // cols) for x in xv]).astype(np.uint64)
+    ct, ct_ntt, skn = encrypted_inputs(base, tctx, prm, t, xs, sk, 166)
+    w, _ = weights_dev(tctx, ext, prm, W, n)
+    out = empty_words(B * 2 * L * N)
+    ext.zp_matvec_grouped(5, B, ct_ntt, w, n, G, dk, pow(5, n // G, 2 * N), dk2, out,
+                          empty_words(ext.zp_grouped_work_words(B, G)))
+    y = decrypt_slots(base, tctx, prm, out, skn, B)
+    Wo = W.astype(object)
+    for b in range(B):
+        assert np.array_equal(y[b, :rows].astype(object), (Wo @ xv[b].astype(object)) % t), b
+    one = empty_words(B * 2 * L * N)
+    two = empty_words(B * 2 * L * N)
+    ext.zp_matvec_grouped(5, B, ct_ntt, w, 64, 1, dk, 1, None, one, empty_words(ext.zp_grouped_work_words(B, 1)))
+    ext.zp_matvec(5, B, ct_ntt, w, 64, dk, two, empty_words(ext.zp_work_words(B)))
+    assert np.array_equal(to_host(one), to_host(two))
