@@ -629,6 +629,7 @@ def run_zp(torch, heconv):
     ext.zp_encode_plain(n, coeffs, w)
     del slots, coeffs
     Wh = W.cpu().numpy().astype(object)
+    keys2 = {}
     res = {"workload": f"FC {cols}->{rows}, N={N}, L={L} + one special prime, t={t} (37-bit prime), "
                        f"{n} diagonals", "by_batch": {}}
     for B, checked in ((16, 4), (64, 2)):
@@ -657,7 +658,32 @@ def run_zp(torch, heconv):
                                    "ct_iterations_per_s": B * n / (ms * 1e-3),
                                    "us_per_iteration": ms * 1e3 / n, "decrypts_to_Wx": exact,
                                    "images_checked": checked}
-        del ct, out, work
+        del work
+        # the same kernel as G chains batched together, combined by G - 1
+        # rotations of n/G slots (a second Galois key)
+        grouped = {}
+        for G in ((4, 8, 16) if B == 16 else (4,)):
+            g2 = pow(g, n // G, 2 * N)
+            if g2 not in keys2:
+                k2 = torch.empty_like(ksk)
+                ext.galois_key(g2, sk, ka.reshape(-1), ke.reshape(-1), k2,
+                               torch.empty(ext.galois_key_work_words(), **dev))
+                keys2[g2] = k2
+            workg = torch.empty(ext.zp_grouped_work_words(B, G), **dev)
+            run = lambda: ext.zp_matvec_grouped(g, B, ct, w, n, G, ksk, g2, keys2[g2], out, workg)
+            run()
+            base.decrypt(B, out, skn, dec, torch.empty(B * L * N, **dev))
+            ys2 = torch.empty(B * N, **dev)
+            tctx.simd_decode(B, dec, ys2, torch.empty(B * N, **dev))
+            yg = ys2.view(B, N)[:, :rows].cpu().numpy()
+            ok = all(np.array_equal(yg[b].astype(object), (Wh @ xh[b]) % t) for b in range(checked))
+            msg = _timed(torch, run, 3)
+            grouped[str(G)] = {"ms": msg, "fc_layers_per_s": B / msg * 1e3,
+                               "zp_macs_per_s": B * rows * cols / (msg * 1e-3), "dependent_steps": n // G + G - 1,
+                               "decrypts_to_Wx": ok}
+            del workg
+        res["by_batch"][str(B)]["grouped"] = grouped
+        del ct, out
     for c in (base, ext, tctx):
         c.close()
     return res
