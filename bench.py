@@ -234,9 +234,10 @@ def main():
         result["batched"] = run_batched(torch, heconv)
         result["batched_polyphase"] = run_batched(torch, heconv, polyphase=True)
         result["stem_polyphase_b16"] = run_stem_polyphase(torch, heconv)
+    bottleneck_pending = None
     if not args.no_bottleneck:
         torch.cuda.empty_cache()
-        result["bottleneck_b16"] = run_bottleneck(torch, heconv)
+        result["bottleneck_b16"], bottleneck_pending = run_bottleneck(torch, heconv)
         torch.cuda.empty_cache()
     if not args.no_serving:
         result["serving"] = run_serving(torch, heconv, args)
@@ -257,6 +258,10 @@ def main():
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"], result["bit_exact"] = cpu_baseline(args, cfg, ctx, d, sz, x_host, K_host, gpu_out)
+        if bottleneck_pending is not None:
+            n_s, ok = check_bottleneck_samples(bottleneck_pending)
+            result["bottleneck_b16"]["sampled_words_vs_oracle"] = n_s
+            result["bottleneck_b16"]["bit_exact"] = ok and result["bottleneck_b16"]["plain_equals_batched"]
     print(json.dumps(result), flush=True)
     ctx.close()
 
@@ -384,18 +389,15 @@ def run_bottleneck(torch, heconv):
     of three grids, one hipGraph).  Sampled output words of both are compared
     with the oracle's definition, and the two outputs with each other by
     per-layer checksums (sum and sum of squares of the words, mod 2^64).
+    Returns the result and the sampled words with their inputs; the oracle
+    compares them in the CPU-baseline leg (check_bottleneck_samples).
 
     Input words are drawn on the device (torch's seeded generator, uniform
     mod q_l): 8 GiB of host-drawn words would dominate the set-up time.  The
-    oracle samples read the input words back from the device before the
-    first run."""
-    import oracle
-
+    sampled inputs are read back from the device before the first run."""
     cfg = synth.WORKLOADS["bottleneck_cnn_b16"]
     N, L, bits, B = cfg["N"], cfg["L"], cfg["bits"], cfg["batch"]
-    prm = oracle.Params(N, L, bits, 2 ** synth.T_BITS)
     ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), 2 ** synth.T_BITS)
-    assert prm.q == ctx.q
     qd = torch.tensor(ctx.q, dtype=torch.int64, device="cuda").view(1, L, 1)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64).copy()).cuda()
     descs, sizes, Ks, wntts, ins, outs, macs = [], [], [], [], [], [], 0
@@ -465,13 +467,6 @@ def run_bottleneck(torch, heconv):
     plain()
     torch.cuda.synchronize()
     got_plain, sums_plain = sampled(), checksums()
-    want = []
-    for (j, b, m, sp, c, l, k, img) in picks:
-        cv = oracle.Conv(*cfg["layers"][j])
-        d = descs[j]
-        g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
-        wc = oracle.pack_weights(Ks[j][m:m + 1], cv, g, prm)
-        want.append(oracle.conv_layer_coeff(img, wc, g, prm, 0, 0, sp, c, l, k))
     fill_inputs()
     for o in outs:
         o.zero_()
@@ -490,12 +485,33 @@ def run_bottleneck(torch, heconv):
            "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_batch * 1e3,
            "plain_ctpt_macs_per_s": macs / t_plain * 1e3, "batched_ctpt_macs_per_s": macs / t_batch * 1e3,
            "speedup": t_plain / t_batch,
-           "sampled_words_vs_oracle": len(picks),
-           "bit_exact": bool(got_plain == want and got_batch == want and sums_plain == sums_batch)}
+           "plain_equals_batched": bool(sums_plain == sums_batch and got_plain == got_batch)}
+    pending = {"q": list(ctx.q), "picks": [(j, b, m, sp, c, l, k, img, Ks[j][m:m + 1].copy(),
+                                             (descs[j].Cw, descs[j].Hw, descs[j].Ww))
+                                            for (j, b, m, sp, c, l, k, img) in picks],
+               "got_plain": got_plain, "got_batch": got_batch}
     bt.close()
     del ins, outs, wntts, jobs
     ctx.close()
-    return res
+    return res, pending
+
+
+def check_bottleneck_samples(pending):
+    """CPU-baseline leg: the oracle's definition (one coefficient of the
+    negacyclic sum over channel blocks) for each sampled output word of the
+    bottleneck CNN, against the plain and the batched words."""
+    import oracle
+
+    cfg = synth.WORKLOADS["bottleneck_cnn_b16"]
+    prm = oracle.Params(cfg["N"], cfg["L"], cfg["bits"], 2 ** synth.T_BITS)
+    assert prm.q == pending["q"]
+    want = []
+    for (j, b, m, sp, c, l, k, img, Km, (Cw, Hw, Ww)) in pending["picks"]:
+        cv = oracle.Conv(*cfg["layers"][j])
+        g = oracle.geometry(cv, Cw, Hw, Ww)
+        wc = oracle.pack_weights(Km, cv, g, prm)
+        want.append(oracle.conv_layer_coeff(img, wc, g, prm, 0, 0, sp, c, l, k))
+    return len(want), bool(pending["got_plain"] == want and pending["got_batch"] == want)
 
 
 def run_client(torch, heconv):
