@@ -136,14 +136,14 @@ he_status dev_err(hipError_t e) { return e == hipSuccess ? HE_OK : HE_EDEVICE; }
 // Every transform of the library goes through here: double precision when
 // all primes allow it (and the tuning asks for it), else the integer
 // kernels -- for a small forward count, in two grids.
-hipError_t ntt_run(const he_ctx* c, bool inverse, uint64_t* polys, uint64_t n, hipStream_t st) {
+hipError_t ntt_run(const he_ctx* c, bool inverse, uint64_t* polys, uint64_t n, hipStream_t st, bool nt = false) {
   if (c->fp64_ok && c->tune.ntt_fp64)
     return heconv::ntt_f64_launch(inverse, c->logN, ntt_loge(c, n), polys, n, c->L, inverse ? c->d_inv64 : c->d_fwd64,
                                   c->d_fc, st);
   if (!inverse && n * c->L < c->tune.ntt_split_below && heconv::ntt_fwd_split_supported(c->logN))
     return heconv::ntt_fwd_split_launch(c->logN, polys, n, c->L, c->d_fwd, c->d_lc, st);
   return heconv::ntt_launch(inverse, c->logN, ntt_loge(c, n), polys, n, c->L, inverse ? c->d_inv : c->d_fwd, c->d_lc,
-                            st);
+                            st, nt);
 }
 
 }  // namespace
@@ -417,7 +417,7 @@ he_status he_ntt_inv(const he_ctx* c, uint64_t* d_polys, uint64_t n, void* strea
   if (check_ctx(c)) return HE_EINVAL;
   if (n == 0) return HE_OK;
   if (!d_polys) return HE_EINVAL;
-  return dev_err(ntt_run(c, true, d_polys, n, (hipStream_t)stream));
+  return dev_err(ntt_run(c, true, d_polys, n, (hipStream_t)stream, true));
 }
 
 he_status he_conv_ntt_mac(const he_ctx* c, const he_conv_desc* d, uint32_t B, const uint64_t* d_in_ntt,
@@ -477,7 +477,7 @@ he_status he_conv_layer(const he_ctx* c, const he_conv_desc* d, uint32_t B, uint
     if (s) return s;
     if (hipEventRecord(c->ev_mac[p], st) != hipSuccess || hipStreamWaitEvent(c->aux, c->ev_mac[p], 0) != hipSuccess)
       return HE_EDEVICE;
-    s = dev_err(ntt_run(c, true, d_out + m0 * out_per_m, (uint64_t)Mp * g.S * 2, c->aux));
+    s = dev_err(ntt_run(c, true, d_out + m0 * out_per_m, (uint64_t)Mp * g.S * 2, c->aux, true));
     if (s) return s;
     m0 = m_end;
   }

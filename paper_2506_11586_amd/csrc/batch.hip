@@ -36,7 +36,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LOGE) void batch_inv_kernel(const Ba
   gword* out = as_global(jobs[it.job].out);
   const uint32_t l = it.idx % L;
   const LimbConst c = lcs[l];
-  ntt_inv_poly<LOGN, LOGE>(out + (size_t)it.idx * N, tw + (size_t)l * N, c, lds, threadIdx.x);
+  ntt_inv_poly<LOGN, LOGE, true>(out + (size_t)it.idx * N, tw + (size_t)l * N, c, lds, threadIdx.x);
 }
 
 // MAC work list: the host interleaves eight per-XCD lists (workgroup b runs

@@ -9,9 +9,10 @@ namespace heconv {
 
 // Forward (inverse = false) or inverse NTT, in place, of n_rns_polys RNS
 // polynomials [n][L][N], N = 2^logN, logN in [10, 14]; 2^loge words per
-// thread (loge 3 or 4; 3 needs logN <= 13, else 4 is used).
+// thread (loge 3 or 4; 3 needs logN <= 13, else 4 is used).  nt: the
+// inverse transform stores its result non-temporally (a layer's output).
 hipError_t ntt_launch(bool inverse, uint32_t logN, uint32_t loge, uint64_t* polys, uint64_t n_rns_polys, uint32_t L,
-                      const Tw* tw, const LimbConst* lc, hipStream_t st);
+                      const Tw* tw, const LimbConst* lc, hipStream_t st, bool nt = false);
 
 // Forward NTT in two grids (first six stages by residue class, the rest by
 // block), for counts too small to occupy every compute unit; logN 12..14.

@@ -171,7 +171,8 @@ __device__ __forceinline__ void mac_tile(cgword* __restrict__ in, cgword* __rest
   for (int j = 0; j < MT; j++)
 #pragma unroll
     for (int i = 0; i < RT; i++)
-      if (mv[j] && rv[i]) out[out_off[i] + (uint64_t)(mt * MT + j) * out_m_stride + (uint32_t)tid] = res[j][i];
+      if (mv[j] && rv[i])  // non-temporal: streamed past the caches, which keep the weights
+        __builtin_nontemporal_store(res[j][i], &out[out_off[i] + (uint64_t)(mt * MT + j) * out_m_stride + (uint32_t)tid]);
 }
 
 }  // namespace heconv

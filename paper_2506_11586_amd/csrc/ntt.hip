@@ -17,7 +17,7 @@ __global__ __launch_bounds__((1 << LOGN) >> LOGE) void ntt_fwd_kernel(uint64_t* 
   ntt_fwd_poly<LOGN, LOGE>(as_global(polys) + (size_t)p * N, tw_all + (size_t)l * N, c, lds, threadIdx.x);
 }
 
-template <int LOGN, int LOGE>
+template <int LOGN, int LOGE, bool NT>
 __global__ __launch_bounds__((1 << LOGN) >> LOGE) void ntt_inv_kernel(uint64_t* __restrict__ polys, uint32_t L,
                                                                        const Tw* __restrict__ tw_all,
                                                                        const LimbConst* __restrict__ lcs) {
@@ -26,12 +26,12 @@ __global__ __launch_bounds__((1 << LOGN) >> LOGE) void ntt_inv_kernel(uint64_t* 
   const uint32_t p = blockIdx.x;
   const uint32_t l = p % L;
   const LimbConst c = lcs[l];
-  ntt_inv_poly<LOGN, LOGE>(as_global(polys) + (size_t)p * N, tw_all + (size_t)l * N, c, lds, threadIdx.x);
+  ntt_inv_poly<LOGN, LOGE, NT>(as_global(polys) + (size_t)p * N, tw_all + (size_t)l * N, c, lds, threadIdx.x);
 }
 
 template <int LOGN, int LOGE>
 static hipError_t launch_ntt(bool inverse, uint64_t* polys, uint64_t nlimbpolys, uint32_t L, const Tw* tw,
-                             const LimbConst* lc, hipStream_t st) {
+                             const LimbConst* lc, hipStream_t st, bool nt) {
   constexpr int T = (1 << LOGN) >> LOGE;
   // grid.x is limited to 2^31-1 workgroups: split larger batches into chunks
   // of whole RNS polynomials so that blockIdx.x % L stays the limb index
@@ -39,8 +39,10 @@ static hipError_t launch_ntt(bool inverse, uint64_t* polys, uint64_t nlimbpolys,
   for (uint64_t off = 0; off < nlimbpolys; off += max_blocks) {
     uint64_t cnt = nlimbpolys - off < max_blocks ? nlimbpolys - off : max_blocks;
     uint64_t* base = polys + off * (1ull << LOGN);
-    if (inverse)
-      hipLaunchKernelGGL((ntt_inv_kernel<LOGN, LOGE>), dim3((uint32_t)cnt), dim3(T), 0, st, base, L, tw, lc);
+    if (inverse && nt)
+      hipLaunchKernelGGL((ntt_inv_kernel<LOGN, LOGE, true>), dim3((uint32_t)cnt), dim3(T), 0, st, base, L, tw, lc);
+    else if (inverse)
+      hipLaunchKernelGGL((ntt_inv_kernel<LOGN, LOGE, false>), dim3((uint32_t)cnt), dim3(T), 0, st, base, L, tw, lc);
     else
       hipLaunchKernelGGL((ntt_fwd_kernel<LOGN, LOGE>), dim3((uint32_t)cnt), dim3(T), 0, st, base, L, tw, lc);
   }
@@ -49,22 +51,22 @@ static hipError_t launch_ntt(bool inverse, uint64_t* polys, uint64_t nlimbpolys,
 
 template <int LOGN>
 static hipError_t launch_ntt_e(bool inverse, uint32_t loge, uint64_t* polys, uint64_t nlp, uint32_t L,
-                               const Tw* tw, const LimbConst* lc, hipStream_t st) {
+                               const Tw* tw, const LimbConst* lc, hipStream_t st, bool nt) {
   if constexpr (LOGN <= 13) {  // 8 words per thread needs N/8 <= 1024 threads
-    if (loge == 3) return launch_ntt<LOGN, 3>(inverse, polys, nlp, L, tw, lc, st);
+    if (loge == 3) return launch_ntt<LOGN, 3>(inverse, polys, nlp, L, tw, lc, st, nt);
   }
-  return launch_ntt<LOGN, 4>(inverse, polys, nlp, L, tw, lc, st);
+  return launch_ntt<LOGN, 4>(inverse, polys, nlp, L, tw, lc, st, nt);
 }
 
 hipError_t ntt_launch(bool inverse, uint32_t logN, uint32_t loge, uint64_t* polys, uint64_t n_rns_polys,
-                      uint32_t L, const Tw* tw, const LimbConst* lc, hipStream_t st) {
+                      uint32_t L, const Tw* tw, const LimbConst* lc, hipStream_t st, bool nt) {
   const uint64_t nlp = n_rns_polys * L;
   switch (logN) {
-    case 10: return launch_ntt_e<10>(inverse, loge, polys, nlp, L, tw, lc, st);
-    case 11: return launch_ntt_e<11>(inverse, loge, polys, nlp, L, tw, lc, st);
-    case 12: return launch_ntt_e<12>(inverse, loge, polys, nlp, L, tw, lc, st);
-    case 13: return launch_ntt_e<13>(inverse, loge, polys, nlp, L, tw, lc, st);
-    case 14: return launch_ntt_e<14>(inverse, loge, polys, nlp, L, tw, lc, st);
+    case 10: return launch_ntt_e<10>(inverse, loge, polys, nlp, L, tw, lc, st, nt);
+    case 11: return launch_ntt_e<11>(inverse, loge, polys, nlp, L, tw, lc, st, nt);
+    case 12: return launch_ntt_e<12>(inverse, loge, polys, nlp, L, tw, lc, st, nt);
+    case 13: return launch_ntt_e<13>(inverse, loge, polys, nlp, L, tw, lc, st, nt);
+    case 14: return launch_ntt_e<14>(inverse, loge, polys, nlp, L, tw, lc, st, nt);
     default: return hipErrorInvalidValue;
   }
 }

@@ -171,8 +171,10 @@ __device__ __forceinline__ void ntt_inv_regs(uint64_t (&x)[1 << LOGE], const Tw*
   inv_rest<LOGN, LOGE, 0>(x, lds, tid, tw, c);
 }
 
-// Inverse transform of one limb polynomial a[N] (in place).
-template <int LOGN, int LOGE>
+// Inverse transform of one limb polynomial a[N] (in place).  With NT the
+// result is stored non-temporally: a layer's output is not read again soon,
+// and streaming it past the caches keeps them for the weights.
+template <int LOGN, int LOGE, bool NT = false>
 __device__ __forceinline__ void ntt_inv_poly(gword* __restrict__ a, const Tw* __restrict__ tw, const LimbConst& c,
                                              uint64_t* lds, int tid) {
   constexpr int N = 1 << LOGN, E = 1 << LOGE, T = N / E;
@@ -181,7 +183,12 @@ __device__ __forceinline__ void ntt_inv_poly(gword* __restrict__ a, const Tw* __
   for (int k = 0; k < E; k++) x[k] = a[tid + k * T];  // coalesced, top mapping
   ntt_inv_regs<LOGN, LOGE>(x, tw, c, lds, tid);
 #pragma unroll
-  for (int k = 0; k < E; k++) a[tid + k * T] = x[k];
+  for (int k = 0; k < E; k++) {
+    if constexpr (NT)
+      __builtin_nontemporal_store(x[k], &a[tid + k * T]);
+    else
+      a[tid + k * T] = x[k];
+  }
 }
 
 }  // namespace heconv
