@@ -12,9 +12,13 @@
 //   (-P/2, P/2]: per modulus q_j, (x_j - ([x]_P mod q_j)) * P^-1 mod q_j
 //   (moddown_kernel), giving (-A', b - B') under s.
 // A rotation applies the automorphism to a while the digits are read and to
-// b in the last step, so the rotated ciphertext is never stored.  Every
-// kernel is elementwise over the N coefficients of a row; the transforms
-// are the library's NTT kernels on the extended context.
+// b in the last step, so the rotated ciphertext is never stored.
+// By default the steps run as three kernels: modup_ntt_kernel (digit
+// extension in the forward transform's load), inner_intt_kernel (the inner
+// product in the inverse transform's load) and moddown_kernel.  The
+// elementwise modup_kernel and ks_inner_kernel with the library's NTT
+// kernels between them are the separate-steps form, and ks_fwd_kernel the
+// form with both sums kept in registers (tuning ks_fused 0 and 2).
 #include "kernels.h"
 #include "ntt_impl.h"
 
