@@ -195,9 +195,10 @@ he_status he_encode_weights(const he_ctx* ctx, const he_conv_desc* desc, const i
 he_status he_ntt_fwd(const he_ctx* ctx, uint64_t* d_polys, uint64_t n, void* stream);
 
 /* Inverse NTT, in place: d_polys[n][L][N] from NTT form back to
- * coefficients (including the factor N^-1).  The result is written with
- * non-temporal stores (streamed past the caches: a layer's output is not
- * read again soon), as he_conv_ntt_mac writes its output. */
+ * coefficients (including the factor N^-1).  The input is read and the
+ * result written non-temporally (streamed past the caches: a layer's MAC
+ * output is read once and its result not again soon), as he_conv_ntt_mac
+ * writes its output. */
 he_status he_ntt_inv(const he_ctx* ctx, uint64_t* d_polys, uint64_t n, void* stream);
 
 /* Multiply-accumulate in the NTT domain over channel blocks (Sec. 6.2):

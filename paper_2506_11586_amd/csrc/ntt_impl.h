@@ -172,15 +172,21 @@ __device__ __forceinline__ void ntt_inv_regs(uint64_t (&x)[1 << LOGE], const Tw*
 }
 
 // Inverse transform of one limb polynomial a[N] (in place).  With NT the
-// result is stored non-temporally: a layer's output is not read again soon,
-// and streaming it past the caches keeps them for the weights.
+// input is loaded and the result stored non-temporally: a layer's MAC output
+// is read once here, and its result is not read again soon, so streaming
+// both past the caches keeps L2 and the Infinity Cache for the weights.
 template <int LOGN, int LOGE, bool NT = false>
 __device__ __forceinline__ void ntt_inv_poly(gword* __restrict__ a, const Tw* __restrict__ tw, const LimbConst& c,
                                              uint64_t* lds, int tid) {
   constexpr int N = 1 << LOGN, E = 1 << LOGE, T = N / E;
   uint64_t x[E];
 #pragma unroll
-  for (int k = 0; k < E; k++) x[k] = a[tid + k * T];  // coalesced, top mapping
+  for (int k = 0; k < E; k++) {  // coalesced, top mapping
+    if constexpr (NT)
+      x[k] = __builtin_nontemporal_load(&a[tid + k * T]);
+    else
+      x[k] = a[tid + k * T];
+  }
   ntt_inv_regs<LOGN, LOGE>(x, tw, c, lds, tid);
 #pragma unroll
   for (int k = 0; k < E; k++) {
