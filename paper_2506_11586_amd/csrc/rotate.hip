@@ -20,6 +20,7 @@
 // kernels between them are the separate-steps form, and ks_fwd_kernel the
 // form with both sums kept in registers (tuning ks_fused 0 and 2).
 #include "kernels.h"
+#include "mac_impl.h"
 #include "ntt_impl.h"
 
 namespace heconv {
@@ -317,21 +318,23 @@ __global__ __launch_bounds__((1 << LOGN) >> 3) void inner_intt_kernel(const uint
 #pragma unroll
   for (int k = 0; k < E; k++) hi[k] = lo[k] = 0;
   // L <= 7 digit products and one plaintext product, each below 2^120: the
-  // 128-bit sums do not overflow
+  // 128-bit sums do not overflow.  Rows are read through buffer resources
+  // (the row base in scalar registers, the lane's byte offset fixed, the
+  // register's offset k*T*8 a scalar), so a load costs no per-lane address
+  // arithmetic.
   const bool plain = xp && m < L;
+  const uint32_t lane = (uint32_t)tid * 8;
   for (uint32_t l = 0; l < nd + (plain ? 1 : 0); l++) {
-    // an opaque copy of the thread index each term keeps the compiler from
-    // turning the loads into per-lane 64-bit pointers carried across the loop
-    int tk = tid;
-    asm volatile("" : "+v"(tk));
     const uint64_t* d =
         l < nd ? digits + ((i * L + l) * L1 + m) * N : xp + (((i % chain_cts) * 2 + comp) * L + m) * N;
     const uint64_t* kr =
         l < nd ? ksk + ((uint64_t)(l * 2 + comp) * L1 + m) * N : wp + (i / chain_cts) * w_stride + (uint64_t)m * N;
+    const __amdgpu_buffer_rsrc_t rd = mac_rsrc((const uint64_t*)uniform64((uint64_t)d), (uint64_t)N * 8);
+    const __amdgpu_buffer_rsrc_t rk = mac_rsrc((const uint64_t*)uniform64((uint64_t)kr), (uint64_t)N * 8);
 #pragma unroll
     for (int k = 0; k < E; k++) {
       uint64_t ph, pl;
-      mul_wide(d[tk + k * T], kr[tk + k * T], ph, pl);
+      mul_wide(mac_load(rd, lane, (uint32_t)(k * T * 8)), mac_load(rk, lane, (uint32_t)(k * T * 8)), ph, pl);
       lo[k] += pl;
       hi[k] += ph + (lo[k] < pl);
     }
