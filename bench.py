@@ -288,7 +288,8 @@ def run_batched(torch, heconv, polyphase=False):
     """Fire-module CNN (26 convs at 224 input, B=1, N=8192, L=3): the 26 layer
     solves one after another through he_conv_layer (plain) vs one batch (two
     chains of three grids, one hipGraph launch).  Outputs compared word for
-    word.  With polyphase, the strided first layer runs as its polyphase
+    word.  With polyphase, every strided layer for which the planner's
+    objective prefers it (here the first layer) runs as its polyphase
     stride-1 layer (the same outputs, fewer output ciphertexts)."""
     cfg = synth.WORKLOADS["fire_cnn"]
     N, L, bits = cfg["N"], cfg["L"], cfg["bits"]
@@ -299,7 +300,7 @@ def run_batched(torch, heconv, polyphase=False):
         C, H, W, M, kh, kw, stride, pad = shape
         K = Stream(cfg["seed"] * 1000 + i, synth.WEIGHT).ints(M * C * kh * kw, *cfg["w_range"])
         Kd = dev(K)
-        if polyphase and stride > 1 and kh > 1:
+        if polyphase and heconv.polyphase_advised(N, L, shape, 1):
             shape = heconv.polyphase_shape(shape)
             Kp = torch.empty(shape[3] * shape[0] * shape[4] * shape[5], dtype=torch.int64, device="cuda")
             heconv.polyphase_weights((C, H, W, M, kh, kw, stride, pad), Kd, Kp)
@@ -335,7 +336,8 @@ def run_batched(torch, heconv, polyphase=False):
     b.close()
     ctx.close()
     if polyphase:
-        return {"workload": cfg["name"] + ", first layer in polyphase form", "out_cts_per_pass": out_cts,
+        return {"workload": cfg["name"] + ", strided layers in polyphase form where the planner prefers it",
+                "out_cts_per_pass": out_cts,
                 "ctpt_macs_per_pass": macs, "plain_ms": t_plain, "batched_ms": t_batch,
                 "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_batch * 1e3,
                 "bit_exact_vs_plain": bool(exact)}

@@ -445,6 +445,13 @@ he_status he_zp_matvec_grouped(const he_ctx* ext, uint64_t g, uint64_t n, const 
  * with he_plan_conv).  HE_ESHAPE if stride < 2 or the shape is empty. */
 he_status he_polyphase_desc(const he_conv_desc* in, he_conv_desc* out);
 
+/* Host only: *use = 1 when the planner's objective (HBM bytes, then
+ * modmuls; see he_plan_conv) is lower for the polyphase form of the strided
+ * conv d at this batch than for the strided form, each with its own
+ * planned packing; 0 otherwise, and for stride 1.  Packing fields of d are
+ * ignored. */
+he_status he_polyphase_advised(uint32_t N, uint32_t L, const he_conv_desc* d, uint32_t batch_hint, int* use);
+
 /* Weights int64 [M][C][kh][kw] of the strided conv -> the polyphase conv's
  * [M][s*s*C][ceil(kh/s)][ceil(kw/s)]: Kp[m][c*s*s + a*s + b][i][j] =
  * K[m][c][s*i + a][s*j + b], zero outside the kernel (device buffers). */

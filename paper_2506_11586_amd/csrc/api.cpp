@@ -333,17 +333,28 @@ he_status he_ctx_set_tuning(he_ctx* c, const he_tuning* t) {
   return HE_OK;
 }
 
+namespace {
+
+// The planner's objective for a planned layer: HBM bytes (weights once,
+// inputs and outputs three times each per image) and modmuls.
+void plan_cost(const he_conv_desc& d, const Geo& g, uint32_t N, uint32_t L, uint32_t B, u128& bytes, u128& mm) {
+  const u128 LN8 = (u128)L * N * 8, ct = 2 * LN8;
+  const u128 ntt_mm = (u128)L * (N / 2) * log2u(N) * 2;  // per ciphertext
+  const u128 in_cts = (u128)g.CB * g.S, out_cts = (u128)d.M * g.S;
+  bytes = (u128)d.M * g.CB * LN8 + (u128)B * 3 * (in_cts + out_cts) * ct;
+  mm = (u128)B * (in_cts + out_cts) * ntt_mm + (u128)B * d.M * g.CB * g.S * 2 * L * N;
+}
+
+}  // namespace
+
 he_status he_plan_conv_host(uint32_t N, uint32_t L, he_conv_desc* io, uint32_t batch_hint) {
   if (!io) return HE_EINVAL;
   if (!pow2(N) || N < 2 || L == 0) return HE_EPARAM;
-  const unsigned logN = log2u(N);
   if (!batch_hint) batch_hint = 1;
   he_conv_desc d = *io;
   d.Cw = 1, d.Hw = d.kh, d.Ww = d.kw;
   Geo g0;
   if (!geo_of(d, N, g0)) return io->C && io->M && io->kh && io->kw && io->stride ? HE_ESHAPE : HE_EINVAL;
-  const u128 LN8 = (u128)L * N * 8, ct = 2 * LN8;
-  const u128 ntt_mm = (u128)L * (N / 2) * logN * 2;  // per ciphertext
   bool have = false;
   u128 best_b = 0, best_m = 0;
   uint32_t bHw = 0, bWw = 0, bCw = 0;
@@ -354,10 +365,8 @@ he_status he_plan_conv_host(uint32_t N, uint32_t L, he_conv_desc* io, uint32_t b
       d.Cw = std::min<uint64_t>(d.C, N / ((uint64_t)Hw * Ww));
       Geo g;
       if (!geo_of(d, N, g)) continue;
-      const u128 in_cts = (u128)g.CB * g.S, out_cts = (u128)d.M * g.S;
-      const u128 bytes = (u128)d.M * g.CB * LN8 + (u128)batch_hint * 3 * (in_cts + out_cts) * ct;
-      const u128 mm = (u128)batch_hint * (in_cts + out_cts) * ntt_mm +
-                      (u128)batch_hint * d.M * g.CB * g.S * 2 * L * N;
+      u128 bytes, mm;
+      plan_cost(d, g, N, L, batch_hint, bytes, mm);
       // strict improvement keeps the earlier (smaller) Hw/Ww on ties of both
       // costs; ties are then broken towards larger Hw, then larger Ww
       bool better = !have || bytes < best_b || (bytes == best_b && mm < best_m) ||
@@ -919,6 +928,25 @@ he_status he_polyphase_desc(const he_conv_desc* in, he_conv_desc* out) {
   heconv::PolyGeom g;
   if (!poly_geom(in, g)) return HE_ESHAPE;
   *out = he_conv_desc{g.Cp, g.Hp, g.Wp, g.M, g.khp, g.kwp, 1, 0, 0, 0, 0};
+  return HE_OK;
+}
+
+he_status he_polyphase_advised(uint32_t N, uint32_t L, const he_conv_desc* d, uint32_t batch_hint, int* use) {
+  if (!d || !use) return HE_EINVAL;
+  *use = 0;
+  if (!batch_hint) batch_hint = 1;
+  if (d->stride < 2) return HE_OK;
+  he_conv_desc ds = *d, dp;
+  ds.Cw = ds.Hw = ds.Ww = 0;
+  if (he_status s = he_plan_conv_host(N, L, &ds, batch_hint)) return s;
+  if (he_status s = he_polyphase_desc(d, &dp)) return s;
+  if (he_status s = he_plan_conv_host(N, L, &dp, batch_hint)) return s;
+  Geo gs, gp;
+  if (!geo_of(ds, N, gs) || !geo_of(dp, N, gp)) return HE_ESHAPE;
+  u128 bs, ms, bp, mp;
+  plan_cost(ds, gs, N, L, batch_hint, bs, ms);
+  plan_cost(dp, gp, N, L, batch_hint, bp, mp);
+  *use = bp < bs || (bp == bs && mp < ms);
   return HE_OK;
 }
 

@@ -112,6 +112,7 @@ def _lib_handle():
         L.he_zp_grouped_work_words.argtypes = [vp, u64, u32, P(u64)]
         L.he_zp_matvec_grouped.argtypes = [vp, u64, u64, vp, vp, u32, u32, vp, u64, vp, vp, vp, vp]
         L.he_polyphase_desc.argtypes = [P(ConvDesc), P(ConvDesc)]
+        L.he_polyphase_advised.argtypes = [u32, u32, P(ConvDesc), u32, P(i32)]
         L.he_polyphase_weights.argtypes = [P(ConvDesc), vp, vp, vp]
         L.he_polyphase_input.argtypes = [P(ConvDesc), u32, vp, vp, vp]
         L.he_batch_create.argtypes = [vp, P(_Job), u32, u32, P(vp)]
@@ -128,7 +129,7 @@ def _lib_handle():
                      "he_key_encode", "he_encrypt", "he_decrypt", "he_keyswitch_work_words", "he_automorph", "he_galois_key",
                      "he_keyswitch", "he_rotate", "he_simd_encode", "he_simd_decode", "he_zp_diagonals",
                      "he_zp_encode_plain", "he_zp_work_words", "he_zp_matvec", "he_zp_grouped_work_words",
-                     "he_zp_matvec_grouped", "he_polyphase_desc",
+                     "he_zp_matvec_grouped", "he_polyphase_desc", "he_polyphase_advised",
                      "he_polyphase_weights", "he_polyphase_input"):
             getattr(L, name).restype = i32
         _LIB = L
@@ -214,6 +215,16 @@ def polyphase_shape(shape) -> tuple:
     d_out = ConvDesc()
     _check(lib().he_polyphase_desc(ctypes.byref(d_in), ctypes.byref(d_out)), "he_polyphase_desc")
     return d_out.shape()
+
+
+def polyphase_advised(N: int, L: int, shape, batch: int = 1) -> bool:
+    """he_polyphase_advised: whether the planner's objective prefers the
+    polyphase form of the strided conv `shape` at this batch (host only)."""
+    d = ConvDesc(*[int(v) for v in shape], 0, 0, 0)
+    use = ctypes.c_int()
+    _check(lib().he_polyphase_advised(int(N), int(L), ctypes.byref(d), int(batch), ctypes.byref(use)),
+           "he_polyphase_advised")
+    return bool(use.value)
 
 
 def polyphase_weights(shape, w_dev, wp_dev, stream=None):

@@ -110,3 +110,29 @@ def test_polyphase_descriptor_matches_oracle():
     with pytest.raises(heconv.HeError) as e:
         heconv.polyphase_shape((3, 16, 16, 4, 3, 3, 1, 1))
     assert e.value.status == heconv.HE_ESHAPE
+
+
+def test_polyphase_advice_matches_oracle_costs():
+    """he_polyphase_advised equals the decision taken from the oracle
+    planner's costs of both forms (bytes, then modmuls) for the strided
+    layers of the two CNNs at their batches; stride 1 is never advised."""
+    import oracle
+    import synth
+    from paper_2506_11586_amd import heconv
+    seen = 0
+    for wl in ("fire_cnn", "bottleneck_cnn_b16"):
+        cfg = synth.WORKLOADS[wl]
+        B = cfg.get("batch", 1)
+        for shape in cfg["layers"]:
+            if shape[6] == 1:
+                assert not heconv.polyphase_advised(cfg["N"], cfg["L"], shape, B)
+                continue
+            cv = oracle.Conv(*shape)
+            pc = oracle.polyphase_conv(cv)
+            bs, ms = oracle.layer_cost(cv, oracle.plan_conv(cv, cfg["N"], cfg["L"], B), cfg["N"], cfg["L"], B)
+            bp, mp = oracle.layer_cost(pc, oracle.plan_conv(pc, cfg["N"], cfg["L"], B), cfg["N"], cfg["L"], B)
+            want = bp < bs or (bp == bs and mp < ms)
+            assert heconv.polyphase_advised(cfg["N"], cfg["L"], shape, B) == want, shape
+            seen += 1
+    assert seen >= 5
+    assert heconv.polyphase_advised(8192, 3, (3, 224, 224, 64, 3, 3, 2, 1), 1)
