@@ -870,3 +870,29 @@ def zp_matvec_grouped_ct(ct_x, diag_polys, G: int, g: int, ksk, g2: int, ksk2, p
     for c in range(G - 2, -1, -1):
         acc = ct_add(rotate(acc, g2, ksk2, prm, P), chains[c], prm)
     return acc
+
+
+def zp_diagonals_rect(W: np.ndarray, n_out: int, n_in: int, N: int, t: int) -> np.ndarray:
+    """The n_out generalized diagonals of W [rows][cols] (rows <= n_out,
+    cols <= n_in, n_out | n_in | N/2, powers of two): diagonal i holds
+    W[(k - i) mod n_out][k mod n_in] in slot k of each row.  With x repeated
+    with period n_in, z = sum_i rot^i(d_i * x) has
+    z[r + j*n_out] = sum over columns r + j*n_out .. r + (j+1)*n_out - 1 of
+    row r, so y = sum_j z[r + j*n_out], log2(n_in/n_out) rotate-and-add
+    steps (rotations by n_out, 2*n_out, ...); n_out = n_in is zp_diagonals."""
+    rows, cols = W.shape
+    Wp = np.zeros((n_out, n_in), dtype=object)
+    Wp[:rows, :cols] = np.mod(W.astype(object), t)
+    h = N // 2
+    k = np.arange(h) % n_in
+    out = np.zeros((n_out, N), dtype=object)
+    for i in range(n_out):
+        row = Wp[(k - i) % n_out, k]
+        out[i, :h] = row
+        out[i, h:] = row
+    return out
+
+
+def zp_fold_ct(ct, g2: int, ksk2, prm: Params, P: int) -> np.ndarray:
+    """One rotate-and-add step: ct + rotate(ct, g2)."""
+    return ct_add(ct, rotate(ct, g2, ksk2, prm, P), prm)

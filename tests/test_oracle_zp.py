@@ -147,3 +147,53 @@ def test_grouped_iteration_decrypts_to_the_matrix_product():
     out = oracle.zp_matvec_grouped_ct(ct, diags, 2, keys[0][0], keys[0][1], keys[1][0], keys[1][1], prm, P)
     y = oracle.simd_decode(oracle.bfv_decrypt(out, sk, prm)[0], t)
     assert np.array_equal(y[:5], want)
+
+
+@pytest.mark.parametrize("rows,cols,n_out,n_in", [(5, 16, 8, 16), (3, 32, 4, 32), (8, 8, 8, 8), (1, 64, 1, 64)])
+def test_rectangular_diagonals_and_folds_give_the_matrix_product(tp, rows, cols, n_out, n_in):
+    """n_out generalized diagonals through the iteration, then
+    log2(n_in/n_out) rotate-and-add steps, on plain slot vectors: W x."""
+    N, t = tp
+    W = Stream(170 + n_in, synth.WEIGHT).below(rows * cols, t).reshape(rows, cols)
+    x = Stream(171 + n_in, synth.INPUT).below(cols, t)
+    d = oracle.zp_diagonals_rect(W, n_out, n_in, N, t)
+    xs = oracle.zp_input_slots(x, n_in, N, t)
+    h = N // 2
+    rot = lambda v, k: np.concatenate([np.roll(v[:h], -k), np.roll(v[h:], -k)])
+    acc = (d[n_out - 1] * xs) % t
+    for i in range(n_out - 2, -1, -1):
+        acc = (rot(acc, 1) + d[i] * xs) % t
+    s = n_out
+    while s < n_in:
+        acc = (acc + rot(acc, s)) % t
+        s *= 2
+    want = (W.astype(object) @ x.astype(object)) % t
+    assert np.array_equal(acc[:rows], want)
+    if n_out == n_in:
+        assert np.array_equal(d, oracle.zp_diagonals(W, n_in, N, t))
+
+
+def test_rectangular_kernel_with_fold_decrypts_to_the_matrix_product():
+    """N=4096, 20-bit t: a 3 x 8 matrix with 4 diagonals of period 8, three
+    rotations by one slot and one fold by 4 slots (two Galois keys)."""
+    N, L, bits = 4096, 2, 50
+    t = oracle.find_primes(N, 20, 1)[0]
+    primes = oracle.find_primes(N, bits, L + 1)
+    prm = oracle.Params(N, L, bits, t, q=primes[:L])
+    P = primes[L]
+    ext = oracle.ext_params(prm, P)
+    sk = wl.secret_key(172, N)
+    keys = {}
+    for gg, seed in ((5, 173), (pow(5, 4, 2 * N), 174)):
+        a = synth.uniform_mod(Stream(seed, synth.UNIFORM), (L, L + 1, N), ext.q)
+        e = Stream(seed, synth.ERROR).cbd(L * N, wl.ETA).reshape(L, N)
+        keys[gg] = oracle.galois_key(sk, gg, a, e, prm, P)
+    W = Stream(175, synth.WEIGHT).below(24, t).reshape(3, 8)
+    x = Stream(175, synth.INPUT).below(8, t)
+    msg = oracle.simd_encode(oracle.zp_input_slots(x, 8, N, t), t).astype(np.uint64)
+    ct = wl.encrypt_polys(msg[None], prm, 176, sk)
+    diags = [oracle.centred_lift(oracle.simd_encode(dv, t), t) for dv in oracle.zp_diagonals_rect(W, 4, 8, N, t)]
+    out = oracle.zp_matvec_ct(ct, diags, 5, keys[5], prm, P)
+    out = oracle.zp_fold_ct(out, pow(5, 4, 2 * N), keys[pow(5, 4, 2 * N)], prm, P)
+    y = oracle.simd_decode(oracle.bfv_decrypt(out, sk, prm)[0], t)
+    assert np.array_equal(y[:3], (W.astype(object) @ x.astype(object)) % t)
