@@ -388,6 +388,18 @@ he_status he_simd_decode(const he_ctx* tctx, uint64_t n, const int64_t* d_coeffs
 he_status he_zp_diagonals(const he_ctx* tctx, const int64_t* d_w, uint32_t rows, uint32_t cols, uint32_t n,
                           uint64_t* d_slots, void* stream);
 
+/* The generalized diagonals of a matrix with fewer rows than columns:
+ * n_out slot vectors [n_out][N], diagonal i holding W[(k - i) mod n_out][k mod
+ * n_in] in slot k of each row (rows <= n_out <= n_in <= N/2, cols <= n_in,
+ * powers of two; HE_ESHAPE otherwise).  With the input repeated with period
+ * n_in, he_zp_matvec over these n_out diagonals leaves in slot
+ * r + j*n_out the sum over columns r + j*n_out .. r + (j+1)*n_out - 1 of
+ * row r; log2(n_in/n_out) he_zp_fold steps (rotations by n_out, 2*n_out,
+ * ...) then give W x in slots 0 .. rows-1: n_out iterations instead of
+ * n_in.  n_out = n_in is he_zp_diagonals. */
+he_status he_zp_diagonals_rect(const he_ctx* tctx, const int64_t* d_w, uint32_t rows, uint32_t cols, uint32_t n_out,
+                               uint32_t n_in, uint64_t* d_slots, void* stream);
+
 /* Weight plaintexts for he_zp_matvec: coefficients [n][N] (centred int64,
  * from he_simd_encode) lifted to the L ciphertext primes of the EXTENDED
  * context (q_0..q_{L-1}, P), multiplied by -P mod q_l and transformed:
@@ -410,6 +422,14 @@ he_status he_zp_work_words(const he_ctx* ext, uint64_t n, uint64_t* words);
  * otherwise); d_work: he_zp_work_words words. */
 he_status he_zp_matvec(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_x_ntt, const uint64_t* d_w,
                        uint32_t n_diag, const uint64_t* d_ksk_ntt, uint64_t* d_out, uint64_t* d_work, void* stream);
+
+/* One rotate-and-add step on n ciphertexts [n][2][L][N] (extended
+ * context): d_out = d_ct + rotate(d_ct, g), with d_ksk_ntt the Galois key
+ * for g as for he_rotate; the addition is folded into the last kernel.
+ * Out of place (d_ct == d_out is HE_EINVAL); d_work: he_keyswitch_work_words
+ * words. */
+he_status he_zp_fold(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_ct, const uint64_t* d_ksk_ntt,
+                     uint64_t* d_out, uint64_t* d_work, void* stream);
 
 /* Words of scratch he_zp_matvec_grouped needs: as he_zp_work_words for
  * groups*n ciphertexts. */

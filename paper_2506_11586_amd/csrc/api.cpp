@@ -636,7 +636,7 @@ he_status ks_check(const he_ctx* ext, uint64_t n) {
 }
 
 he_status ks_run(const he_ctx* ext, uint32_t ginv, uint64_t n, const uint64_t* ct, const uint64_t* ksk, uint64_t* out,
-                 uint64_t* work, hipStream_t st) {
+                 uint64_t* work, hipStream_t st, const uint64_t* addp = nullptr) {
   const uint32_t L = ext->L - 1, N = ext->N;
   const uint64_t P = ext->q[L];
   heconv::PinvConst pc{};
@@ -663,7 +663,7 @@ he_status ks_run(const he_ctx* ext, uint32_t ginv, uint64_t n, const uint64_t* c
     }
     if (!s) s = dev_err(ntt_run(ext, true, acc, 2 * n, st));
   }
-  if (!s) s = dev_err(heconv::moddown_launch(acc, ct, out, n, N, L, ginv, pc, ext->d_lc, st));
+  if (!s) s = dev_err(heconv::moddown_launch(acc, ct, out, n, N, L, ginv, pc, ext->d_lc, st, addp));
   return s;
 }
 
@@ -715,6 +715,15 @@ he_status he_keyswitch(const he_ctx* ext, uint64_t n, const uint64_t* d_ct, cons
   if (n == 0) return HE_OK;
   if (!d_ct || !d_ksk_ntt || !d_out || !d_work) return HE_EINVAL;
   return ks_run(ext, 1, n, d_ct, d_ksk_ntt, d_out, d_work, (hipStream_t)stream);
+}
+
+he_status he_zp_fold(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_ct, const uint64_t* d_ksk_ntt,
+                     uint64_t* d_out, uint64_t* d_work, void* stream) {
+  if (he_status s = ks_check(ext, n)) return s;
+  if (!galois_ok(g, ext->N)) return HE_EINVAL;
+  if (n == 0) return HE_OK;
+  if (!d_ct || !d_ksk_ntt || !d_out || !d_work || d_ct == d_out) return HE_EINVAL;
+  return ks_run(ext, inv_mod_2n(g, ext->N), n, d_ct, d_ksk_ntt, d_out, d_work, (hipStream_t)stream, d_ct);
 }
 
 he_status he_rotate(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_ct, const uint64_t* d_ksk_ntt,
@@ -774,7 +783,18 @@ he_status he_zp_diagonals(const he_ctx* tctx, const int64_t* d_w, uint32_t rows,
   if (he_status s = t_ctx_check(tctx)) return s;
   if (!pow2(n) || n > tctx->N / 2 || n > 65535 || rows == 0 || cols == 0 || rows > n || cols > n) return HE_ESHAPE;
   if (!d_w || !d_slots) return HE_EINVAL;
-  return dev_err(heconv::diagonals_launch(d_w, rows, cols, n, tctx->N, d_slots, tctx->lc[0], (hipStream_t)stream));
+  return dev_err(heconv::diagonals_launch(d_w, rows, cols, n, n, tctx->N, d_slots, tctx->lc[0], (hipStream_t)stream));
+}
+
+he_status he_zp_diagonals_rect(const he_ctx* tctx, const int64_t* d_w, uint32_t rows, uint32_t cols, uint32_t n_out,
+                               uint32_t n_in, uint64_t* d_slots, void* stream) {
+  if (he_status s = t_ctx_check(tctx)) return s;
+  if (!pow2(n_out) || !pow2(n_in) || n_out > n_in || n_in > tctx->N / 2 || n_out > 65535 || rows == 0 || cols == 0 ||
+      rows > n_out || cols > n_in)
+    return HE_ESHAPE;
+  if (!d_w || !d_slots) return HE_EINVAL;
+  return dev_err(heconv::diagonals_launch(d_w, rows, cols, n_out, n_in, tctx->N, d_slots, tctx->lc[0],
+                                          (hipStream_t)stream));
 }
 
 he_status he_zp_encode_plain(const he_ctx* ext, uint64_t n, const int64_t* d_coeffs, uint64_t* d_w, void* stream) {

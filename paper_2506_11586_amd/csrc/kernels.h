@@ -60,8 +60,8 @@ hipError_t slot_permute_launch(const uint64_t* in, uint64_t* out, uint64_t n, ui
                                hipStream_t st);
 hipError_t centre_launch(uint64_t* v, uint64_t words, uint64_t t, hipStream_t st);
 hipError_t reduce_t_launch(const int64_t* in, uint64_t* out, uint64_t words, const LimbConst& tc, hipStream_t st);
-hipError_t diagonals_launch(const int64_t* W, uint32_t rows, uint32_t cols, uint32_t n, uint32_t N, uint64_t* slots,
-                            const LimbConst& tc, hipStream_t st);
+hipError_t diagonals_launch(const int64_t* W, uint32_t rows, uint32_t cols, uint32_t n_out, uint32_t n_in, uint32_t N,
+                            uint64_t* slots, const LimbConst& tc, hipStream_t st);
 hipError_t lift_scaled_launch(const int64_t* c, uint64_t* out, uint64_t n, uint32_t N, uint32_t L,
                               const ScaleConst& sc, const LimbConst* lc, hipStream_t st);
 

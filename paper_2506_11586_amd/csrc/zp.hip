@@ -65,16 +65,19 @@ __global__ __launch_bounds__(ZP_THREADS) void reduce_t_kernel(const int64_t* __r
   out[idx] = v < 0 && r ? tc.q - r : r;
 }
 
-// slots[i][r*N/2 + k] = W[(k - i) mod n][k mod n] mod t (zero outside
-// rows x cols), for i < n, both rows r.
+// slots[i][r*N/2 + j] = W[(k - i) mod n_out][k] mod t with k = j mod n_in
+// (zero outside rows x cols), for i < n_out, both rows r.  n_out = n_in is
+// the square layout; n_out < n_in the generalized diagonals of a matrix
+// with fewer rows than columns.
 __global__ __launch_bounds__(ZP_THREADS) void diagonals_kernel(const int64_t* __restrict__ W, uint32_t rows,
-                                                                uint32_t cols, uint32_t n, uint32_t N,
-                                                                uint64_t* __restrict__ slots, LimbConst tc) {
+                                                                uint32_t cols, uint32_t n_out, uint32_t n_in,
+                                                                uint32_t N, uint64_t* __restrict__ slots,
+                                                                LimbConst tc) {
   const uint64_t i = blockIdx.y;
   const uint32_t s = blockIdx.x * ZP_THREADS + threadIdx.x;
   if (s >= N) return;
-  const uint32_t k = s & (n - 1);
-  const uint32_t r = (uint32_t)((k + n - (uint32_t)i) & (n - 1));
+  const uint32_t k = s & (n_in - 1);
+  const uint32_t r = (uint32_t)((k + n_out - (uint32_t)i) & (n_out - 1));
   uint64_t v = 0;
   if (r < rows && k < cols) {
     const int64_t w = W[(uint64_t)r * cols + k];
@@ -131,10 +134,11 @@ hipError_t reduce_t_launch(const int64_t* in, uint64_t* out, uint64_t words, con
   return hipGetLastError();
 }
 
-hipError_t diagonals_launch(const int64_t* W, uint32_t rows, uint32_t cols, uint32_t n, uint32_t N, uint64_t* slots,
-                            const LimbConst& tc, hipStream_t st) {
-  if (n > 65535) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(diagonals_kernel, zp_grid(N, n), dim3(ZP_THREADS), 0, st, W, rows, cols, n, N, slots, tc);
+hipError_t diagonals_launch(const int64_t* W, uint32_t rows, uint32_t cols, uint32_t n_out, uint32_t n_in, uint32_t N,
+                            uint64_t* slots, const LimbConst& tc, hipStream_t st) {
+  if (n_out > 65535) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(diagonals_kernel, zp_grid(N, n_out), dim3(ZP_THREADS), 0, st, W, rows, cols, n_out, n_in, N,
+                     slots, tc);
   return hipGetLastError();
 }
 

@@ -111,6 +111,8 @@ def _lib_handle():
         L.he_zp_matvec.argtypes = [vp, u64, u64, vp, vp, u32, vp, vp, vp, vp]
         L.he_zp_grouped_work_words.argtypes = [vp, u64, u32, P(u64)]
         L.he_zp_matvec_grouped.argtypes = [vp, u64, u64, vp, vp, u32, u32, vp, u64, vp, vp, vp, vp]
+        L.he_zp_diagonals_rect.argtypes = [vp, vp, u32, u32, u32, u32, vp, vp]
+        L.he_zp_fold.argtypes = [vp, u64, u64, vp, vp, vp, vp, vp]
         L.he_polyphase_desc.argtypes = [P(ConvDesc), P(ConvDesc)]
         L.he_polyphase_advised.argtypes = [u32, u32, P(ConvDesc), u32, P(i32)]
         L.he_polyphase_weights.argtypes = [P(ConvDesc), vp, vp, vp]
@@ -129,7 +131,8 @@ def _lib_handle():
                      "he_key_encode", "he_encrypt", "he_decrypt", "he_keyswitch_work_words", "he_automorph", "he_galois_key",
                      "he_keyswitch", "he_rotate", "he_simd_encode", "he_simd_decode", "he_zp_diagonals",
                      "he_zp_encode_plain", "he_zp_work_words", "he_zp_matvec", "he_zp_grouped_work_words",
-                     "he_zp_matvec_grouped", "he_polyphase_desc", "he_polyphase_advised",
+                     "he_zp_matvec_grouped", "he_zp_diagonals_rect", "he_zp_fold", "he_polyphase_desc",
+                     "he_polyphase_advised",
                      "he_polyphase_weights", "he_polyphase_input"):
             getattr(L, name).restype = i32
         _LIB = L
@@ -455,6 +458,20 @@ class Context:
         """he_zp_diagonals: W [rows][cols] -> n diagonal slot vectors [n][N]."""
         _check(lib().he_zp_diagonals(self._h, _ptr(w_dev, rows * cols, "W"), int(rows), int(cols), int(n),
                                      _ptr(slots_dev, n * self.N, "slots"), _stream(stream)), "he_zp_diagonals")
+
+    def zp_diagonals_rect(self, w_dev, rows: int, cols: int, n_out: int, n_in: int, slots_dev, stream=None):
+        """he_zp_diagonals_rect: W [rows][cols] -> n_out generalized diagonals [n_out][N]."""
+        _check(lib().he_zp_diagonals_rect(self._h, _ptr(w_dev, rows * cols, "W"), int(rows), int(cols), int(n_out),
+                                          int(n_in), _ptr(slots_dev, n_out * self.N, "slots"), _stream(stream)),
+               "he_zp_diagonals_rect")
+
+    def zp_fold(self, g: int, n: int, ct_dev, ksk_ntt_dev, out_dev, work_dev, stream=None):
+        """he_zp_fold (extended context): out = ct + rotate(ct, g)."""
+        Lc, N = self.L - 1, self.N
+        ct = n * 2 * Lc * N
+        _check(lib().he_zp_fold(self._h, int(g), int(n), _ptr(ct_dev, ct, "ct"),
+                                _ptr(ksk_ntt_dev, Lc * 2 * self.L * N, "ksk"), _ptr(out_dev, ct, "out"),
+                                _ptr(work_dev, self.keyswitch_work_words(n), "work"), _stream(stream)), "he_zp_fold")
 
     def zp_encode_plain(self, n: int, coeffs_dev, w_dev, stream=None):
         """he_zp_encode_plain (extended context): coefficients [n][N] -> [n][L-1][N]."""

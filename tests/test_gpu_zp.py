@@ -284,3 +284,76 @@ def test_grouped_fc_2048_to_1000_decrypts():
     ext.zp_matvec_grouped(5, B, ct_ntt, w, 64, 1, dk, 1, None, one, empty_words(ext.zp_grouped_work_words(B, 1)))
     ext.zp_matvec(5, B, ct_ntt, w, 64, dk, two, empty_words(ext.zp_work_words(B)))
     assert np.array_equal(to_host(one), to_host(two))
+
+
+@pytest.mark.parametrize("rows,cols,n_out,n_in", [(5, 16, 8, 16), (3, 32, 4, 32), (1000, 2048, 1024, 2048)])
+def test_rectangular_diagonals_match_oracle(rows, cols, n_out, n_in):
+    _, _, tctx, prm, P, t = setup(8192, 3, 60, 37)
+    N = prm.N
+    W = Stream(180 + n_in, synth.WEIGHT).ints(rows * cols, -t, t).reshape(rows, cols)
+    slots = empty_words(n_out * N)
+    tctx.zp_diagonals_rect(to_dev(W.astype(np.int64)), rows, cols, n_out, n_in, slots)
+    got = to_host(slots).reshape(n_out, N)
+    if n_out <= 8:
+        assert np.array_equal(got.astype(object), oracle.zp_diagonals_rect(W, n_out, n_in, N, t))
+    else:  # sampled rows of the large layout against the oracle's definition
+        want = oracle.zp_diagonals_rect(W[:, :], n_out, n_in, N, t)
+        for i in (0, 1, 511, 1023):
+            assert np.array_equal(got[i].astype(object), want[i]), i
+
+
+def test_fold_matches_oracle_word_for_word():
+    """out = ct + rotate(ct, g2) on arbitrary words (N=4096), against the
+    oracle's rotation and addition."""
+    base, ext, tctx, prm, P, t = setup(4096, 2, 50, 20)
+    N, L, n = prm.N, prm.L, 2
+    g2 = pow(5, 4, 2 * N)
+    sk = wl.secret_key(185, N)
+    dk, (a, e) = galois_key_dev(ext, prm, P, sk, g2, 186)
+    ksk = oracle.galois_key(sk, g2, a, e, prm, P)
+    ct = synth.uniform_mod(Stream(187, synth.UNIFORM), (n, 2, L, N), prm.q)
+    out = empty_words(ct.size)
+    ext.zp_fold(g2, n, to_dev(ct), dk, out, empty_words(ext.keyswitch_work_words(n)))
+    want = oracle.zp_fold_ct(ct, g2, ksk, prm, P)
+    assert np.array_equal(to_host(out).reshape(want.shape), want)
+    from paper_2506_11586_amd import heconv
+    d = to_dev(ct)
+    with pytest.raises(heconv.HeError) as exc:
+        ext.zp_fold(g2, n, d, dk, d, empty_words(ext.keyswitch_work_words(n)))
+    assert exc.value.status == heconv.HE_EINVAL
+
+
+@pytest.mark.parametrize("G", [1, 8])
+def test_rectangular_fc_2048_to_1000_decrypts(G):
+    """N=8192, L=3, 37-bit t: the 1000 x 2048 matrix as 1024 generalized
+    diagonals (as one chain, or as 8 chains) and one fold by 1024 slots:
+    every output decrypts to W x mod t."""
+    base, ext, tctx, prm, P, t = setup(8192, 3, 60, 37)
+    N, L, rows, cols, n_out, B = prm.N, prm.L, 1000, 2048, 1024, 3
+    sk = wl.secret_key(188, N)
+    dk, _ = galois_key_dev(ext, prm, P, sk, 5, 189)
+    gf = pow(5, n_out, 2 * N)
+    dkf, _ = galois_key_dev(ext, prm, P, sk, gf, 190)
+    W = Stream(191, synth.WEIGHT).below(rows * cols, t).reshape(rows, cols)
+    xv = Stream(192, synth.INPUT).below(B * cols, t).reshape(B, cols)
+    xs = np.stack([np.tile(x, N // cols) for x in xv]).astype(np.uint64)
+    ct, ct_ntt, skn = encrypted_inputs(base, tctx, prm, t, xs, sk, 193)
+    slots = empty_words(n_out * N)
+    tctx.zp_diagonals_rect(to_dev(W.astype(np.int64)), rows, cols, n_out, cols, slots)
+    coeffs = empty_words(n_out * N)
+    tctx.simd_encode(n_out, slots, coeffs)
+    w = empty_words(n_out * L * N)
+    ext.zp_encode_plain(n_out, coeffs, w)
+    z = empty_words(B * 2 * L * N)
+    if G == 1:
+        ext.zp_matvec(5, B, ct_ntt, w, n_out, dk, z, empty_words(ext.zp_work_words(B)))
+    else:
+        g2 = pow(5, n_out // G, 2 * N)
+        dk2, _ = galois_key_dev(ext, prm, P, sk, g2, 194)
+        ext.zp_matvec_grouped(5, B, ct_ntt, w, n_out, G, dk, g2, dk2, z, empty_words(ext.zp_grouped_work_words(B, G)))
+    out = empty_words(B * 2 * L * N)
+    ext.zp_fold(gf, B, z, dkf, out, empty_words(ext.keyswitch_work_words(B)))
+    y = decrypt_slots(base, tctx, prm, out, skn, B)
+    Wo = W.astype(object)
+    for b in range(B):
+        assert np.array_equal(y[b, :rows].astype(object), (Wo @ xv[b].astype(object)) % t), b
