@@ -614,7 +614,9 @@ def run_rotation(torch, heconv):
 def run_zp(torch, heconv):
     """The Z_P variant's linear kernel on a fully connected layer of
     ResNet-50's classifier shape, 2048 -> 1000, at 16 and at 64 images per
-    call: N=8192, L=3 (60-bit) plus a 60-bit special prime, t the largest
+    call (square diagonal layout, the same as batched chains, and the
+    generalized diagonals of a matrix with fewer rows than columns with
+    one rotate-and-add): N=8192, L=3 (60-bit) plus a 60-bit special prime, t the largest
     37-bit prime = 1 mod 2N; 2048 diagonals, so 2048 iterations (2047
     rotations of every ciphertext).  Inputs and weights are uniform mod t;
     the first images of each batch are decrypted and decoded on the GPU and
@@ -646,6 +648,17 @@ def run_zp(torch, heconv):
     w = torch.empty(n * L * N, **dev)
     ext.zp_encode_plain(n, coeffs, w)
     del slots, coeffs
+    # the same matrix as 1024 generalized diagonals of period 2048 (rows
+    # padded to 1024 < 2048 columns) and the Galois element of the fold
+    n_rect = 1024
+    slots = torch.empty(n_rect * N, **dev)
+    tctx.zp_diagonals_rect(W.reshape(-1), rows, cols, n_rect, cols, slots)
+    coeffs = torch.empty(n_rect * N, **dev)
+    tctx.simd_encode(n_rect, slots, coeffs)
+    w_rect = torch.empty(n_rect * L * N, **dev)
+    ext.zp_encode_plain(n_rect, coeffs, w_rect)
+    del slots, coeffs
+    g_fold = pow(g, n_rect, 2 * N)
     Wh = W.cpu().numpy().astype(object)
     keys2 = {}
     res = {"workload": f"FC {cols}->{rows}, N={N}, L={L} + one special prime, t={t} (37-bit prime), "
@@ -701,7 +714,41 @@ def run_zp(torch, heconv):
                                "decrypts_to_Wx": ok}
             del workg
         res["by_batch"][str(B)]["grouped"] = grouped
-        del ct, out
+        # fewer rows than columns: 1024 generalized diagonals (period 2048),
+        # then one rotate-and-add by 1024 slots
+        rect = {}
+        z = torch.empty_like(ct)
+        workf = torch.empty(ext.keyswitch_work_words(B), **dev)
+        for G in ((1, 8) if B == 16 else (1,)):
+            g2 = pow(g, n_rect // G, 2 * N) if G > 1 else 1
+            for gg in ([g2] if G > 1 else []) + [g_fold]:
+                if gg not in keys2:
+                    k2 = torch.empty_like(ksk)
+                    ext.galois_key(gg, sk, ka.reshape(-1), ke.reshape(-1), k2,
+                                   torch.empty(ext.galois_key_work_words(), **dev))
+                    keys2[gg] = k2
+            workg = torch.empty(ext.zp_grouped_work_words(B, G), **dev)
+
+            def run_rect():
+                if G == 1:
+                    ext.zp_matvec(g, B, ct, w_rect, n_rect, ksk, z, workg)
+                else:
+                    ext.zp_matvec_grouped(g, B, ct, w_rect, n_rect, G, ksk, g2, keys2[g2], z, workg)
+                ext.zp_fold(g_fold, B, z, keys2[g_fold], out, workf)
+
+            run_rect()
+            base.decrypt(B, out, skn, dec, torch.empty(B * L * N, **dev))
+            ys3 = torch.empty(B * N, **dev)
+            tctx.simd_decode(B, dec, ys3, torch.empty(B * N, **dev))
+            yr = ys3.view(B, N)[:, :rows].cpu().numpy()
+            ok = all(np.array_equal(yr[b].astype(object), (Wh @ xh[b]) % t) for b in range(checked))
+            msr = _timed(torch, run_rect, 3)
+            rect[str(G)] = {"ms": msr, "fc_layers_per_s": B / msr * 1e3,
+                            "zp_macs_per_s": B * rows * cols / (msr * 1e-3),
+                            "dependent_steps": n_rect // G + G - 1 + 1, "decrypts_to_Wx": ok}
+            del workg
+        res["by_batch"][str(B)]["rectangular"] = rect
+        del ct, out, z, workf
     for c in (base, ext, tctx):
         c.close()
     return res
