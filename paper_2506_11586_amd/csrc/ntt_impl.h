@@ -101,12 +101,33 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LOGE], int tid, cons
 // Move the thread's registers from the mapping at FROM to the mapping at TO
 // through LDS.  The leading barrier keeps the previous exchange's readers
 // ahead of this exchange's writers.
+//
+// Wave-local form.  In a mapping with LO <= 6 the 64 threads of wave w
+// (tid = 64w + i) hold exactly the elements whose index bits from 6+LOGE up
+// equal w: the low LO bits come from i, and tid >> LO = w*2^(6-LO) + (i >> LO).
+// When FROM and TO both satisfy this, each wave writes and reads only its
+// own aligned block of 2^(6+LOGE) elements (a disjoint range of LDS after
+// padding), so no other wave is involved and no workgroup barrier is needed.
+// The LDS operations of one wave are performed in issue order, and the
+// empty asm statements with a memory clobber keep the compiler from moving
+// a read above a write (for one lane the addresses differ, so it otherwise
+// could).  The exchange before a wave-local one either is wave-local too or
+// ends with every wave reading its own block, so the leading barrier can go
+// as well.  A cross-wave exchange keeps both barriers, which also order it
+// after any wave-local one.
 template <int LOGE, int FROM, int TO>
 __device__ __forceinline__ void exchange(uint64_t* lds, uint64_t (&x)[1 << LOGE], int tid) {
-  __syncthreads();
+  constexpr bool WAVE = FROM <= 6 && TO <= 6;
+  if constexpr (WAVE)
+    asm volatile("" ::: "memory");
+  else
+    __syncthreads();
 #pragma unroll
   for (int k = 0; k < (1 << LOGE); k++) lds[lds_pad(elem_index<LOGE, FROM>(tid, k))] = x[k];
-  __syncthreads();
+  if constexpr (WAVE)
+    asm volatile("" ::: "memory");
+  else
+    __syncthreads();
 #pragma unroll
   for (int k = 0; k < (1 << LOGE); k++) x[k] = lds[lds_pad(elem_index<LOGE, TO>(tid, k))];
 }
