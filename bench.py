@@ -34,6 +34,7 @@ from synth import Stream  # noqa: E402
 
 METRIC = "HE conv ct×pt MACs/s and layers/s (bit-exact), batched vs plain; p99 latency"
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_GIPS = 256 * 2.4  # G full-rate wave64 VALU instructions/s: one per CU per cycle, 256 CUs at 2.4 GHz
 
 
 def parse():
@@ -70,9 +71,10 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM traffic per launch from the committed rocprofv3 counter summary,
-    only while the kernel sources still hash to what was profiled."""
+def load_counters(kernel: str, workload: str):
+    """The committed rocprofv3 counter record of a kernel (HBM bytes per
+    launch, VALU instructions per launch), only while the kernel sources
+    still hash to what was profiled."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -82,7 +84,13 @@ def load_traffic(kernel: str, workload: str):
         return None
     if not rec or rec.get("sources") != kernel_sources_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM traffic per launch from the committed counter record, or None."""
+    rec = load_counters(kernel, workload)
+    return rec.get("bytes_per_launch") if rec else None
 
 
 def main():
@@ -208,6 +216,27 @@ def main():
     traffic = load_traffic(dom, wl_name)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+    # integer-VALU side: wave64 VALU instructions per launch from the SQ
+    # counters of the committed profile, over this run's live average
+    # duration, against one full-rate wave64 VALU instruction per CU per
+    # cycle (256 CUs x 2.4 GHz).  The 32-bit multiplies issue at half rate,
+    # so this counts each instruction once and is a lower bound on how busy
+    # the VALU is.
+    for k in ks:
+        rec = load_counters(k, wl_name)
+        if rec and rec.get("valu_insts_per_launch"):
+            rate = rec["valu_insts_per_launch"] / (kavg[k] * 1e-6) / 1e9
+            kernels[k]["valu"] = {"insts_per_launch": rec["valu_insts_per_launch"],
+                                  "achieved": round(rate, 1), "peak": VALU_PEAK_GIPS, "unit": "G wave64 instr/s",
+                                  "issue_frac": round(rate / VALU_PEAK_GIPS, 3)}
+    valu_k = "ntt_inv"
+    roofline_valu = None
+    if "valu" in kernels[valu_k]:
+        v = kernels[valu_k]["valu"]
+        roofline_valu = {"bound": "alu", "kernel": valu_k, "achieved": v["achieved"], "peak": VALU_PEAK_GIPS,
+                         "unit": v["unit"], "frac": v["issue_frac"],
+                         "note": "each VALU instruction counted once; half-rate 32-bit multiplies make the "
+                                 "busy fraction higher"}
 
     # the autotuner on the same layer, after the timed region: it starts from
     # the context's defaults (which time the headline above) and reports its
@@ -250,6 +279,8 @@ def main():
                            "note": "512 MiB read between launches (Infinity Cache 256 MB)"},
         "roofline": roofline,
     }
+    if roofline_valu is not None:
+        result["roofline_valu"] = roofline_valu
     if autotuned is not None:
         result["autotuned"] = autotuned
 
