@@ -8,6 +8,10 @@ What it picks:
 - the MAC's register tile: output channels x ciphertext rows per thread;
 - the output-channel MAC/iNTT pipeline of a one-image layer;
 - the two-grid forward NTT for small calls;
+- the MAC and inverse NTT as one fused kernel or two (one launch fewer on
+  small layers);
+- double-precision transforms where every prime is below 2^50 (the switch
+  is ignored otherwise);
 - for a batch: the schedule (one or two chains) and the MAC tile.
 
 A tuning changes only launch shapes, never a result word, so the tuner can
@@ -53,6 +57,8 @@ def layer_space(N: int) -> list[tuple[str, list[dict]]]:
         ("mac", [{"mac_mt": a, "mac_rt": b} for a, b in MAC_TILES]),
         ("layer_split", [{"layer_split": v} for v in (1, 2, 4)]),
         ("ntt_split_below", [{"ntt_split_below": v} for v in (0, 96, 160, 224, 320)]),
+        ("layer_fused", [{"layer_fused": v} for v in (0, 1)]),
+        ("ntt_fp64", [{"ntt_fp64": v} for v in (0, 1)]),
     ]
 
 
