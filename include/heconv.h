@@ -136,7 +136,15 @@ void he_ctx_destroy(he_ctx* ctx);
  * digits of a (ciphertext, modulus) pair by the key and stores only the two
  * sums (registers limit it to one workgroup per compute unit).  0 = the
  * steps as separate kernels.  Results are the same words in every mode.
- * Defaults: {3, 3, 512, 0, 0, 0, 1, 160, 1, 1}: 8 words per thread was measured faster
+ * ntt_inv_split_below: inverse NTTs of fewer than this many limb
+ * polynomials (N = 2^13 and 2^14) run as two grids of 128-thread
+ * workgroups, eight per 2^13 points (the stages on the low bits in blocks of
+ * 2^(n-6) consecutive entries, then the top six stages per residue); 0 =
+ * never.  Measured at N = 2^13: 9.5-11.0 against 13.0-13.9 us for 3 to 96
+ * limb polynomials, 14.4 against 14.2 for 144, 16.8 against 14.8 for 192.
+ * At N = 2^12 one workgroup per polynomial was faster at every count (7.5
+ * against 9.7 us), so that size never splits.
+ * Defaults: {3, 3, 512, 0, 0, 0, 1, 160, 1, 1, 128}: 8 words per thread was measured faster
  * than 16 at every count at N = 8192 (768 limb polys: 47.7 against 51.4 us
  * inverse); N = 16384 always uses 16.  The channel pipeline (layer_split)
  * was measured slower than the plain order on 64->64, 128->128 and
@@ -151,6 +159,7 @@ typedef struct {
   uint32_t ntt_split_below;
   uint32_t ntt_fp64;
   uint32_t ks_fused;
+  uint32_t ntt_inv_split_below;
 } he_tuning;
 
 he_status he_ctx_get_tuning(const he_ctx* ctx, he_tuning* out);

@@ -7,7 +7,7 @@ What it picks:
   separately for small and large calls;
 - the MAC's register tile: output channels x ciphertext rows per thread;
 - the output-channel MAC/iNTT pipeline of a one-image layer;
-- the two-grid forward NTT for small calls;
+- the two-grid forward and inverse NTTs for small calls;
 - the MAC and inverse NTT as one fused kernel or two (one launch fewer on
   small layers);
 - double-precision transforms where every prime is below 2^50 (the switch
@@ -57,6 +57,7 @@ def layer_space(N: int) -> list[tuple[str, list[dict]]]:
         ("mac", [{"mac_mt": a, "mac_rt": b} for a, b in MAC_TILES]),
         ("layer_split", [{"layer_split": v} for v in (1, 2, 4)]),
         ("ntt_split_below", [{"ntt_split_below": v} for v in (0, 96, 160, 224, 320)]),
+        ("ntt_inv_split_below", [{"ntt_inv_split_below": v} for v in (0, 64, 128, 192)]),
         ("layer_fused", [{"layer_fused": v} for v in (0, 1)]),
         ("ntt_fp64", [{"ntt_fp64": v} for v in (0, 1)]),
     ]

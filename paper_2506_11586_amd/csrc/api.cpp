@@ -135,13 +135,15 @@ he_status dev_err(hipError_t e) { return e == hipSuccess ? HE_OK : HE_EDEVICE; }
 
 // Every transform of the library goes through here: double precision when
 // all primes allow it (and the tuning asks for it), else the integer
-// kernels -- for a small forward count, in two grids.
+// kernels -- for a small count, in two grids.
 hipError_t ntt_run(const he_ctx* c, bool inverse, uint64_t* polys, uint64_t n, hipStream_t st, bool nt = false) {
   if (c->fp64_ok && c->tune.ntt_fp64)
     return heconv::ntt_f64_launch(inverse, c->logN, ntt_loge(c, n), polys, n, c->L, inverse ? c->d_inv64 : c->d_fwd64,
                                   c->d_fc, st);
   if (!inverse && n * c->L < c->tune.ntt_split_below && heconv::ntt_fwd_split_supported(c->logN))
     return heconv::ntt_fwd_split_launch(c->logN, polys, n, c->L, c->d_fwd, c->d_lc, st);
+  if (inverse && n * c->L < c->tune.ntt_inv_split_below && heconv::ntt_inv_split_supported(c->logN))
+    return heconv::ntt_inv_split_launch(c->logN, polys, n, c->L, c->d_inv, c->d_lc, st);
   return heconv::ntt_launch(inverse, c->logN, ntt_loge(c, n), polys, n, c->L, inverse ? c->d_inv : c->d_fwd, c->d_lc,
                             st, nt);
 }

@@ -17,6 +17,10 @@ hipError_t ntt_launch(bool inverse, uint32_t logN, uint32_t loge, uint64_t* poly
 // Forward NTT in two grids (first six stages by residue class, the rest by
 // block), for counts too small to occupy every compute unit; logN 12..14.
 bool ntt_fwd_split_supported(uint32_t logN);
+// the inverse in two grids (N = 2^13, 2^14)
+bool ntt_inv_split_supported(uint32_t logN);
+hipError_t ntt_inv_split_launch(uint32_t logN, uint64_t* polys, uint64_t n_rns_polys, uint32_t L, const Tw* tw,
+                                const LimbConst* lc, hipStream_t st);
 hipError_t ntt_fwd_split_launch(uint32_t logN, uint64_t* polys, uint64_t n_rns_polys, uint32_t L, const Tw* tw,
                                 const LimbConst* lc, hipStream_t st);
 

@@ -64,10 +64,11 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LOGE], int tid, cons
 
 // Inverse stages u from LOGE-1 down to U0 of the pass at LO.  With LAST, the
 // stage on the top bit (u = 0 of the pass at n-LOGE) also applies N^-1 and
-// leaves canonical values.
+// leaves canonical values.  jb as in fwd_pass (a block's first element, for
+// the stages on bits below the block size; never with LAST).
 template <int LOGN, int LOGE, int LO, int U0, bool LAST>
 __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LOGE], int tid, const Tw* __restrict__ tw,
-                                         const LimbConst& c) {
+                                         const LimbConst& c, uint32_t jb = 0) {
   const int high = tid >> LO;
   const uint64_t q2 = c.two_q;
 #pragma unroll
@@ -86,7 +87,7 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LOGE], int tid, cons
     }
 #pragma unroll
     for (int g = 0; g < (1 << u); g++) {
-      const Tw t = tw[(1 << s) + (high << u) + g];
+      const Tw t = tw[(1 << s) + (jb >> (LO + LOGE - u)) + (high << u) + g];
 #pragma unroll
       for (int e = 0; e < half; e++) {
         const int k0 = g * 2 * half + e, k1 = k0 + half;

@@ -298,6 +298,52 @@ def test_ntt_forward_two_grid_split(N, L, bits, n_rns):
     assert np.array_equal(got, oracle.ntt(x, prm))
 
 
+@pytest.mark.parametrize("N,L,bits", [(8192, 3, 60), (16384, 2, 60), (16384, 3, 49)])
+@pytest.mark.parametrize("n_rns", [1, 3, 8, 40])
+def test_ntt_inverse_two_grid_split(N, L, bits, n_rns):
+    """The two-grid inverse NTT (forced for every count; N = 2^13 and 2^14,
+    the sizes that use it) against the oracle, and the round trip with the
+    two-grid forward; counts with and without the XCD grouping, lazy-range
+    edge words included."""
+    ctx, prm = ctx_and_prm(N, L, bits)
+    before = ctx.get_tuning().as_dict()
+    ctx.set_tuning(ntt_inv_split_below=1 << 30, ntt_split_below=1 << 30, ntt_fp64=0)
+    x = rand_polys(11 * N + n_rns, n_rns, prm)
+    x[0] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)
+    x[-1, 0, :4] = [0, 1, 2, 0]
+    d = to_dev(x)
+    ctx.ntt_inv(d, n_rns)
+    got = to_host(d).reshape(x.shape)
+    ctx.ntt_fwd(d, n_rns)
+    back = to_host(d).reshape(x.shape)
+    ctx.set_tuning(**before)
+    assert np.array_equal(got, oracle.intt(x, prm))
+    assert np.array_equal(back, x)
+
+
+def test_layer_with_both_split_transforms():
+    """he_conv_layer with the forward and the inverse as two grids each,
+    against the oracle's flow (N = 8192, L = 3)."""
+    ctx, prm = ctx_and_prm(8192, 3, 60)
+    before = ctx.get_tuning().as_dict()
+    ctx.set_tuning(ntt_inv_split_below=1 << 30, ntt_split_below=1 << 30)
+    shape = (9, 12, 12, 7, 3, 3, 1, 1)
+    cv = wl.conv_of(shape)
+    d = ctx.plan(shape)
+    g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+    x = rand_polys(73, g.CB * g.S * 2, prm)
+    K = Stream(74, synth.WEIGHT).ints(cv.M * cv.C * 9, -2 ** 8, 2 ** 8).reshape(cv.M, cv.C, 3, 3)
+    s = ctx.sizes(d)
+    wntt = empty_words(s.w_words)
+    ctx.encode_weights(d, to_dev(K), wntt)
+    out = empty_words(s.out_cts * 2 * prm.L * prm.N)
+    ctx.conv_layer(d, 1, to_dev(x), wntt, out)
+    ctx.set_tuning(**before)
+    want = oracle.conv_layer_ntt(x.reshape(1, g.CB, g.S, 2, prm.L, prm.N), oracle.encode_weights(K, cv, g, prm), 1, g,
+                                 cv.M, prm)
+    assert np.array_equal(to_host(out).reshape(want.shape), want)
+
+
 def test_layer_largest_ring():
     """he_conv_layer at N = 2^14 (16 words per thread; the two-grid forward
     transform for a small count) against the oracle's flow."""
