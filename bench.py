@@ -792,7 +792,7 @@ def run_zp(torch, heconv):
         rect = {}
         z = torch.empty_like(ct)
         workf = torch.empty(ext.keyswitch_work_words(B), **dev)
-        for G in ((1, 8) if B == 16 else (1,)):
+        for G in ((1, 8) if B == 16 else (1, 2)):
             g2 = pow(g, n_rect // G, 2 * N) if G > 1 else 1
             for gg in ([g2] if G > 1 else []) + [g_fold]:
                 if gg not in keys2:
