@@ -429,13 +429,24 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
                 "ctpt_macs_per_pass": macs, "plain_ms": t_plain, "batched_ms": t_batch,
                 "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_batch * 1e3,
                 "bit_exact_vs_plain": bool(exact)}
+    # the batched form is the autotuner's pick when it ran (schedule, MAC
+    # tile and NTT grouping chosen by measurement), else the fixed form
+    fixed = {"batched_ms": t_batch, "batched_layers_per_s": n / t_batch * 1e3,
+             "form": "two chains of three grids, tiles by shape, one hipGraph", "bit_exact_vs_plain": bool(exact)}
+    if tuned is not None:
+        mt, rt = tuned["tuning"]["mac_mt"], tuned["tuning"]["mac_rt"]
+        tile = "by shape" if mt == 0 else f"{mt}x{rt}"
+        t_b, ok, form = tuned["batched_ms"], tuned["bit_exact_vs_plain"] and exact, (
+            f"autotuned: {tuned['schedule']} of three grids (forward NTTs, MAC tiles {tile}, inverse NTTs), "
+            "one hipGraph")
+    else:
+        t_b, ok, form = t_batch, exact, fixed["form"]
     return {"workload": cfg["name"], "layers": n, "ctpt_macs_per_pass": macs, "out_cts_per_pass": out_cts,
-            "plain_ms": t_plain, "batched_ms": t_batch,
-            "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_batch * 1e3,
-            "plain_ctpt_macs_per_s": macs / t_plain * 1e3, "batched_ctpt_macs_per_s": macs / t_batch * 1e3,
-            "speedup": t_plain / t_batch, "bit_exact_vs_plain": bool(exact),
-            "batched_form": "two chains of three grids (forward NTTs, MAC tiles, inverse NTTs), one hipGraph",
-            **({"autotuned": tuned} if tuned is not None else {})}
+            "plain_ms": t_plain, "batched_ms": t_b,
+            "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_b * 1e3,
+            "plain_ctpt_macs_per_s": macs / t_plain * 1e3, "batched_ctpt_macs_per_s": macs / t_b * 1e3,
+            "speedup": t_plain / t_b, "bit_exact_vs_plain": bool(ok), "batched_form": form,
+            "fixed_form": fixed, **({"autotuned": tuned} if tuned is not None else {})}
 
 
 def run_stem_polyphase(torch, heconv):
