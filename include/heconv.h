@@ -26,7 +26,8 @@
  *  - NTT form: entry i of a limb is the evaluation of the polynomial at
  *    psi_l^(2*brv(i)+1), brv = bit reversal over log2 N bits, psi_l the
  *    smallest primitive 2N-th root of unity mod q_l (App. C.1).
- *  - No entry point allocates device memory except he_ctx_create.
+ *  - No entry point allocates device memory except he_ctx_create and
+ *    he_batch_create.
  */
 #ifndef HECONV_H
 #define HECONV_H
@@ -89,7 +90,8 @@ const char* he_status_str(he_status s);
  * outside [20, 60], or fewer than L such primes exist. */
 he_status he_gen_primes(uint32_t N, uint32_t bits, uint32_t L, uint64_t* q_out);
 
-/* Create a context on the current HIP device: checks the parameters, picks
+/* Create a context on the current HIP device (the ring Z_Q[X]/(X^N+1) of
+ * Sec. 2.1 in RNS form, App. C): checks the parameters, picks
  * psi_l (the smallest primitive 2N-th root of unity mod q_l), builds the
  * twiddle tables (powers of psi in bit-reversed order with their Shoup
  * quotients, N^-1) and copies them to the device.  *out receives the
@@ -186,7 +188,8 @@ he_status he_plan_conv_host(uint32_t N, uint32_t L, he_conv_desc* io, uint32_t b
  * 2^62 with q = 1 mod 2N. */
 he_status he_min_root(uint64_t q, uint32_t N, uint64_t* psi_out);
 
-/* Sizes for a planned layer (per image): CB = ceil(C/Cw) channel blocks,
+/* Sizes for a planned layer (per image; the ciphertext counts of the
+ * coefficient encoding of Sec. 6.1 under the layout above): CB = ceil(C/Cw) channel blocks,
  * S spatial tiles, in_cts = CB*S, out_cts = M*S, w_words = M*CB*L*N.  Any
  * output pointer may be NULL.  HE_ESHAPE if the descriptor is invalid. */
 he_status he_conv_sizes(const he_ctx* ctx, const he_conv_desc* desc, uint32_t* CB, uint32_t* S,
@@ -203,7 +206,8 @@ he_status he_encode_weights(const he_ctx* ctx, const he_conv_desc* desc, const i
  * (App. C.1).  n = 0 is a no-op. */
 he_status he_ntt_fwd(const he_ctx* ctx, uint64_t* d_polys, uint64_t n, void* stream);
 
-/* Inverse NTT, in place: d_polys[n][L][N] from NTT form back to
+/* Inverse NTT, in place (App. C.1; Sec. 6.2: only the final results leave
+ * the NTT domain): d_polys[n][L][N] from NTT form back to
  * coefficients (including the factor N^-1).  The input is read and the
  * result written non-temporally (streamed past the caches: a layer's MAC
  * output is read once and its result not again soon), as he_conv_ntt_mac
@@ -229,7 +233,9 @@ he_status he_conv_ntt_mac(const he_ctx* ctx, const he_conv_desc* desc, uint32_t 
 he_status he_conv_mac_intt(const he_ctx* ctx, const he_conv_desc* desc, uint32_t B, const uint64_t* d_in_ntt,
                            const uint64_t* d_wntt, uint64_t* d_out, void* stream);
 
-/* The whole online layer: forward NTT of the B*CB*S input ciphertexts in
+/* The whole online layer (Sec. 6.2, NTT preprocessing: inputs transformed
+ * on receipt, every MAC in the NTT domain, results transformed back):
+ * forward NTT of the B*CB*S input ciphertexts in
  * place (d_in is clobbered: it holds their NTT form afterwards), the MAC,
  * then the inverse NTT of the B*M*S output ciphertexts.
  * d_in: [B][CB][S][2][L][N] coefficient form; d_out: [B][M][S][2][L][N]

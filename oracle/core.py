@@ -345,15 +345,16 @@ def pack_weights(K: np.ndarray, cv: Conv, g: Geometry, prm: Params) -> np.ndarra
     M, C, kh, kw = K.shape
     HW = g.Hw * g.Ww
     out = np.zeros((M, g.CB, prm.L, prm.N), dtype=np.uint64)
-    for m in range(M):
-        for c in range(C):
-            cb, cc = divmod(c, g.Cw)
-            for i in range(kh):
-                for j in range(kw):
-                    idx = g.O - cc * HW - i * g.Ww - j
-                    v = int(K[m, c, i, j])
-                    for l, q in enumerate(prm.q):
-                        out[m, cb, l, idx] = v % q
+    K = np.asarray(K, dtype=np.int64)
+    for c in range(C):
+        cb, cc = divmod(c, g.Cw)
+        for i in range(kh):
+            for j in range(kw):
+                idx = g.O - cc * HW - i * g.Ww - j
+                v = K[:, c, i, j]  # every output channel at once
+                for l, q in enumerate(prm.q):
+                    # signed lift into [0, q): integer floor-mod by q < 2^63
+                    out[:, cb, l, idx] = np.mod(v, np.int64(q)).astype(np.uint64)
     return out
 
 

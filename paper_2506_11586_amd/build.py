@@ -1,39 +1,65 @@
-"""Build step: compile the HIP sources into paper_2506_11586_amd/_lib/libheconv.so (gfx950)."""
+"""Build step: compile the HIP sources into paper_2506_11586_amd/_lib/libheconv.so (gfx950).
+
+Each source is compiled to its own object in parallel (no device code is
+shared across translation units, so no relocatable device code is needed),
+then the objects are linked into one shared library.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
+OBJDIR = os.path.join(ROOT, "_build", "heconv")
 LIB = os.path.join(LIBDIR, "libheconv.so")
-SOURCES = ["api.cpp", "batch_api.cpp", "ntt.hip", "mac.hip", "batch.hip", "fused.hip", "protocol.hip", "client.hip", "ntt_split.hip", "ntt_fp64.hip", "rotate.hip", "zp.hip", "polyphase.hip"]
+SOURCES = ["api.cpp", "batch_api.cpp", "ntt.hip", "mac.hip", "batch.hip", "fused.hip", "protocol.hip", "client.hip",
+           "ntt_split.hip", "ntt_fp64.hip", "rotate.hip", "zp.hip", "polyphase.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed fp32 instructions are kept out of every device build
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(LIBDIR, exist_ok=True)
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _clean(text: str) -> str:
+    return "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l)
+
+
+def _compile(src: str) -> tuple[str, str]:
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
-    out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
+    out = _clean(r.stdout + r.stderr)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({r.returncode}):\n{out}")
-    if verbose and out.strip():
-        print(out, file=sys.stderr)
+        raise RuntimeError(f"hipcc failed on {os.path.basename(src)} ({r.returncode}):\n{out}")
+    return obj, out
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    os.makedirs(LIBDIR, exist_ok=True)
+    os.makedirs(OBJDIR, exist_ok=True)
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
+    if verbose:
+        print(f"{HIPCC} {' '.join(FLAGS)} -c <each of {len(srcs)} sources> ({jobs} jobs)", flush=True)
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(_compile, srcs))
+    for _, out in results:
+        if verbose and out.strip():
+            print(out, file=sys.stderr)
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *[o for o, _ in results], "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed ({r.returncode}):\n{_clean(r.stdout + r.stderr)}")
     os.replace(tmp, LIB)
     return LIB
 

@@ -89,11 +89,7 @@ class Stream:
 
 
 def _popcount(x: np.ndarray) -> np.ndarray:
-    x = x.astype(np.uint64)
-    c = np.zeros(x.shape, dtype=np.int64)
-    for b in range(64):
-        c += ((x >> np.uint64(b)) & np.uint64(1)).astype(np.int64)
-    return c
+    return np.bitwise_count(x.astype(np.uint64)).astype(np.int64)
 
 
 def uniform_mod(stream: Stream, shape, moduli) -> np.ndarray:

@@ -50,7 +50,10 @@ def test_ntt_forward_and_inverse(N, L, bits, loge, fp64):
     below 2^50) double-precision kernels, against the oracle."""
     ctx, prm = ctx_and_prm(N, L, bits)
     before = ctx.get_tuning().as_dict()
-    ctx.set_tuning(ntt_loge_small=loge, ntt_loge_large=loge, ntt_fp64=fp64, ntt_split_below=0)
+    # both two-grid forms off: the one-workgroup kernels at every N (the
+    # two-grid forms have their own tests)
+    ctx.set_tuning(ntt_loge_small=loge, ntt_loge_large=loge, ntt_fp64=fp64, ntt_split_below=0,
+                   ntt_inv_split_below=0)
     x = rand_polys(N + L, 3, prm)
     x[2] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)  # all q-1: lazy-range edge
     x[1, 0, :5] = [0, 1, 2, 3, 0]

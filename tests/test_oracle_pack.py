@@ -122,3 +122,26 @@ def test_output_slots_do_not_wrap():
     assert s.min() == g.O and s.max() < 8192
     max_in = g.Cw * g.Hw * g.Ww - 1
     assert max_in + g.O - 8192 < g.O
+
+
+def test_weight_lift_of_int64_extremes():
+    """The signed lift of every kernel value into [0, q_l) is the integer
+    residue v mod q_l, including the int64 extremes and values above q_l;
+    each value lands at coefficient O - cc*Hw*Ww - i*Ww - j of its block."""
+    prm = oracle.Params(8192, 3, 60, 2 ** 37)
+    cv = Conv(3, 4, 4, 2, 2, 2, 1, 0)
+    g = oracle.geometry(cv, 2, 4, 4)
+    vals = [-2 ** 63, 2 ** 63 - 1, -1, 0, prm.q[0], prm.q[1] + 5, -prm.q[2] - 7, 12345, -2 ** 12, 2 ** 12 - 1]
+    K = np.array([vals[k % len(vals)] for k in range(2 * 3 * 2 * 2)], dtype=np.int64).reshape(2, 3, 2, 2)
+    wc = oracle.pack_weights(K, cv, g, prm)
+    seen = np.zeros(wc.shape, dtype=bool)
+    for m in range(2):
+        for c in range(3):
+            cb, cc = divmod(c, g.Cw)
+            for i in range(2):
+                for j in range(2):
+                    idx = g.O - cc * 16 - i * 4 - j
+                    for l, q in enumerate(prm.q):
+                        assert int(wc[m, cb, l, idx]) == int(K[m, c, i, j]) % q
+                        seen[m, cb, l, idx] = True
+    assert not wc[~seen].any()
