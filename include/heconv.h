@@ -373,6 +373,22 @@ he_status he_keyswitch(const he_ctx* ext, uint64_t n, const uint64_t* d_ct, cons
 he_status he_rotate(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_ct, const uint64_t* d_ksk_ntt,
                     uint64_t* d_out, uint64_t* d_work, void* stream);
 
+/* For callers that cannot allocate device memory or pass a work buffer
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): he_rotate with its key-switching scratch taken from a fixed
+ * device array of the library instead of d_work.  The array holds
+ * HE_ROTATE_NOALLOC_MAX_WORDS uint64 words (64 MiB) on every GPU the call
+ * runs on, kept until the process ends; n is limited to what fits
+ * (he_keyswitch_work_words(ext, n) <= that: 51 ciphertexts at N = 8192 with
+ * 3 ciphertext primes), HE_ESHAPE beyond it.  No allocation and no library
+ * routine that allocates.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (several streams or host threads) race and
+ * must be serialised by the caller.  Arguments and results otherwise as
+ * he_rotate. */
+#define HE_ROTATE_NOALLOC_MAX_WORDS (8ull * 1024 * 1024)
+he_status he_rotate_noalloc(const he_ctx* ext, uint64_t g, uint64_t n, const uint64_t* d_ct,
+                            const uint64_t* d_ksk_ntt, uint64_t* d_out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Z_P variant: batched plaintext slots over a prime t and the linear kernel
  * (Sec. 6.1: each iteration multiplies the input by NTT-preprocessed

@@ -114,6 +114,7 @@ def _lib_handle():
         L.he_zp_matvec_grouped.argtypes = [vp, u64, u64, vp, vp, u32, u32, vp, u64, vp, vp, vp, vp]
         L.he_zp_diagonals_rect.argtypes = [vp, vp, u32, u32, u32, u32, vp, vp]
         L.he_zp_fold.argtypes = [vp, u64, u64, vp, vp, vp, vp, vp]
+        L.he_rotate_noalloc.argtypes = [vp, u64, u64, vp, vp, vp, vp]
         L.he_polyphase_desc.argtypes = [P(ConvDesc), P(ConvDesc)]
         L.he_polyphase_advised.argtypes = [u32, u32, P(ConvDesc), u32, P(i32)]
         L.he_polyphase_weights.argtypes = [P(ConvDesc), vp, vp, vp]
@@ -132,7 +133,7 @@ def _lib_handle():
                      "he_key_encode", "he_encrypt", "he_decrypt", "he_keyswitch_work_words", "he_automorph", "he_galois_key",
                      "he_keyswitch", "he_rotate", "he_simd_encode", "he_simd_decode", "he_zp_diagonals",
                      "he_zp_encode_plain", "he_zp_work_words", "he_zp_matvec", "he_zp_grouped_work_words",
-                     "he_zp_matvec_grouped", "he_zp_diagonals_rect", "he_zp_fold", "he_polyphase_desc",
+                     "he_zp_matvec_grouped", "he_zp_diagonals_rect", "he_zp_fold", "he_rotate_noalloc", "he_polyphase_desc",
                      "he_polyphase_advised",
                      "he_polyphase_weights", "he_polyphase_input"):
             getattr(L, name).restype = i32
@@ -441,6 +442,16 @@ class Context:
                                _ptr(ksk_ntt_dev, Lc * 2 * self.L * self.N, "ksk"), _ptr(out_dev, ct, "out"),
                                _ptr(work_dev, self.keyswitch_work_words(n), "work"), _stream(stream)),
                "he_rotate")
+
+    def rotate_noalloc(self, g: int, n: int, ct_dev, ksk_ntt_dev, out_dev, stream=None):
+        """he_rotate_noalloc: he_rotate with the library's fixed device scratch
+        (no work buffer, no allocation; calls on one GPU must not overlap)."""
+        Lc = self.L - 1
+        ct = n * 2 * Lc * self.N
+        _check(lib().he_rotate_noalloc(self._h, int(g), int(n), _ptr(ct_dev, ct, "ct"),
+                                       _ptr(ksk_ntt_dev, Lc * 2 * self.L * self.N, "ksk"), _ptr(out_dev, ct, "out"),
+                                       _stream(stream)),
+               "he_rotate_noalloc")
 
     # ---- Z_P variant (slot calls on a one-prime context over t) ----
 
