@@ -11,9 +11,10 @@ namespace heconv {
 // thread owns one k for a tile of MT output channels x RT rows (b, s, c).
 // Each operand is split into 30-bit halves and the four partial products
 // are accumulated exactly in 64-bit registers (16 channel blocks per
-// accumulator), then folded mod q once per 16 blocks.  Consecutive lanes
-// take consecutive k: every load and store is a coalesced 512-byte wave
-// access.
+// accumulator), then folded mod q once per 16 blocks; the folded residue
+// seeds the next 16 blocks' accumulators (its low 30 bits in a00, the rest
+// in a01), so no separate running sum is kept.  Consecutive lanes take
+// consecutive k: every load and store is a coalesced 512-byte wave access.
 // ---------------------------------------------------------------------------
 constexpr uint32_t MAC_CHUNK = 16;
 
@@ -80,6 +81,33 @@ __device__ __forceinline__ void mac_step(const uint64_t (&xr)[RT], const uint64_
     }
 }
 
+// Fold every (m, row) accumulator set of a tile into its residue mod q and
+// leave it as the seed of the next blocks: a00 = r mod 2^30, a01 = r >> 30,
+// a10 = a11 = 0 (the bounds of both folds hold for 16 blocks plus that
+// seed).  Primes 2^60 - delta with delta < 2^20 (c.pmd = delta) take the
+// shift-and-multiply-by-delta fold, other primes the Shoup fold.
+template <int MT, int RT>
+__device__ __forceinline__ void mac_fold(uint64_t (&a00)[MT][RT], uint64_t (&a01)[MT][RT], uint64_t (&a10)[MT][RT],
+                                         uint64_t (&a11)[MT][RT], const LimbConst& c) {
+  if (c.pmd) {
+#pragma unroll
+    for (int j = 0; j < MT; j++)
+#pragma unroll
+      for (int i = 0; i < RT; i++) {
+        const uint64_t r = fold30_pm(a00[j][i], a01[j][i], a10[j][i], a11[j][i], c.q, (uint32_t)c.pmd);
+        a00[j][i] = r & 0x3fffffffu, a01[j][i] = r >> 30, a10[j][i] = 0, a11[j][i] = 0;
+      }
+  } else {
+#pragma unroll
+    for (int j = 0; j < MT; j++)
+#pragma unroll
+      for (int i = 0; i < RT; i++) {
+        const uint64_t r = fold30(a00[j][i], a01[j][i], a10[j][i], a11[j][i], c);
+        a00[j][i] = r & 0x3fffffffu, a01[j][i] = r >> 30, a10[j][i] = 0, a11[j][i] = 0;
+      }
+  }
+}
+
 // One MAC tile: k-chunk kc (THREADS consecutive NTT points of limb
 // kc / (N/THREADS)), output channels mt*MT.., rows rt*RT.., for the calling
 // workgroup of THREADS threads.  c = constants of that limb.
@@ -123,21 +151,16 @@ __device__ __forceinline__ void mac_tile(cgword* __restrict__ in, cgword* __rest
   }
   const uint32_t lane = (uint32_t)tid * 8;
 
-  uint64_t res[MT][RT];
+  uint64_t a00[MT][RT], a01[MT][RT], a10[MT][RT], a11[MT][RT];
 #pragma unroll
   for (int j = 0; j < MT; j++)
 #pragma unroll
-    for (int i = 0; i < RT; i++) res[j][i] = 0;
+    for (int i = 0; i < RT; i++) a00[j][i] = a01[j][i] = a10[j][i] = a11[j][i] = 0;
 
   // Rows and channels past the end read row 0 / channel 0 (valid memory);
   // their sums are never stored, so every load is unconditional.
   for (uint32_t cb0 = 0; cb0 < CB; cb0 += MAC_CHUNK) {
     const uint32_t cb1 = cb0 + MAC_CHUNK < CB ? cb0 + MAC_CHUNK : CB;
-    uint64_t a00[MT][RT], a01[MT][RT], a10[MT][RT], a11[MT][RT];
-#pragma unroll
-    for (int j = 0; j < MT; j++)
-#pragma unroll
-      for (int i = 0; i < RT; i++) a00[j][i] = a01[j][i] = a10[j][i] = a11[j][i] = 0;
     uint32_t cb = cb0;
     // MAC_DEPTH channel blocks per step: all their loads are issued before
     // the first product, so that many loads per thread are in flight
@@ -161,18 +184,15 @@ __device__ __forceinline__ void mac_tile(cgword* __restrict__ in, cgword* __rest
       for (int j = 0; j < MT; j++) wr[j] = mac_load(wb[j], lane, (uint32_t)(cb * LN * 8));
       mac_step<MT, RT>(xr, wr, a00, a01, a10, a11);
     }
-#pragma unroll
-    for (int j = 0; j < MT; j++)
-#pragma unroll
-      for (int i = 0; i < RT; i++)
-        res[j][i] = csub(res[j][i] + fold30(a00[j][i], a01[j][i], a10[j][i], a11[j][i], c), c.q);
+    mac_fold<MT, RT>(a00, a01, a10, a11, c);
   }
 #pragma unroll
   for (int j = 0; j < MT; j++)
 #pragma unroll
     for (int i = 0; i < RT; i++)
       if (mv[j] && rv[i])  // non-temporal: streamed past the caches, which keep the weights
-        __builtin_nontemporal_store(res[j][i], &out[out_off[i] + (uint64_t)(mt * MT + j) * out_m_stride + (uint32_t)tid]);
+        __builtin_nontemporal_store(a00[j][i] | (a01[j][i] << 30),
+                                    &out[out_off[i] + (uint64_t)(mt * MT + j) * out_m_stride + (uint32_t)tid]);
 }
 
 }  // namespace heconv

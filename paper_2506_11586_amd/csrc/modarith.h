@@ -22,6 +22,7 @@ struct LimbConst {
   uint64_t delta, delta_sh;    // floor(Q/t) mod q and its Shoup quotient (0 if t is unusable)
   uint64_t negq, neg2q;        // 2^64 - q and 2^64 - 2q
   uint64_t r64_sh63;           // Shoup quotient of 2^64 mod q at scale 2^63
+  uint64_t pmd;                // delta when q = 2^60 - delta with delta < 2^20, else 0
 };
 
 // Device buffers are passed to the transform and MAC bodies as pointers in
@@ -108,6 +109,31 @@ struct Half30 {
 
 __device__ __forceinline__ Half30 split30(uint64_t x) {
   return Half30{(uint32_t)x & 0x3fffffffu, (uint32_t)(x >> 30)};
+}
+
+// Fold for a prime q = 2^60 - delta with delta < 2^20 (the largest primes
+// below 2^60 are of this form): 2^60 = delta mod q, so a value
+// lo + hi*2^60 is congruent to lo + hi*delta, which two rounds bring below
+// 2^60 + 2^45 < 2q.  Exact for every a00, a01, a10, a11 < 2^64 with
+// a11 + (a01 + a10) / 2^30 + a00 / 2^60 + 1 < 2^64, which sixteen blocks of
+// 30-bit products (each below (2^30-1)^2) plus a carried residue below 2^60
+// satisfy.  Three 32 x 32 multiply-adds and no 64 x 64 products.
+__host__ __device__ __forceinline__ uint64_t fold30_pm(uint64_t a00, uint64_t a01, uint64_t a10, uint64_t a11,
+                                                       uint64_t q, uint32_t delta) {
+  constexpr uint64_t M60 = (1ull << 60) - 1, M30 = (1ull << 30) - 1;
+  const uint64_t mid = a01 + a10;  // 65 bits: carry in mc
+  const uint64_t mc = mid < a01;
+  // T = a00 + mid*2^30 + a11*2^60 = s_lo + V*2^60 with s = a00 mod 2^60 + (mid mod 2^30)*2^30
+  const uint64_t s = (a00 & M60) + ((mid & M30) << 30);  // < 2^61
+  const uint64_t V = a11 + ((mid >> 30) | (mc << 34)) + ((a00 >> 60) + (s >> 60));
+  // T = s_lo + V*delta = A + P*2^32 (mod q), with V split into 32-bit halves
+  const uint64_t A = (uint64_t)(uint32_t)V * delta + (s & M60);  // < 2^61
+  const uint64_t P = (V >> 32) * (uint64_t)delta;                // < 2^52
+  const uint64_t Wlo = A + (P << 32);
+  const uint64_t Whi = (P >> 32) + (Wlo < A);  // W = Whi*2^64 + Wlo < 2^85
+  const uint64_t t = (Whi << 4) | (Wlo >> 60);  // W >> 60, < 2^25
+  const uint64_t X = (Wlo & M60) + t * delta;  // < 2^60 + 2^45 < 2q
+  return X >= q ? X - q : X;
 }
 
 // Exact sum of products in four accumulators: a00 + (a01 + a10)*2^30 +
