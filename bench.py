@@ -1,19 +1,24 @@
 """Benchmark of the HE convolution hot path on one MI355X.
 
-A step is one online layer solve -- forward NTT of the input ciphertexts,
-channel-block MAC against NTT-preprocessed weights, inverse NTT of the
-results (he_conv_layer) -- over one batch of seeded synthetic ciphertexts
-already resident in HBM.  The weights are NTT-preprocessed once before the
-timed region (the paper's offline step); its time is reported separately.
+A step is one pass of the whole hot path -- for every layer solve, forward
+NTT of its input ciphertexts, channel-block MAC against NTT-preprocessed
+weights, inverse NTT of the results -- over one batch of seeded synthetic
+ciphertexts already resident in HBM.  The weights are NTT-preprocessed once
+before the timed region (the paper's offline step); its time is reported
+separately.
 
-Default workload: 3x3 conv 64->64 on a 56x56 tensor, N=8192, three 60-bit
-primes, batch 1 (32 input / 128 output ciphertexts, 2048 ct x pt MACs).
+Headline workload: the bottleneck residual CNN (53 convolutions at 224
+input) for 16 images, N=8192, three 60-bit primes, all 848 layer solves
+resident at once (about 229 GiB), in its batched form (one hipGraph launch
+per pass), with the plain per-layer path (one he_conv_layer call per layer
+solve) timed beside it on the same buffers.
 
-Prints one JSON line.  `value` = ct x pt MACs per second; the line also
-carries layers/s, per-step p50/p99, the roofline of the dominant kernel
-(measured with HIP events on the launch stream), and the CPU oracle timed on
-a bounded sample of the same workload, which also checks the GPU output word
-for word.
+Prints one JSON line.  `value` = ct x pt MACs per second of the batched
+pass; the line also carries layers/s, per-pass p50/p99 of both forms, the
+rooflines of the dominant kernel (measured with HIP events on its launch
+stream), the CPU oracle timed on a bounded sample of the same workload
+(which also checks those layer solves word for word), and the other
+workloads as secondary fields.
 """
 from __future__ import annotations
 
@@ -50,28 +55,41 @@ PAPER_CONTEXT = {
             "resident ciphertexts (the fire-module CNN field is the closest workload)",
 }
 VALU_PEAK_GIPS = 256 * 2.4  # G full-rate wave64 VALU instructions/s: one per CU per cycle, 256 CUs at 2.4 GHz
+VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9  # full-rate 32-bit lane operations/s: 256 CUs x 64 lanes x 2.4 GHz
+MAD_RATE_FRAC = 1.0  # v_mad_u64_u32 issues at the full rate on gfx950 (the probe's mad_u64_u32 field: 0.975)
+# layer solves (image 0) the oracle recomputes in the CPU-baseline leg
+ORACLE_SAMPLE_LAYERS = [0, 2, 3, 12, 14, 16, 25, 26, 29, 44, 45, 48]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=20, help="timed batched passes of the headline workload")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed batched passes first")
+    ap.add_argument("--plain-steps", type=int, default=20, help="timed passes of the plain and per-layer forms")
+    ap.add_argument("--kernel-reps", type=int, default=5, help="instrumented passes for the per-grid durations")
+    ap.add_argument("--schedule", type=int, default=1, choices=[1, 2], help="chains of the headline batch")
+    ap.add_argument("--single-steps", type=int, default=200, help="timed steps of the 64->64 single layer")
+    ap.add_argument("--single-warmup", type=int, default=500)
     ap.add_argument("--workload", default="conv64_56x56", choices=["conv4_16x16", "conv64_56x56"],
-                    help="single-layer workload of the main line")
+                    help="workload of the single-layer section")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-headline", action="store_true", help="skip the batch-16 bottleneck CNN (about 230 GiB)")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-layer section")
+    ap.add_argument("--no-probes", action="store_true", help="skip the integer-VALU rate probes")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched fire-module CNN section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-client", action="store_true", help="skip the client-side encrypt/decrypt section")
     ap.add_argument("--no-rotation", action="store_true", help="skip the ciphertext rotation section")
     ap.add_argument("--no-zp", action="store_true", help="skip the Z_P linear-kernel section")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="skip the autotuner runs (main layer and fire-module batch)")
-    ap.add_argument("--no-bottleneck", action="store_true",
-                    help="skip the batch-16 bottleneck residual CNN section (about 230 GiB resident)")
+                    help="skip the autotuner runs (single layer and fire-module batch)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-sweep", type=float, nargs="*", default=[1000.0, 2000.0, 4000.0, 8000.0, 16000.0],
+                    help="offered rates (req/s) of the open-loop sweep")
+    ap.add_argument("--serve-sweep-requests", type=int, default=1500)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM counter scaling)")
     return ap.parse_args()
@@ -108,19 +126,12 @@ def load_traffic(kernel: str, workload: str):
     return rec.get("bytes_per_launch") if rec else None
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the HE convolution path runs on a single MI355X here "
-              "(run with --gpus 1).", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    from paper_2506_11586_amd import heconv
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
+def run_single_layer(torch, heconv, args):
+    """One layer solve repeated (he_conv_layer): by default the 3x3 conv
+    64->64 on a 56x56 tensor, N=8192, three 60-bit primes, one image (32
+    input / 128 output ciphertexts, 2048 ct x pt MACs), with the per-kernel
+    breakdown, the MAC's HBM roofline warm and with the caches flushed, the
+    autotuner's pick and the oracle's CPU rate on the same layer."""
     cfg = synth.WORKLOADS[args.workload]
     shape = cfg["layers"][0]
     N, L, bits, B = cfg["N"], cfg["L"], cfg["bits"], cfg["batch"]
@@ -162,23 +173,23 @@ def main():
 
     # timed region: K layer solves (the input buffer is re-transformed each
     # step; the kernels' work does not depend on the values)
-    for _ in range(args.warmup):
+    for _ in range(args.single_warmup):
         ctx.conv_layer(d, B, d_in, wntt, d_out)
     torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.single_steps + 1)]
     t0 = time.perf_counter()
     evs[0].record(stream)
-    for i in range(args.steps):
+    for i in range(args.single_steps):
         ctx.conv_layer(d, B, d_in, wntt, d_out)
         evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per_step = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    per_step = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.single_steps)])
     total_ms = evs[0].elapsed_time(evs[-1])
-    ms_per_step = total_ms / args.steps
+    ms_per_step = total_ms / args.single_steps
 
     # per-kernel breakdown: the same three launches, events between them
-    reps = max(20, args.steps // 4)
+    reps = max(20, args.single_steps // 4)
     ks = {"ntt_fwd": [], "mac": [], "ntt_inv": []}
     for _ in range(reps):
         a, b, c, e = (torch.cuda.Event(enable_timing=True) for _ in range(4))
@@ -272,15 +283,10 @@ def main():
                      "output_equals_default": same,
                      "note": "median of 20 launches per candidate; coordinate descent from the defaults"}
 
-    result = {
-        "metric": METRIC,
-        "value": macs / (ms_per_step * 1e-3),
-        "unit": "ct×pt MACs/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64", "data": "synthetic",
-        "config": {"workload": wl_name, "conv": dict(C=C, H=H, W=W, M=M, k=kh, stride=stride, pad=pad),
+    res = {
+        "workload": wl_name, "steps": args.single_steps, "warmup": args.single_warmup,
+        "value": macs / (ms_per_step * 1e-3), "unit": "ct×pt MACs/s", "ms_per_step": ms_per_step,
+        "config": {"conv": dict(C=C, H=H, W=W, M=M, k=kh, stride=stride, pad=pad),
                    "N": N, "L": L, "q_bits": bits, "t": f"2^{synth.T_BITS}", "batch": B,
                    "packing": dict(Cw=d.Cw, Hw=d.Hw, Ww=d.Ww, CB=sz.CB, S=sz.S),
                    "in_cts": n_in, "out_cts": n_out, "ctpt_macs_per_layer": macs, "path": "plain per-layer"},
@@ -291,24 +297,47 @@ def main():
         "kernels": kernels,
         "mac_cold_cache": {"avg_us": round(mac_cold_us, 3),
                            "GBps": round(kbytes["mac"] / (mac_cold_us * 1e-6) / 1e9, 1),
+                           "frac": round(kbytes["mac"] / (mac_cold_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                            "note": "512 MiB read between launches (Infinity Cache 256 MB)"},
         "roofline": roofline,
     }
     if roofline_valu is not None:
-        result["roofline_valu"] = roofline_valu
-    result["paper_context"] = PAPER_CONTEXT
+        res["roofline_valu"] = roofline_valu
     if autotuned is not None:
-        result["autotuned"] = autotuned
+        res["autotuned"] = autotuned
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"], res["bit_exact"] = cpu_baseline(args, cfg, ctx, d, sz, x_host, K_host, gpu_out)
+    ctx.close()
+    return res
 
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the HE convolution path runs on a single MI355X here "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2506_11586_amd import heconv
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    probes = None if args.no_probes else run_probes(torch, heconv)
+    result, pending = {}, None
+    if not args.no_headline:
+        result, pending = run_bottleneck_main(torch, heconv, args, probes)
+        torch.cuda.empty_cache()
+    if probes is not None:
+        result["valu_probes"] = probes
+    result["paper_context"] = PAPER_CONTEXT
+    if not args.no_single:
+        result["single_layer"] = run_single_layer(torch, heconv, args)
     if not args.no_batched:
         result["batched"] = run_batched(torch, heconv, tune=not args.no_autotune)
         result["batched_polyphase"] = run_batched(torch, heconv, polyphase=True)
         result["stem_polyphase_b16"] = run_stem_polyphase(torch, heconv)
-    bottleneck_pending = None
-    if not args.no_bottleneck:
-        torch.cuda.empty_cache()
-        result["bottleneck_b16"], bottleneck_pending = run_bottleneck(torch, heconv)
-        torch.cuda.empty_cache()
     if not args.no_serving:
         result["serving"] = run_serving(torch, heconv, args)
     if not args.no_client:
@@ -317,7 +346,6 @@ def main():
         result["rotation"] = run_rotation(torch, heconv)
     if not args.no_zp:
         result["zp_fc"] = run_zp(torch, heconv)
-
     if args.copy_probe:
         src = torch.ones(32 << 20, dtype=torch.int64, device="cuda")
         dst = torch.empty_like(src)
@@ -325,15 +353,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         result["copy_probe_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
-
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"], result["bit_exact"] = cpu_baseline(args, cfg, ctx, d, sz, x_host, K_host, gpu_out)
-        if bottleneck_pending is not None:
-            n_s, ok = check_bottleneck_samples(bottleneck_pending)
-            result["bottleneck_b16"]["sampled_words_vs_oracle"] = n_s
-            result["bottleneck_b16"]["bit_exact"] = ok and result["bottleneck_b16"]["plain_equals_batched"]
+    if pending is not None and not args.no_cpu_baseline:
+        result["cpu_baseline"], chk = cpu_baseline_bottleneck(args, pending)
+        result["oracle_checked_layer_solves"] = chk
+        result["bit_exact"] = bool(result["batched_equals_plain_all_words"] and chk["words_equal"])
     print(json.dumps(result), flush=True)
-    ctx.close()
 
 
 def _timed(torch, fn, reps, warm=2, warm_s=0.1):
@@ -483,26 +507,54 @@ def run_stem_polyphase(torch, heconv):
     return res
 
 
-def run_bottleneck(torch, heconv):
-    """Bottleneck residual CNN (53 convs at 224 input, batch 16, N=8192, L=3)
-    with every layer solve of all 16 images resident at once: NTT-form
-    weights about 62 GiB, inputs 8 GiB, outputs about 159 GiB.  Plain: 53
-    he_conv_layer calls of 16 images each; batched: one he_batch (two chains
-    of three grids, one hipGraph).  Sampled output words of both are compared
-    with the oracle's definition, and the two outputs with each other by
-    per-layer checksums (sum and sum of squares of the words, mod 2^64).
-    Returns the result and the sampled words with their inputs; the oracle
-    compares them in the CPU-baseline leg (check_bottleneck_samples).
+def run_probes(torch, heconv):
+    """Integer-VALU rates measured by the library's probes (heconv_probe.h):
+    the v_mad_u64_u32 / v_mul_hi_u32 / v_mul_lo_u32 / v_add_u32 lane rates
+    and the ceilings of the MAC's and the transforms' own instruction mixes
+    (operands in registers, no memory traffic).  Best of three runs each."""
+    ctx = heconv.Context(8192, heconv.gen_primes(8192, 60, 3))
+    spec = [("mad_u64_u32", heconv.PROBE_MAD_U64_U32, 3000, "lane ops/s"),
+            ("mul_hi_u32", heconv.PROBE_MUL_HI_U32, 3000, "lane ops/s"),
+            ("mul_lo_u32", heconv.PROBE_MUL_LO_U32, 3000, "lane ops/s"),
+            ("add_u32", heconv.PROBE_ADD_U32, 3000, "lane ops/s"),
+            ("mac_mix", heconv.PROBE_MAC_MIX, 300, "modmul-adds/s (4x4 tile, fold per 16 blocks)"),
+            ("intt_mix", heconv.PROBE_INTT_MIX, 900, "butterflies/s"),
+            ("ntt_mix", heconv.PROBE_NTT_MIX, 900, "butterflies/s")]
+    out = {}
+    for name, which, iters, unit in spec:
+        out[name] = {"rate": max(ctx.probe_valu(which, iters) for _ in range(3)), "unit": unit}
+    full = VALU_LANE_OPS_PEAK
+    for k in ("mad_u64_u32", "mul_hi_u32", "mul_lo_u32", "add_u32"):
+        out[k]["frac_of_full_rate"] = round(out[k]["rate"] / full, 3)
+    ctx.close()
+    return out
 
-    Input words are drawn on the device (torch's seeded generator, uniform
-    mod q_l): 8 GiB of host-drawn words would dominate the set-up time.  The
-    sampled inputs are read back from the device before the first run."""
+
+def run_bottleneck_main(torch, heconv, args, probes):
+    """The headline: the bottleneck residual CNN (53 convs at 224 input, 16
+    images, N=8192, L=3 60-bit primes), every layer solve of all 16 images
+    resident at once (NTT-form weights about 62 GiB, inputs 8 GiB, outputs
+    about 159 GiB).
+
+      batched:  the 53 layer jobs of 16 images each in one batch, replayed as
+                one hipGraph launch per pass (the step of this bench);
+      plain:    the plain per-layer path, one he_conv_layer call per layer
+                solve (one image, one layer): 848 calls per pass;
+      per-layer x16: one he_conv_layer call of 16 images per layer.
+
+    All three use the same packing (planned for 16 images) and the same
+    ciphertexts.  Batched and plain outputs are compared word for word on
+    the device for every layer; the oracle checks sampled layer solves in
+    the CPU-baseline leg.  Input words are drawn on the device (torch's
+    seeded generator, uniform mod q_l)."""
     cfg = synth.WORKLOADS["bottleneck_cnn_b16"]
     N, L, bits, B = cfg["N"], cfg["L"], cfg["bits"], cfg["batch"]
     ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), 2 ** synth.T_BITS)
     qd = torch.tensor(ctx.q, dtype=torch.int64, device="cuda").view(1, L, 1)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64).copy()).cuda()
-    descs, sizes, Ks, wntts, ins, outs, macs = [], [], [], [], [], [], 0
+    ct_words = 2 * L * N
+    descs, sizes, Ks, wntts, ins, outs = [], [], [], [], [], []
+    macs = 0
     t_enc = 0.0
     for i, shape in enumerate(cfg["layers"]):
         C, H, W, M, kh, kw, stride, pad = shape
@@ -518,102 +570,207 @@ def run_bottleneck(torch, heconv):
         t_enc += time.perf_counter() - t0
         del Kd
         descs.append(d), sizes.append(s), Ks.append(K), wntts.append(w)
-        ins.append(torch.empty(B * s.in_cts * 2 * L * N, dtype=torch.int64, device="cuda"))
-        outs.append(torch.empty(B * s.out_cts * 2 * L * N, dtype=torch.int64, device="cuda"))
+        ins.append(torch.empty(B * s.in_cts * ct_words, dtype=torch.int64, device="cuda"))
+        outs.append(torch.empty(B * s.out_cts * ct_words, dtype=torch.int64, device="cuda"))
         macs += B * M * s.CB * s.S
+    n_solves = len(descs) * B
     gen = torch.Generator(device="cuda")
 
-    def fill_inputs():
-        for j, x in enumerate(ins):
-            gen.manual_seed(4000 + j)
-            v = x.view(-1, L, N)
-            for r0 in range(0, v.shape[0], 4096):
-                r1 = min(v.shape[0], r0 + 4096)
-                v[r0:r1] = torch.randint(0, 2 ** 62, (r1 - r0, L, N), generator=gen, device="cuda") % qd
+    def fill_input(j):
+        gen.manual_seed(4000 + j)
+        v = ins[j].view(-1, L, N)
+        for r0 in range(0, v.shape[0], 4096):
+            r1 = min(v.shape[0], r0 + 4096)
+            v[r0:r1] = torch.randint(0, 2 ** 62, (r1 - r0, L, N), generator=gen, device="cuda") % qd
 
-    def checksums():
-        out = []
-        for o in outs:
-            s1 = s2 = 0
-            for c0 in range(0, o.numel(), 1 << 27):
-                ch = o[c0:c0 + (1 << 27)]
-                s1 += int(ch.sum())
-                s2 += int((ch * ch).sum())
-            out.append((s1 % 2 ** 64, s2 % 2 ** 64))
-        return out
+    for j in range(len(ins)):
+        fill_input(j)
+    # layer solves the oracle checks in the CPU-baseline leg: image 0 of
+    # these layers, input read back before the first pass
+    sample_layers = [j for j in ORACLE_SAMPLE_LAYERS if j < len(descs)]
+    samples = {j: ins[j][:sizes[j].in_cts * ct_words].cpu().numpy().view(np.uint64).copy() for j in sample_layers}
 
-    # sampled words: (job, image, m, s, comp, limb, k), inputs read back now
-    fill_inputs()
-    rng = Stream(cfg["seed"], synth.MIX)
-    picks = []
-    for j in np.linspace(0, len(descs) - 1, 8).astype(int):
-        s, K = sizes[j], Ks[j]
-        M = K.shape[0]
-        b, m, sp, c, l, k = (int(rng.below(1, v)[0]) for v in (B, M, s.S, 2, L, N))
-        img = ins[j].view(B, -1)[b].cpu().numpy().view(np.uint64).reshape(1, s.CB, s.S, 2, L, N).copy()
-        picks.append((int(j), b, m, sp, c, l, k, img))
+    sched = heconv.SCHED_ONE_CHAIN if args.schedule == 1 else heconv.SCHED_TWO_CHAINS
+    jobs = [(d, B, x, w, o) for d, x, w, o in zip(descs, ins, wntts, outs)]
+    bt = heconv.Batch(ctx, jobs, schedule=sched)
+    bt.launch(graph=True)
+    bt.status()
+    sample_out = {j: outs[j][:sizes[j].out_cts * ct_words].cpu().numpy().view(np.uint64).copy()
+                  for j in sample_layers}
+
+    # every output word of the batched pass against the plain per-layer path
+    # (one he_conv_layer call per image), layer by layer into a scratch buffer
+    scratch = torch.empty(max(o.numel() for o in outs), dtype=torch.int64, device="cuda")
+    equal_layers = 0
+    for j, (d, s) in enumerate(zip(descs, sizes)):
+        fill_input(j)
+        iw, ow = s.in_cts * ct_words, s.out_cts * ct_words
+        for b in range(B):
+            ctx.conv_layer(d, 1, ins[j][b * iw:(b + 1) * iw], wntts[j], scratch[b * ow:(b + 1) * ow])
+        equal_layers += bool(torch.equal(scratch[:B * ow], outs[j]))
+    del scratch
     torch.cuda.synchronize()
 
-    def sampled():
-        got = []
-        for j, b, m, sp, c, l, k, _ in picks:
-            s = sizes[j]
-            idx = ((((b * Ks[j].shape[0] + m) * s.S + sp) * 2 + c) * L + l) * N + k
-            got.append(int(outs[j][idx].item()) % 2 ** 64)
-        return got
+    def plain_pass():
+        for d, s, x, w, o in zip(descs, sizes, ins, wntts, outs):
+            iw, ow = s.in_cts * ct_words, s.out_cts * ct_words
+            for b in range(B):
+                ctx.conv_layer(d, 1, x[b * iw:(b + 1) * iw], w, o[b * ow:(b + 1) * ow])
 
-    def plain():
+    def per_layer_pass():
         for d, x, w, o in zip(descs, ins, wntts, outs):
             ctx.conv_layer(d, B, x, w, o)
 
-    plain()
-    torch.cuda.synchronize()
-    got_plain, sums_plain = sampled(), checksums()
-    fill_inputs()
-    for o in outs:
-        o.zero_()
-    jobs = [(d, B, x, w, o) for d, x, w, o in zip(descs, ins, wntts, outs)]
-    bt = heconv.Batch(ctx, jobs, schedule=heconv.SCHED_TWO_CHAINS)
-    bt.launch(graph=True)
-    bt.status()
-    got_batch, sums_batch = sampled(), checksums()
-    t_plain = _timed(torch, plain, 3, warm=1)
-    t_batch = _timed(torch, lambda: bt.launch(graph=True), 3, warm=1)
-    n = len(descs) * B
-    res = {"workload": cfg["name"], "layer_solves": n, "ctpt_macs_per_pass": macs,
-           "resident_GiB": round(sum(t.numel() * 8 for t in wntts + ins + outs) / 2 ** 30, 1),
-           "offline_encode_ms": t_enc * 1e3,
-           "plain_ms": t_plain, "batched_ms": t_batch,
-           "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_batch * 1e3,
-           "plain_ctpt_macs_per_s": macs / t_plain * 1e3, "batched_ctpt_macs_per_s": macs / t_batch * 1e3,
-           "speedup": t_plain / t_batch,
-           "plain_equals_batched": bool(sums_plain == sums_batch and got_plain == got_batch)}
-    pending = {"q": list(ctx.q), "picks": [(j, b, m, sp, c, l, k, img, Ks[j][m:m + 1].copy(),
-                                             (descs[j].Cw, descs[j].Hw, descs[j].Ww))
-                                            for (j, b, m, sp, c, l, k, img) in picks],
-               "got_plain": got_plain, "got_batch": got_batch}
+    stream = torch.cuda.current_stream()
+    batched = _passes(torch, lambda: bt.launch(graph=True), args.steps, args.warmup, stream)
+    plain = _passes(torch, plain_pass, args.plain_steps, 1, stream)
+    per_layer = _passes(torch, per_layer_pass, args.plain_steps, 1, stream)
+
+    # per-grid durations: instrumented eager passes of the same batch (the
+    # same kernels as the graph), HIP events around every grid on its stream
+    grid_ms = [bt.launch_timed(stream) for _ in range(args.kernel_reps)]
+    n_ch = bt.n_chains
+    kavg = {}
+    for p, name in enumerate(("batch_fwd", "batch_mac", "batch_inv")):
+        per_launch = [grid_ms[r][c][p] for r in range(len(grid_ms)) for c in range(n_ch)]
+        kavg[name] = {"avg_ms_per_launch": float(np.mean(per_launch)), "launches_per_pass": n_ch,
+                      "ms_per_pass": float(np.mean([sum(grid_ms[r][c][p] for c in range(n_ch))
+                                                    for r in range(len(grid_ms))]))}
+    in_cts = sum(B * s.in_cts for s in sizes)
+    out_cts = sum(B * s.out_cts for s in sizes)
+    logN = N.bit_length() - 1
+    w_bytes = sum(s.w_words * 8 for s in sizes)
+    alg = {"batch_fwd": {"bytes": in_cts * 2 * L * 16 * N, "modmuls": in_cts * 2 * L * (N // 2) * logN},
+           "batch_mac": {"bytes": w_bytes + (in_cts + out_cts) * ct_words * 8, "modmul_adds": macs * ct_words},
+           "batch_inv": {"bytes": out_cts * 2 * L * 16 * N, "modmuls": out_cts * 2 * L * (N // 2) * logN}}
+    for k in kavg:
+        t = kavg[k]["ms_per_pass"] * 1e-3
+        kavg[k]["alg"] = alg[k]
+        kavg[k]["GBps"] = round(alg[k]["bytes"] / t / 1e9, 1)
+    dom = max(kavg, key=lambda k: kavg[k]["ms_per_pass"])
+    # the MAC at 16 images is bound by integer multiply-adds: each modmul-add
+    # is four v_mad_u64_u32 of 30-bit halves, so the ceiling is the chip's
+    # v_mad_u64_u32 rate / 4 (256 CUs x 64 lanes x 2.4 GHz; the probe
+    # measures that instruction at the full rate)
+    mac_t = kavg["batch_mac"]["ms_per_pass"] * 1e-3
+    achieved = alg["batch_mac"]["modmul_adds"] / mac_t / 1e9
+    peak = VALU_LANE_OPS_PEAK * MAD_RATE_FRAC / 4 / 1e9
+    traffic = load_traffic("batch_mac", cfg["name"])
+    roofline = {"bound": "alu", "kernel": "batch_mac_kernel (MAC grid of the batch)", "achieved": round(achieved, 1),
+                "peak": round(peak, 1), "unit": "G modmul-adds/s", "frac": round(achieved / peak, 4),
+                "traffic": traffic,
+                "peak_derivation": "256 CUs x 64 lanes x 2.4 GHz (v_mad_u64_u32 issues at the full rate) / 4 "
+                                   "multiply-adds per modmul-add",
+                "avg_launch_ms": round(kavg["batch_mac"]["avg_ms_per_launch"], 4)}
+    if probes:
+        mix = probes["mac_mix"]["rate"] / 1e9
+        roofline["measured_mix_ceiling"] = {"rate": round(mix, 1), "frac": round(achieved / mix, 4),
+                                            "note": "the MAC's own step and fold on registers, 16-block chunks"}
+    roofline_hbm = {"bound": "hbm", "kernel": "batch_mac_kernel", "achieved": kavg["batch_mac"]["GBps"],
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kavg["batch_mac"]["GBps"] / HBM_PEAK_GBS, 4)}
+    inv_t = kavg["batch_inv"]["ms_per_pass"] * 1e-3
+    bfly = alg["batch_inv"]["modmuls"] / inv_t / 1e9
+    roofline_valu = None
+    if probes:
+        ceil = probes["intt_mix"]["rate"] / 1e9
+        roofline_valu = {"bound": "alu", "kernel": "batch_inv_kernel (inverse NTTs)", "achieved": round(bfly, 1),
+                         "peak": round(ceil, 1), "unit": "G butterflies/s", "frac": round(bfly / ceil, 4),
+                         "peak_kind": "measured ceiling of the inverse butterfly's own instruction mix "
+                                      "(he_probe_valu, registers only)"}
+    resident = sum(t.numel() * 8 for t in wntts + ins + outs) / 2 ** 30
+    res = {
+        "metric": METRIC,
+        "value": macs / (batched["mean_ms"] * 1e-3),
+        "unit": "ct×pt MACs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": batched["mean_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": cfg["name"], "N": N, "L": L, "q_bits": bits, "t": f"2^{synth.T_BITS}", "batch": B,
+                   "layers": len(descs), "layer_solves_per_step": n_solves, "ctpt_macs_per_step": macs,
+                   "in_cts_per_step": in_cts, "out_cts_per_step": out_cts, "resident_GiB": round(resident, 1),
+                   "path": f"batched: {len(descs)} layer jobs x {B} images, "
+                           f"{'one chain' if n_ch == 1 else 'two chains'} of three grids, one hipGraph launch"},
+        "layers_per_s": n_solves / (batched["mean_ms"] * 1e-3),
+        "p50_ms": batched["p50_ms"], "p99_ms": batched["p99_ms"],
+        "plain": {"path": "plain per-layer: one he_conv_layer call per layer solve (one image)",
+                  "calls_per_pass": n_solves, **plain,
+                  "layers_per_s": n_solves / (plain["mean_ms"] * 1e-3),
+                  "ctpt_macs_per_s": macs / (plain["mean_ms"] * 1e-3)},
+        "per_layer_x16": {"path": "one he_conv_layer call of 16 images per layer", "calls_per_pass": len(descs),
+                          **per_layer, "layers_per_s": n_solves / (per_layer["mean_ms"] * 1e-3),
+                          "ctpt_macs_per_s": macs / (per_layer["mean_ms"] * 1e-3)},
+        "batched_vs_plain": plain["mean_ms"] / batched["mean_ms"],
+        "batched_vs_per_layer_x16": per_layer["mean_ms"] / batched["mean_ms"],
+        "batched_equals_plain_all_words": equal_layers == len(descs),
+        "layers_compared_all_words": equal_layers,
+        "kernels": kavg,
+        "roofline": roofline,
+        "roofline_hbm": roofline_hbm,
+        "offline_encode_ms": t_enc * 1e3,
+    }
+    if roofline_valu:
+        res["roofline_valu"] = roofline_valu
+    pending = {"q": list(ctx.q), "samples": {j: (samples[j], sample_out[j], Ks[j], (descs[j].Cw, descs[j].Hw,
+                                                                                      descs[j].Ww))
+                                             for j in sample_layers}}
     bt.close()
     del ins, outs, wntts, jobs
     ctx.close()
     return res, pending
 
 
-def check_bottleneck_samples(pending):
-    """CPU-baseline leg: the oracle's definition (one coefficient of the
-    negacyclic sum over channel blocks) for each sampled output word of the
-    bottleneck CNN, against the plain and the batched words."""
+def _passes(torch, fn, k, warm, stream):
+    """k timed calls of fn (one pass each) after `warm` calls and at least
+    0.2 s of warm-up; HIP events between passes on `stream`.  Returns mean,
+    p50 and p99 in ms."""
+    t0, n = time.perf_counter(), 0
+    while n < warm or time.perf_counter() - t0 < 0.2:
+        fn()
+        torch.cuda.synchronize()
+        n += 1
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
+    ev[0].record(stream)
+    for i in range(k):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(k)])
+    return {"passes_timed": k, "mean_ms": float(ev[0].elapsed_time(ev[-1]) / k),
+            "p50_ms": float(np.percentile(per, 50)), "p99_ms": float(np.percentile(per, 99))}
+
+
+def cpu_baseline_bottleneck(args, pending):
+    """The CPU oracle (as it stands) on a bounded sample of the headline
+    workload: image 0 of the layers in ORACLE_SAMPLE_LAYERS through the
+    oracle's textbook NTT flow (forward NTT, MAC, inverse NTT; OpenMP over
+    limb polynomials), one layer after another until about --cpu-seconds,
+    scaled to ct x pt MACs/s.  Every word of each computed layer solve is
+    compared with the GPU's batched output."""
     import oracle
 
     cfg = synth.WORKLOADS["bottleneck_cnn_b16"]
     prm = oracle.Params(cfg["N"], cfg["L"], cfg["bits"], 2 ** synth.T_BITS)
     assert prm.q == pending["q"]
-    want = []
-    for (j, b, m, sp, c, l, k, img, Km, (Cw, Hw, Ww)) in pending["picks"]:
+    spent, macs, done, exact = 0.0, 0, [], True
+    for j, (x, y, K, (Cw, Hw, Ww)) in pending["samples"].items():
         cv = oracle.Conv(*cfg["layers"][j])
         g = oracle.geometry(cv, Cw, Hw, Ww)
-        wc = oracle.pack_weights(Km, cv, g, prm)
-        want.append(oracle.conv_layer_coeff(img, wc, g, prm, 0, 0, sp, c, l, k))
-    return len(want), bool(pending["got_plain"] == want and pending["got_batch"] == want)
+        w_ntt = oracle.encode_weights(K, cv, g, prm)
+        t0 = time.perf_counter()
+        want = oracle.conv_layer_ntt(x.reshape(1, g.CB, g.S, 2, prm.L, prm.N), w_ntt, 1, g, cv.M, prm)
+        spent += time.perf_counter() - t0
+        macs += cv.M * g.CB * g.S
+        exact &= bool(np.array_equal(y.reshape(want.shape), want))
+        done.append(int(j))
+        if spent > args.cpu_seconds:
+            break
+    cores = oracle.num_threads()
+    return ({"value": macs / spent, "unit": "ct×pt MACs/s", "cores": cores, "kind": "oracle",
+             "sample": f"image 0 of layers {done} of the bottleneck CNN ({macs} ct x pt MACs) through the "
+                       f"oracle's textbook NTT flow (forward NTT, MAC, inverse NTT; OpenMP over limb "
+                       f"polynomials), {spent:.1f} s; weight preprocessing not included"},
+            {"layer_solves": len(done), "words_equal": exact})
 
 
 def run_client(torch, heconv):
@@ -857,8 +1014,11 @@ def run_zp(torch, heconv):
 def run_serving(torch, heconv, args):
     """Open-loop Poisson arrivals over the 28 single-layer shapes of the three
     workloads above (the small layer keeps N=4096, L=2), weights resident,
-    HBM budget 200 GB, four streams; then the same requests closed-loop
-    (saturation), served vs one at a time on one stream; then closed-loop in
+    HBM budget 200 GB, four streams, queued requests of one layer merged
+    into one launch; then the same requests closed-loop (saturation), served
+    vs the plain path (one request per launch, one stream) and vs four
+    streams without merging; an open-loop sweep of offered rates across the
+    plain capacity, served and plain, with p50/p99; then closed-loop in
     protocol mode (each request also folds in the server's input share and
     returns masked, extracted outputs)."""
     from paper_2506_11586_amd import serving
@@ -892,13 +1052,36 @@ def run_serving(torch, heconv, args):
     def requests():
         return [serving.Request(i, int(mix[i]), float(times[i]), pool[mix[i]][i % 2]) for i in range(n)]
 
+    def requests_at(rate, k, seed):
+        mx = Stream(seed, synth.MIX).below(k, len(layers)).astype(int)
+        ts = serving.poisson_arrivals(rate, k, Stream(seed, synth.ARRIVAL).uniform_f64(k))
+        return [serving.Request(i, int(mx[i]), float(ts[i]), pool[mx[i]][i % 2]) for i in range(k)]
+
+    def summary(st, macs_of=None):
+        d = {"layers_per_s": st.layers_per_s, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
+             "max_inflight": st.max_inflight, "launches": st.launches, "mean_batch": round(st.mean_batch, 3),
+             "wall_s": st.wall_s}
+        return d
+
     server = serving.Server(layers, n_streams=4, hbm_budget=200e9)
-    server.run(requests()[:32], closed_loop=True)  # warm-up: slots, code paths
+    server.run(requests()[:64], closed_loop=True)  # warm-up: launch buffers, code paths
     op = server.run(requests())
     cl = server.run(requests(), closed_loop=True)
-    one = serving.Server(layers, n_streams=1, hbm_budget=200e9)
+    # plain: one request per launch on one stream (the plain per-layer path)
+    one = serving.Server(layers, n_streams=1, hbm_budget=200e9, max_batch=1)
     one.run(requests()[:32], closed_loop=True)
     seq = one.run(requests(), closed_loop=True)
+    # served without merging (four streams, one request per launch)
+    nomerge = serving.Server(layers, n_streams=4, hbm_budget=200e9, max_batch=1)
+    nomerge.run(requests()[:32], closed_loop=True)
+    ncl = nomerge.run(requests(), closed_loop=True)
+    # open-loop arrival-rate sweep across the plain capacity
+    sweep = []
+    for k, rate in enumerate(args.serve_sweep):
+        reqs = requests_at(rate, args.serve_sweep_requests, 50 + k)
+        st = server.run(reqs)
+        pl = one.run(requests_at(rate, args.serve_sweep_requests, 50 + k))
+        sweep.append({"offered_per_s": rate, "served": summary(st), "plain_one_stream": summary(pl)})
     # protocol mode: a seeded share and mask per layer, reused by its requests
     shares = [torch.from_numpy(Stream(7000 + i, synth.SHARE).below(lay.share_words, 2 ** synth.T_BITS)
                                .astype(np.int64)).pin_memory() for i, lay in enumerate(layers)]
@@ -912,20 +1095,21 @@ def run_serving(torch, heconv, args):
         return rs
 
     proto = serving.Server(layers, n_streams=4, hbm_budget=200e9, protocol=True)
-    proto.run(proto_requests()[:32], closed_loop=True)
+    proto.run(proto_requests()[:64], closed_loop=True)
     pcl = proto.run(proto_requests(), closed_loop=True)
     macs = {i: lay.desc.M * lay.sizes.CB * lay.sizes.S for i, lay in enumerate(layers)}
     tot_macs = sum(macs[int(m)] for m in mix)
     out = {"workload": f"Poisson {args.serve_rate:g} req/s, {n} single-layer requests over {len(layers)} shapes",
-           "open_loop": {"layers_per_s": op.layers_per_s, "p50_ms": op.p50_ms, "p99_ms": op.p99_ms,
-                         "mean_ms": op.mean_ms, "max_inflight": op.max_inflight, "wall_s": op.wall_s},
-           "closed_loop_served": {"layers_per_s": cl.layers_per_s, "ctpt_macs_per_s": tot_macs / cl.wall_s,
-                                  "p50_ms": cl.p50_ms, "p99_ms": cl.p99_ms, "max_inflight": cl.max_inflight},
-           "closed_loop_plain_one_stream": {"layers_per_s": seq.layers_per_s, "ctpt_macs_per_s": tot_macs / seq.wall_s},
+           "form": "continuous batching: queued requests of one layer merged into one he_conv_layer launch "
+                   "(up to 16 images), four streams",
+           "open_loop": summary(op),
+           "closed_loop_served": dict(summary(cl), ctpt_macs_per_s=tot_macs / cl.wall_s),
+           "closed_loop_plain_one_stream": dict(summary(seq), ctpt_macs_per_s=tot_macs / seq.wall_s),
+           "closed_loop_four_streams_no_merging": summary(ncl),
            "served_vs_plain": cl.layers_per_s / seq.layers_per_s,
-           "closed_loop_protocol": {"layers_per_s": pcl.layers_per_s, "ctpt_macs_per_s": tot_macs / pcl.wall_s,
-                                    "p50_ms": pcl.p50_ms, "p99_ms": pcl.p99_ms,
-                                    "steps": "share folded in, layer, masked extraction (Sec. 7)"},
+           "sweep": sweep,
+           "closed_loop_protocol": dict(summary(pcl), ctpt_macs_per_s=tot_macs / pcl.wall_s,
+                                        steps="share folded in, layer, masked extraction (Sec. 7)"),
            "hbm_budget_GB": 200, "resident_weights_GB": server.resident / 1e9,
            "latency": "arrival -> device completion (H2D copy of the input included; results stay in HBM)"}
     for c in ctxs.values():

@@ -541,7 +541,10 @@ enum {
 
 /* Validate the jobs, build the work lists and copy them and the job table
  * to the device (the batch's only allocations, besides two streams and two
- * events for HE_SCHED_TWO_CHAINS).  The buffers named by the jobs must stay
+ * events for HE_SCHED_TWO_CHAINS).  The MAC register tile is the context's
+ * (he_tuning mac_mt x mac_rt) when it is (4,4), (4,2), (2,4) or (2,2), else
+ * (4,4), or (2,2) when a job has fewer than 4 ciphertext rows or output
+ * channels.  The buffers named by the jobs must stay
  * allocated while the batch is used; jobs must not share input or output
  * buffers.  HE_EINVAL for an unknown schedule (value 0 named a persistent
  * single-kernel executor, which is disabled).  HE_ESHAPE for an invalid
@@ -553,6 +556,14 @@ he_status he_batch_create(const he_ctx* ctx, const he_job* jobs, uint32_t n_jobs
  * kernels directly; else one hipGraphLaunch of the graph captured on first
  * use).  Executions of one batch must not overlap. */
 he_status he_batch_launch(he_batch* b, void* stream, int use_graph);
+
+/* One eager execution of the batch on `stream`, with HIP events around
+ * each of its grids, for measurement: ms[3*c + p] receives the duration of
+ * grid p (0 forward NTT, 1 MAC, 2 inverse NTT) of chain c, c < the chains
+ * used (he_batch_info); an empty grid reads 0.  Same results as
+ * he_batch_launch; synchronises `stream`.  Must not overlap another
+ * execution of the batch. */
+he_status he_batch_launch_timed(he_batch* b, void* stream, float* ms);
 
 /* Synchronise `stream`; HE_EDEVICE if the device reported an error. */
 he_status he_batch_status(he_batch* b, void* stream);

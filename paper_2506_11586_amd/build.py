@@ -18,7 +18,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 OBJDIR = os.path.join(ROOT, "_build", "heconv")
 LIB = os.path.join(LIBDIR, "libheconv.so")
 SOURCES = ["api.cpp", "batch_api.cpp", "ntt.hip", "mac.hip", "batch.hip", "fused.hip", "protocol.hip", "client.hip",
-           "ntt_split.hip", "ntt_fp64.hip", "rotate.hip", "zp.hip", "polyphase.hip", "noalloc.hip"]
+           "ntt_split.hip", "ntt_fp64.hip", "rotate.hip", "zp.hip", "polyphase.hip", "noalloc.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -42,10 +42,16 @@ struct BatchArgs {
   const LimbConst* lcs;
   uint32_t L, N, logN;
   uint32_t loge_small, loge_large;  // NTT words per thread below / from 512 limb polys
-  uint32_t mac_mt, mac_rt;          // (4,4) or (2,2)
+  uint32_t mac_mt, mac_rt;          // MAC register tile, see batch_tile_supported
 };
+
+// Register tiles the batch MAC is built for: (4,4), (4,2), (2,4), (2,2).
+bool batch_tile_supported(uint32_t mt, uint32_t rt);
 
 // Forward-NTT grid, MAC grid, inverse-NTT grid of one chain, on stream st.
 hipError_t batch_chain(const BatchChain& ch, const BatchArgs& a, hipStream_t st);
+
+// One of the three grids of a chain (0 forward NTT, 1 MAC, 2 inverse NTT).
+hipError_t batch_phase(const BatchChain& ch, const BatchArgs& a, int phase, hipStream_t st);
 
 }  // namespace heconv

@@ -95,27 +95,36 @@ static hipError_t ntt_phase_n(bool inverse, uint32_t logN, uint32_t loge, const 
   }
 }
 
+template <int MT, int RT>
+static hipError_t mac_go(const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((batch_mac_kernel<MT, RT>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs, a.lcs,
+                     a.L, a.N);
+  return hipGetLastError();
+}
+
 static hipError_t mac_phase(const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
   if (p.n == 0) return hipSuccess;
-  if (a.mac_mt == 4 && a.mac_rt == 4) {
-    hipLaunchKernelGGL((batch_mac_kernel<4, 4>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs, a.lcs,
-                       a.L, a.N);
-    return hipGetLastError();
-  }
-  if (a.mac_mt == 2 && a.mac_rt == 2) {
-    hipLaunchKernelGGL((batch_mac_kernel<2, 2>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs, a.lcs,
-                       a.L, a.N);
-    return hipGetLastError();
-  }
+  if (a.mac_mt == 4 && a.mac_rt == 4) return mac_go<4, 4>(p, a, st);
+  if (a.mac_mt == 4 && a.mac_rt == 2) return mac_go<4, 2>(p, a, st);
+  if (a.mac_mt == 2 && a.mac_rt == 4) return mac_go<2, 4>(p, a, st);
+  if (a.mac_mt == 2 && a.mac_rt == 2) return mac_go<2, 2>(p, a, st);
   return hipErrorInvalidValue;
 }
 
-hipError_t batch_chain(const BatchChain& ch, const BatchArgs& a, hipStream_t st) {
-  hipError_t e = ntt_phase_n(false, a.logN, ch.fwd.n < 512 ? a.loge_small : a.loge_large, ch.fwd, a, st);
-  if (e != hipSuccess) return e;
-  e = mac_phase(ch.mac, a, st);
-  if (e != hipSuccess) return e;
+bool batch_tile_supported(uint32_t mt, uint32_t rt) {
+  return (mt == 4 && rt == 4) || (mt == 4 && rt == 2) || (mt == 2 && rt == 4) || (mt == 2 && rt == 2);
+}
+
+hipError_t batch_phase(const BatchChain& ch, const BatchArgs& a, int phase, hipStream_t st) {
+  if (phase == 0) return ntt_phase_n(false, a.logN, ch.fwd.n < 512 ? a.loge_small : a.loge_large, ch.fwd, a, st);
+  if (phase == 1) return mac_phase(ch.mac, a, st);
   return ntt_phase_n(true, a.logN, ch.inv.n < 512 ? a.loge_small : a.loge_large, ch.inv, a, st);
+}
+
+hipError_t batch_chain(const BatchChain& ch, const BatchArgs& a, hipStream_t st) {
+  for (int p = 0; p < 3; p++)
+    if (hipError_t e = batch_phase(ch, a, p, st); e != hipSuccess) return e;
+  return hipSuccess;
 }
 
 }  // namespace heconv

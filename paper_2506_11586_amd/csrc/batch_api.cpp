@@ -79,8 +79,9 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
   b->ctx = c;
   b->n_chains = (schedule == HE_SCHED_TWO_CHAINS && n_jobs > 1) ? 2 : 1;
 
-  // validate, and pick the MAC tile: (4,4) unless a job has fewer than 4
-  // ciphertext rows or output channels, or the context asks for (2,2)
+  // validate, and pick the MAC tile: the context's tile when the batch
+  // kernel is built for it, else (4,4) unless a job has fewer than 4
+  // ciphertext rows or output channels
   std::vector<heconv::Geo> geo(n_jobs);
   bool small = false;
   for (uint32_t j = 0; j < n_jobs; j++) {
@@ -95,9 +96,11 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
     }
     small |= (uint64_t)jb.B * geo[j].S * 2 < 4 || jb.desc.M < 4;
   }
-  if (c->tune.mac_mt == 2 && c->tune.mac_rt == 2) small = true;
-  if (c->tune.mac_mt == 4 && c->tune.mac_rt == 4) small = false;
-  b->mac_mt = b->mac_rt = small ? 2 : 4;
+  if (heconv::batch_tile_supported(c->tune.mac_mt, c->tune.mac_rt)) {
+    b->mac_mt = c->tune.mac_mt, b->mac_rt = c->tune.mac_rt;
+  } else {
+    b->mac_mt = b->mac_rt = small ? 2 : 4;
+  }
 
   const uint64_t n_kc = (uint64_t)c->L * c->N / heconv::BATCH_MAC_THREADS;
   std::vector<BatchJob> dj(n_jobs);
@@ -209,6 +212,41 @@ he_status he_batch_launch(he_batch* b, void* stream, int use_graph) {
     if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) return HE_EDEVICE;
   }
   return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? HE_OK : HE_EDEVICE;
+}
+
+he_status he_batch_launch_timed(he_batch* b, void* stream, float* ms) {
+  if (!b || !ms) return HE_EINVAL;
+  hipStream_t main = (hipStream_t)stream;
+  const heconv::BatchArgs a = args_of(b);
+  hipEvent_t ev[2][4] = {};
+  he_status s = HE_OK;
+  for (uint32_t c = 0; c < b->n_chains && !s; c++)
+    for (int k = 0; k < 4 && !s; k++)
+      if (hipEventCreate(&ev[c][k]) != hipSuccess) s = HE_EDEVICE;
+  if (!s && b->n_chains == 2 &&
+      (hipEventRecord(b->fork, main) != hipSuccess || hipStreamWaitEvent(b->side, b->fork, 0) != hipSuccess))
+    s = HE_EDEVICE;
+  for (uint32_t c = 0; c < b->n_chains && !s; c++) {
+    hipStream_t st = c == 0 ? main : b->side;
+    if (hipEventRecord(ev[c][0], st) != hipSuccess) s = HE_EDEVICE;
+    for (int p = 0; p < 3 && !s; p++)
+      if (heconv::batch_phase(b->chains[c], a, p, st) != hipSuccess || hipEventRecord(ev[c][p + 1], st) != hipSuccess)
+        s = HE_EDEVICE;
+  }
+  if (!s && b->n_chains == 2 &&
+      (hipEventRecord(b->join, b->side) != hipSuccess || hipStreamWaitEvent(main, b->join, 0) != hipSuccess))
+    s = HE_EDEVICE;
+  if (!s && hipStreamSynchronize(main) != hipSuccess) s = HE_EDEVICE;
+  for (uint32_t c = 0; c < 2; c++)
+    for (int p = 0; p < 3; p++) {
+      float t = 0;
+      if (!s && c < b->n_chains && hipEventElapsedTime(&t, ev[c][p], ev[c][p + 1]) != hipSuccess) s = HE_EDEVICE;
+      if (c < b->n_chains) ms[3 * c + p] = t;
+    }
+  for (auto& row : ev)
+    for (hipEvent_t e : row)
+      if (e) (void)hipEventDestroy(e);
+  return s;
 }
 
 he_status he_batch_status(he_batch* b, void* stream) {

@@ -62,6 +62,8 @@ class _Job(ctypes.Structure):
 
 
 SCHED_ONE_CHAIN, SCHED_TWO_CHAINS = 1, 2
+# he_probe_valu probes (include/heconv_probe.h)
+PROBE_MAD_U64_U32, PROBE_MUL_HI_U32, PROBE_MUL_LO_U32, PROBE_ADD_U32, PROBE_MAC_MIX, PROBE_INTT_MIX, PROBE_NTT_MIX = range(7)
 
 _LIB = None
 
@@ -115,17 +117,19 @@ def _lib_handle():
         L.he_zp_diagonals_rect.argtypes = [vp, vp, u32, u32, u32, u32, vp, vp]
         L.he_zp_fold.argtypes = [vp, u64, u64, vp, vp, vp, vp, vp]
         L.he_rotate_noalloc.argtypes = [vp, u64, u64, vp, vp, vp, vp]
+        L.he_probe_valu.argtypes = [vp, u32, u32, u32, vp, P(ctypes.c_double), vp]
         L.he_polyphase_desc.argtypes = [P(ConvDesc), P(ConvDesc)]
         L.he_polyphase_advised.argtypes = [u32, u32, P(ConvDesc), u32, P(i32)]
         L.he_polyphase_weights.argtypes = [P(ConvDesc), vp, vp, vp]
         L.he_polyphase_input.argtypes = [P(ConvDesc), u32, vp, vp, vp]
         L.he_batch_create.argtypes = [vp, P(_Job), u32, u32, P(vp)]
         L.he_batch_launch.argtypes = [vp, vp, i32]
+        L.he_batch_launch_timed.argtypes = [vp, vp, P(ctypes.c_float)]
         L.he_batch_status.argtypes = [vp, vp]
         L.he_batch_info.argtypes = [vp, P(u64), P(u32)]
         L.he_batch_destroy.argtypes = [vp]
         L.he_batch_destroy.restype = None
-        for name in ("he_batch_create", "he_batch_launch", "he_batch_status", "he_batch_info"):
+        for name in ("he_batch_create", "he_batch_launch", "he_batch_launch_timed", "he_batch_status", "he_batch_info"):
             getattr(L, name).restype = i32
         for name in ("he_gen_primes", "he_ctx_create", "he_ctx_psi", "he_ctx_get_tuning", "he_ctx_set_tuning", "he_plan_conv", "he_plan_conv_host", "he_min_root", "he_conv_sizes",
                      "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer",
@@ -133,7 +137,7 @@ def _lib_handle():
                      "he_key_encode", "he_encrypt", "he_decrypt", "he_keyswitch_work_words", "he_automorph", "he_galois_key",
                      "he_keyswitch", "he_rotate", "he_simd_encode", "he_simd_decode", "he_zp_diagonals",
                      "he_zp_encode_plain", "he_zp_work_words", "he_zp_matvec", "he_zp_grouped_work_words",
-                     "he_zp_matvec_grouped", "he_zp_diagonals_rect", "he_zp_fold", "he_rotate_noalloc", "he_polyphase_desc",
+                     "he_zp_matvec_grouped", "he_zp_diagonals_rect", "he_zp_fold", "he_rotate_noalloc", "he_probe_valu", "he_polyphase_desc",
                      "he_polyphase_advised",
                      "he_polyphase_weights", "he_polyphase_input"):
             getattr(L, name).restype = i32
@@ -453,6 +457,17 @@ class Context:
                                        _stream(stream)),
                "he_rotate_noalloc")
 
+    def probe_valu(self, which: int, iters: int, blocks: int = 2048) -> float:
+        """he_probe_valu (include/heconv_probe.h): the measured rate of one
+        integer instruction or of one kernel's arithmetic mix, in that
+        probe's unit per second (synchronises the current stream)."""
+        import torch
+        work = torch.randint(1, 2 ** 62, (64 + 256 * blocks,), dtype=torch.int64, device="cuda")
+        rate = ctypes.c_double(0.0)
+        _check(lib().he_probe_valu(self._h, int(which), int(iters), int(blocks), _ptr(work, 64 + 256 * blocks, "work"),
+                                   ctypes.byref(rate), _stream(None)), "he_probe_valu")
+        return rate.value
+
     # ---- Z_P variant (slot calls on a one-prime context over t) ----
 
     def simd_encode(self, n: int, slots_dev, coeffs_dev, stream=None):
@@ -554,6 +569,13 @@ class Batch:
 
     def launch(self, stream=None, graph: bool = True):
         _check(lib().he_batch_launch(self._h, _stream(stream), int(bool(graph))), "he_batch_launch")
+
+    def launch_timed(self, stream=None):
+        """he_batch_launch_timed: one eager execution with events around every
+        grid; returns [[fwd, mac, inv] ms per chain] (synchronises)."""
+        ms = (ctypes.c_float * 6)()
+        _check(lib().he_batch_launch_timed(self._h, _stream(stream), ms), "he_batch_launch_timed")
+        return [[ms[3 * c + p] for p in range(3)] for c in range(self.n_chains)]
 
     def status(self, stream=None):
         _check(lib().he_batch_status(self._h, _stream(stream)), "he_batch_status")

@@ -2,21 +2,27 @@
 a pool of HIP streams with weights resident in HBM.
 
 Each request is one layer solve (one image) of a resident layer: its input
-ciphertexts arrive in host memory, are copied into a device slot, and the
-layer's NTT -> MAC -> iNTT runs on the device; results stay resident in the
-request's output slot.  In protocol mode (the server's whole step for a
-linear layer in the online protocol, Sec. 7) a request also brings the
-server's input share and output mask: the share is folded into the input
-ciphertexts before the layer, and the output is masked and reduced to the
-coefficients that hold results (he_add_share, he_conv_layer,
-he_mask_extract).  The dispatcher admits requests as they arrive, as
-long as the HBM budget allows their slots, and puts them on any free
-stream, so requests that arrive while others are on the GPU run alongside
-them.  Latency is arrival -> device completion, measured on the GPU timeline with
-events.  Each request runs as one he_conv_layer call (which allocates
-nothing) on its stream; grouping queued requests into one he_batch would
-allocate and free device memory per group, and a device free synchronises
-every stream, so the server does not group.
+ciphertexts arrive in host memory and the layer's NTT -> MAC -> iNTT runs on
+the device.  In protocol mode (the server's whole step for a linear layer
+in the online protocol, Sec. 7) a request also brings the server's input
+share and output mask: the share is folded into the input ciphertexts
+before the layer, and the output is masked and reduced to the coefficients
+that hold results (he_add_share, he_conv_layer, he_mask_extract).
+
+Continuous batching.  Whenever a stream is free, the dispatcher takes the
+oldest waiting request and every other waiting request of the same layer
+(up to `max_batch`), copies their inputs into consecutive image slots of a
+launch buffer of that layer, and runs them as ONE he_conv_layer call of b
+images: the layer's weights are read once for all of them, which is where
+serving many requests beats one call per request.  Requests that arrive
+while others are on the GPU join the next launch of their layer.  Launch
+buffers are allocated on first use, then reused (a launch allocates
+nothing); their memory counts against the HBM budget together with the
+resident weights, and admission waits while the budget is used up.  The
+packing of each layer is planned for one image; a launch of b images uses
+the same descriptor, so each request's output words do not depend on what
+it was batched with.  Latency is arrival -> device completion, measured on
+the GPU timeline with events.
 
 All device work is the C library's; this module is scheduling only.
 """
@@ -55,7 +61,8 @@ class Request:
     t_arrival: float  # seconds from the start of the run
     host_in: object   # pinned host tensor with the request's input words
     t_done: float = math.nan
-    slot: tuple = None
+    result: object = None      # keep_outputs: device tensor with the output (protocol mode: extracted words)
+    batch: int = 0             # images in the launch that served it
     host_share: object = None  # protocol mode: pinned int64 share [C*H*W]
     host_mask: object = None   # protocol mode: pinned int64 mask [M*Ho*Wo]
 
@@ -69,131 +76,166 @@ class Stats:
     p99_ms: float
     mean_ms: float
     max_inflight: int
+    launches: int = 0
+    mean_batch: float = 1.0
     latencies_ms: list = field(default_factory=list)
 
 
-class Server:
-    """Resident layers + slot pools + a stream pool."""
+def single_stream_tunings(ctxs) -> list:
+    """Set layer_split = 1 on every context that is not already so, and
+    return those contexts.  A split layer runs its inverse NTTs on the
+    context's one internal stream with shared events, so calls from several
+    streams would wait on and race with each other's transforms."""
+    changed = []
+    for c in ctxs:
+        if c.get_tuning().layer_split != 1:
+            c.set_tuning(layer_split=1)
+            changed.append(c)
+    return changed
 
-    def __init__(self, layers: list[Layer], n_streams: int = 4, hbm_budget: float = 200e9, protocol: bool = False):
+
+class Server:
+    """Resident layers + launch buffers per layer + a stream pool."""
+
+    def __init__(self, layers: list[Layer], n_streams: int = 4, hbm_budget: float = 200e9, protocol: bool = False,
+                 max_batch: int = 16):
         import torch
         self.torch = torch
         self.protocol = protocol
         self.layers = layers
+        self.max_batch = max(1, int(max_batch))
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]  # default priority
         self.budget = float(hbm_budget)
         self.resident = sum(l.wntt.numel() * 8 for l in layers)
         if self.resident > self.budget:
             raise MemoryError(f"weights ({self.resident / 1e9:.1f} GB) exceed the HBM budget")
         self.used = self.resident
-        self.free_slots = {i: [] for i in range(len(layers))}
+        self.free_bufs = {i: [] for i in range(len(layers))}
+        single_stream_tunings({id(l.ctx): l.ctx for l in layers}.values())
 
-    # -- slots ---------------------------------------------------------------
+    # -- launch buffers: max_batch image slots of one layer ------------------
     def _slot_words(self, L: Layer) -> list[int]:
         w = [L.in_words, L.out_words]
         if self.protocol:
             w += [L.share_words, L.mask_words, L.y_words]
         return w
 
-    def _slot(self, li: int):
-        """(d_in, d_out[, d_share, d_mask, d_y]) for layer li from the pool,
-        or a new set if the budget allows; None when it does not."""
-        if self.free_slots[li]:
-            return self.free_slots[li].pop()
-        L = self.layers[li]
-        need = sum(self._slot_words(L)) * 8
-        # idle slots of other layers give their memory back first
-        for lj, pool in self.free_slots.items():
+    def _buf_bytes(self, li: int) -> int:
+        return sum(self._slot_words(self.layers[li])) * 8 * self.max_batch
+
+    def _buffer(self, li: int):
+        """A launch buffer of layer li (one tensor per slot kind, max_batch
+        images each) from the pool, or a new one if the budget allows; None
+        when it does not."""
+        if self.free_bufs[li]:
+            return self.free_bufs[li].pop()
+        need = self._buf_bytes(li)
+        # idle buffers of other layers give their memory back first
+        for lj, pool in self.free_bufs.items():
             while pool and self.used + need > self.budget:
                 pool.pop()
-                self.used -= sum(self._slot_words(self.layers[lj])) * 8
+                self.used -= self._buf_bytes(lj)
         if self.used + need > self.budget:
             return None
         self.used += need
         t = self.torch
-        return tuple(t.empty(w, dtype=t.int64, device="cuda") for w in self._slot_words(L))
+        return tuple(t.empty(w * self.max_batch, dtype=t.int64, device="cuda")
+                     for w in self._slot_words(self.layers[li]))
 
-    def _release(self, li: int, slot):
-        self.free_slots[li].append(slot)
+    def _release(self, li: int, buf):
+        self.free_bufs[li].append(buf)
 
-    # -- one request on one stream -------------------------------------------
-    def _launch(self, r: Request, stream):
+    # -- one launch of b requests of one layer on one stream -----------------
+    def _launch(self, li: int, reqs: list[Request], buf, stream, keep: bool):
         t = self.torch
-        L = self.layers[r.layer]
+        L = self.layers[li]
+        b = len(reqs)
+        iw, ow = L.in_words, L.out_words
         with t.cuda.stream(stream):
-            r.slot[0].copy_(r.host_in, non_blocking=True)
+            for i, r in enumerate(reqs):
+                buf[0][i * iw:(i + 1) * iw].copy_(r.host_in, non_blocking=True)
+                if self.protocol:
+                    buf[2][i * L.share_words:(i + 1) * L.share_words].copy_(r.host_share, non_blocking=True)
+                    buf[3][i * L.mask_words:(i + 1) * L.mask_words].copy_(r.host_mask, non_blocking=True)
             if self.protocol:
-                r.slot[2].copy_(r.host_share, non_blocking=True)
-                r.slot[3].copy_(r.host_mask, non_blocking=True)
-                L.ctx.add_share(L.desc, 1, r.slot[0], r.slot[2], stream=stream)
-            L.ctx.conv_layer(L.desc, 1, r.slot[0], L.wntt, r.slot[1], stream=stream)
+                L.ctx.add_share(L.desc, b, buf[0], buf[2], stream=stream)
+            L.ctx.conv_layer(L.desc, b, buf[0], L.wntt, buf[1], stream=stream)
             if self.protocol:
-                L.ctx.mask_extract(L.desc, 1, r.slot[1], r.slot[3], None, r.slot[4], stream=stream)
+                L.ctx.mask_extract(L.desc, b, buf[1], buf[3], None, buf[4], stream=stream)
+            if keep:  # each request keeps its own copy of its result (before the buffer is free again)
+                src, w = (buf[4], L.y_words) if self.protocol else (buf[1], ow)
+                for i, r in enumerate(reqs):
+                    r.result = src[i * w:(i + 1) * w].clone()
             ev = t.cuda.Event(enable_timing=True)
             ev.record(stream)
+        for r in reqs:
+            r.batch = b
         return ev
 
     def run(self, requests: list[Request], closed_loop: bool = False, keep_outputs: bool = False) -> Stats:
         """Serve `requests`.  Open loop: a request becomes available at its
         arrival time.  Closed loop: all are available at once (saturation).
-        keep_outputs: completed requests keep their slot (r.slot[1] holds the
-        result after the run, and in protocol mode r.slot[4] the extracted
-        outputs) instead of returning it to the pool."""
+        keep_outputs: each request gets r.result, a device tensor with its
+        output words (in protocol mode the extracted outputs)."""
         t = self.torch
         t.cuda.synchronize()
         start_ev = t.cuda.Event(enable_timing=True)
         start_ev.record(t.cuda.current_stream())
         t.cuda.synchronize()
         t0 = time.perf_counter()
-        pending = deque()
         arrivals = deque(sorted(requests, key=lambda r: r.t_arrival))
         if closed_loop:
             for r in arrivals:
                 r.t_arrival = 0.0
+        waiting = deque()                       # arrival order
         free = list(range(len(self.streams)))
-        inflight = []  # (stream index, event, request)
-        max_inflight = 0
-        n_done = 0
+        inflight = []  # (stream index, event, layer, buffer, requests)
+        max_inflight = n_done = launches = 0
         while n_done < len(requests):
             now = time.perf_counter() - t0
             while arrivals and arrivals[0].t_arrival <= now:
-                pending.append(arrivals.popleft())
-            # completions free their stream and their slot
+                waiting.append(arrivals.popleft())
+            # completions free their stream and their buffer
             still = []
-            for si, ev, r in inflight:
+            for si, ev, li, buf, rs in inflight:
                 if ev.query():
-                    r.t_done = start_ev.elapsed_time(ev) / 1e3
-                    if not keep_outputs:
-                        self._release(r.layer, r.slot)
-                        r.slot = None
+                    done_t = start_ev.elapsed_time(ev) / 1e3
+                    for r in rs:
+                        r.t_done = done_t
+                    self._release(li, buf)
                     free.append(si)
-                    n_done += 1
+                    n_done += len(rs)
                 else:
-                    still.append((si, ev, r))
+                    still.append((si, ev, li, buf, rs))
             inflight = still
-            # admissions: FIFO, onto any free stream, while the budget allows
-            while free and pending:
-                r = pending[0]
-                slot = self._slot(r.layer)
-                if slot is None:
+            # launches: the oldest waiting request's layer, with every other
+            # waiting request of that layer, onto any free stream
+            while free and waiting:
+                li = waiting[0].layer
+                buf = self._buffer(li)
+                if buf is None:
                     if not inflight:
-                        raise MemoryError(f"request {r.rid} needs more HBM than the budget leaves for slots")
+                        raise MemoryError(f"layer {li} needs more HBM than the budget leaves for launch buffers")
                     break
-                pending.popleft()
-                r.slot = slot
+                group, rest = [], deque()
+                for r in waiting:
+                    (group if r.layer == li and len(group) < self.max_batch else rest).append(r)
+                waiting = rest
                 si = free.pop()
-                inflight.append((si, self._launch(r, self.streams[si]), r))
+                inflight.append((si, self._launch(li, group, buf, self.streams[si], keep_outputs), li, buf, group))
+                launches += 1
                 max_inflight = max(max_inflight, len(inflight))
-            if inflight and not (free and pending):
+            if inflight and not (free and waiting):
                 time.sleep(20e-6)
-            elif not inflight and not pending and arrivals:
+            elif not inflight and not waiting and arrivals:
                 time.sleep(max(0.0, min(1e-3, arrivals[0].t_arrival - (time.perf_counter() - t0))))
         t.cuda.synchronize()
         wall = max(r.t_done for r in requests) - min(r.t_arrival for r in requests)
         lat = np.array([(r.t_done - r.t_arrival) * 1e3 for r in requests])
         return Stats(n=len(requests), wall_s=wall, layers_per_s=len(requests) / wall,
                      p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                     mean_ms=float(lat.mean()), max_inflight=max_inflight, latencies_ms=lat.tolist())
+                     mean_ms=float(lat.mean()), max_inflight=max_inflight, launches=launches,
+                     mean_batch=len(requests) / max(1, launches), latencies_ms=lat.tolist())
 
 
 def make_layer(ctx: heconv.Context, shape, w_dev) -> Layer:

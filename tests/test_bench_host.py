@@ -34,3 +34,17 @@ def test_counter_records_follow_the_sources(tmp_path, monkeypatch):
 def test_peaks():
     assert bench.HBM_PEAK_GBS == 8000.0
     assert abs(bench.VALU_PEAK_GIPS - 614.4) < 1e-9
+
+
+def test_alu_peak_derivation():
+    """The integer-VALU ceiling of the MAC: 256 CUs x 64 lanes x 2.4 GHz, with
+    v_mad_u64_u32 at the full rate, four multiply-adds per modmul-add."""
+    assert abs(bench.VALU_LANE_OPS_PEAK - 256 * 64 * 2.4e9) < 1
+    assert bench.MAD_RATE_FRAC == 1.0
+    assert abs(bench.VALU_LANE_OPS_PEAK * bench.MAD_RATE_FRAC / 4 / 1e9 - 9830.4) < 1e-6
+
+
+def test_oracle_sample_layers_are_bottleneck_layers():
+    import synth
+    n = len(synth.WORKLOADS["bottleneck_cnn_b16"]["layers"])
+    assert bench.ORACLE_SAMPLE_LAYERS and all(0 <= j < n for j in bench.ORACLE_SAMPLE_LAYERS)

@@ -72,6 +72,39 @@ def test_batch_equals_layer_and_oracle(ctx4096, schedule, graph):
     b.close()
 
 
+@pytest.mark.parametrize("tile", [(4, 2), (2, 4), (2, 2), (4, 4)])
+def test_batch_forced_tiles_and_timed_launch(ctx4096, tile):
+    """Every register tile the batch MAC is built for, forced through the
+    context's tuning, gives the oracle's words; the timed eager launch gives
+    the same words and one duration per grid."""
+    from paper_2506_11586_amd import heconv
+    ctx, prm = ctx4096
+    before = ctx.get_tuning().as_dict()
+    ctx.set_tuning(mac_mt=tile[0], mac_rt=tile[1])
+    jobs, host = make_jobs(ctx, prm, SHAPES_4096, 200 + tile[0] * 10 + tile[1])
+    pristine = [j[2].clone() for j in jobs]
+    b = heconv.Batch(ctx, jobs, schedule=2)
+    ctx.set_tuning(**before)
+    ms = b.launch_timed()
+    assert len(ms) == b.n_chains and all(len(r) == 3 and min(r) >= 0 for r in ms)
+    assert sum(ms[0]) > 0
+    for (d, B, d_in, wntt, d_out), (cv, _, _, x, K) in zip(jobs, host):
+        g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+        got = to_host(d_out).reshape(B, cv.M, g.S, 2, prm.L, prm.N)
+        w_ntt = oracle.encode_weights(K, cv, g, prm)
+        want = oracle.conv_layer_ntt(x.reshape(B, g.CB, g.S, 2, prm.L, prm.N), w_ntt, B, g, cv.M, prm)
+        assert np.array_equal(got, want), (tile, cv)
+    timed_out = [to_host(j[4]).copy() for j in jobs]
+    for j, p in zip(jobs, pristine):
+        j[2].copy_(p)
+        j[4].fill_(-1)
+    b.launch(graph=True)
+    b.status()
+    for j, t in zip(jobs, timed_out):
+        assert np.array_equal(to_host(j[4]), t)
+    b.close()
+
+
 def test_graph_replays_match_eager(ctx4096):
     """The captured graph replayed several times, with eager work (restoring
     the inputs, clearing the outputs) and synchronisation between replays:

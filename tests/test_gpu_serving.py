@@ -1,5 +1,7 @@
 """GPU: the request server -- every result is the same alone and in the mix
-(bit-exact), requests overlap on the device, and the HBM budget holds."""
+(bit-exact), queued requests of one layer merge into one launch, served
+outputs equal the oracle's layer (and one real encryption decrypts to the
+plaintext conv), and the HBM budget holds."""
 import numpy as np
 import pytest
 
@@ -49,40 +51,102 @@ def make_requests(layers, n, rate, seed):
     return reqs
 
 
-def test_alone_equals_in_the_mix():
-    require_gpu()
-    ensure_built()
-    server, layers = build_server(n_streams=4, budget=200e9)
-    reqs = make_requests(layers, 40, rate=5000.0, seed=41)
-    # alone: each request by itself, default stream, fresh buffers
-    alone = []
+def alone_outputs(layers, reqs):
+    """Each request by itself: default stream, fresh buffers, one image."""
+    out = []
     for r in reqs:
         lay = layers[r.layer]
         d_in = r.host_in.cuda()
         d_out = empty_words(lay.out_words)
         lay.ctx.conv_layer(lay.desc, 1, d_in, lay.wntt, d_out)
-        alone.append(to_host(d_out).copy())
+        out.append(to_host(d_out).copy())
+    return out
+
+
+def test_alone_equals_in_the_mix():
+    require_gpu()
+    ensure_built()
+    server, layers = build_server(n_streams=4, budget=200e9)
+    reqs = make_requests(layers, 40, rate=5000.0, seed=41)
+    alone = alone_outputs(layers, reqs)
     # in the mix: open loop at 5000 req/s over 4 streams
     st = server.run(reqs, keep_outputs=True)
     assert st.n == len(reqs) and st.max_inflight > 1
     for r, a in zip(reqs, alone):
-        assert np.array_equal(to_host(r.slot[1]), a), r.rid
+        assert np.array_equal(to_host(r.result), a), r.rid
     assert server.used <= 200e9
+    # saturated (all at once): queued requests of a layer share launches
+    st = server.run(reqs, closed_loop=True, keep_outputs=True)
+    assert st.launches < len(reqs) and max(r.batch for r in reqs) > 1
+    for r, a in zip(reqs, alone):
+        assert np.array_equal(to_host(r.result), a), (r.rid, r.batch)
+
+
+def test_served_outputs_match_oracle():
+    """Merged launches against the oracle: one served request of each layer
+    (each in a launch with others of its layer) equals oracle.conv_layer_ntt
+    on its input word for word; and a real encryption of a packed input to
+    the small layer, served in the mix, decrypts to the plaintext conv."""
+    require_gpu()
+    ensure_built()
+    import torch
+    import oracle
+    from tests import workload as wl
+    server, layers = build_server(n_streams=4, budget=200e9)
+    reqs = make_requests(layers, 30, rate=1e6, seed=45)
+    # the small 4->4 layer: a real encryption as one more request
+    lay0 = layers[0]
+    N, L = lay0.ctx.N, lay0.ctx.L
+    prm = oracle.Params(N, L, 50, 2 ** synth.T_BITS)
+    assert prm.q == lay0.ctx.q
+    cv = oracle.Conv(*lay0.shape)
+    g = oracle.geometry(cv, lay0.desc.Cw, lay0.desc.Hw, lay0.desc.Ww)
+    x = Stream(46, synth.INPUT).ints(cv.C * cv.H * cv.W, 0, 2 ** 37).reshape(cv.C, cv.H, cv.W)
+    sk = wl.secret_key(46, N)
+    ct = wl.encrypt_input(x, cv, g, prm, 46, sk)
+    from paper_2506_11586_amd import serving
+    enc = serving.Request(len(reqs), 0, 0.0, torch.from_numpy(ct.view(np.int64).ravel().copy()).pin_memory())
+    reqs.append(enc)
+    st = server.run(reqs, closed_loop=True, keep_outputs=True)
+    assert st.launches < len(reqs) and enc.batch > 1
+    checked = set()
+    for r in reqs:
+        if r.layer in checked or r is enc or r.batch < 2:
+            continue
+        checked.add(r.layer)
+        lay = layers[r.layer]
+        p = oracle.Params(lay.ctx.N, lay.ctx.L, 60 if lay.ctx.N == 8192 else 50, 2 ** synth.T_BITS)
+        assert p.q == lay.ctx.q
+        c = oracle.Conv(*lay.shape)
+        gg = oracle.geometry(c, lay.desc.Cw, lay.desc.Hw, lay.desc.Ww)
+        K = Stream(700 + r.layer, synth.WEIGHT).ints(c.M * c.C * c.kh * c.kw, -2 ** 12, 2 ** 12)
+        w_ntt = oracle.encode_weights(K.reshape(c.M, c.C, c.kh, c.kw), c, gg, p)
+        xin = r.host_in.numpy().view(np.uint64).reshape(1, gg.CB, gg.S, 2, p.L, p.N)
+        want = oracle.conv_layer_ntt(xin, w_ntt, 1, gg, c.M, p)
+        assert np.array_equal(to_host(r.result).reshape(want.shape), want), (r.rid, r.layer, r.batch)
+    assert len(checked) >= 3
+    K0 = Stream(700, synth.WEIGHT).ints(cv.M * cv.C * cv.kh * cv.kw, -2 ** 12, 2 ** 12).reshape(
+        cv.M, cv.C, cv.kh, cv.kw)
+    got = to_host(enc.result).reshape(cv.M, g.S, 2, L, N)
+    y = wl.decrypt_output(got, cv, g, prm, sk)
+    assert np.array_equal(y, oracle.centre_mod(oracle.plain_conv(x, K0, cv.stride, cv.pad), prm.t))
 
 
 def test_budget_limits_admission():
-    """With a budget that fits the weights and one slot pair of the largest
-    layer only, requests queue for slots, never exceed the budget, and still
-    all complete with the same results."""
+    """With a budget that fits the weights and one launch buffer of the
+    largest layer only, requests queue for buffers, never exceed the budget,
+    and still all complete with the same results."""
     require_gpu()
     ensure_built()
     server, layers = build_server(n_streams=4, budget=200e9)
-    biggest = max((l.in_words + l.out_words) * 8 for l in layers)
-    server.budget = server.resident + biggest
+    server.budget = server.resident + max(server._buf_bytes(i) for i in range(len(layers)))
     reqs = make_requests(layers, 12, rate=1e5, seed=43)
-    st = server.run(reqs, closed_loop=True)
+    alone = alone_outputs(layers, reqs)
+    st = server.run(reqs, closed_loop=True, keep_outputs=True)
     assert st.n == 12 and server.used <= server.budget
     assert all(np.isfinite(r.t_done) for r in reqs)
+    for r, a in zip(reqs, alone):
+        assert np.array_equal(to_host(r.result), a), r.rid
 
 
 def test_budget_too_small_for_weights():
@@ -95,8 +159,9 @@ def test_budget_too_small_for_weights():
 
 
 def test_protocol_mode_equals_direct_calls():
-    """Protocol mode (share folded in, layer, masked extraction) gives the
-    same extracted words as the three calls made directly."""
+    """Protocol mode (share folded in, layer, masked extraction; requests of
+    one layer merged into one launch) gives the same extracted words as the
+    three calls made directly for each request."""
     require_gpu()
     ensure_built()
     import torch
@@ -118,7 +183,7 @@ def test_protocol_mode_equals_direct_calls():
         lay.ctx.conv_layer(lay.desc, 1, d_in, lay.wntt, d_out)
         lay.ctx.mask_extract(lay.desc, 1, d_out, r.host_mask.cuda(), None, y)
         direct.append(to_host(y).copy())
-    st = server.run(reqs, keep_outputs=True)
-    assert st.n == len(reqs)
+    st = server.run(reqs, closed_loop=True, keep_outputs=True)
+    assert st.n == len(reqs) and max(r.batch for r in reqs) > 1
     for r, want in zip(reqs, direct):
-        assert np.array_equal(to_host(r.slot[4]), want), r.rid
+        assert np.array_equal(to_host(r.result), want), r.rid
