@@ -548,7 +548,8 @@ enum {
  * allocated while the batch is used; jobs must not share input or output
  * buffers.  HE_EINVAL for an unknown schedule (value 0 named a persistent
  * single-kernel executor, which is disabled).  HE_ESHAPE for an invalid
- * descriptor or more than 2^31 items in one grid. */
+ * descriptor or a grid larger than one launch covers (2^32 - 1 work-items:
+ * 16,777,215 MAC tiles, 4,194,303 limb polynomials per transform grid). */
 he_status he_batch_create(const he_ctx* ctx, const he_job* jobs, uint32_t n_jobs, uint32_t schedule,
                           he_batch** out);
 

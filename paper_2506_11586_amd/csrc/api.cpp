@@ -617,7 +617,8 @@ he_status he_decrypt(const he_ctx* c, uint64_t n, const uint64_t* d_ct, const ui
 
 namespace {
 
-constexpr uint64_t ROT_MAX_BLOCKS = 0x7fffffffull;
+// largest grid of the rotation kernels (workgroups of up to N/8 = 1024 threads)
+constexpr uint64_t ROT_MAX_BLOCKS = heconv::grid_max_blocks(1024);
 
 // g^-1 mod 2N for odd g (the odd residues mod 2N form a group).
 uint32_t inv_mod_2n(uint64_t g, uint32_t N) {

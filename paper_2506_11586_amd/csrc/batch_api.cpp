@@ -165,7 +165,8 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
         }
       }
       cnt[ch][ph] = items.size() - off[ch][ph];
-      if (cnt[ch][ph] > 0x7fffffffull) {
+      // NTT grids use workgroups of up to 1024 threads, the MAC grid 256
+      if (cnt[ch][ph] > heconv::grid_max_blocks(ph == 1 ? heconv::BATCH_MAC_THREADS : 1024)) {
         free_batch(b);
         return HE_ESHAPE;
       }

@@ -103,7 +103,7 @@ template <int LOGN>
 static hipError_t go(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t B, uint32_t CB, uint32_t S,
                      uint32_t M, uint32_t L, const Tw* twi, const LimbConst* lc, hipStream_t st) {
   const uint64_t blocks = (uint64_t)B * S * 2 * M * L;
-  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (blocks > grid_max_blocks((1u << LOGN) / FUSED_E)) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((mac_intt_kernel<LOGN>), dim3((uint32_t)blocks), dim3((1 << LOGN) / FUSED_E), 0, st,
                      in, w, out, B, CB, S, M, L, twi, lc);
   return hipGetLastError();

@@ -7,6 +7,11 @@
 
 namespace heconv {
 
+// One launch covers at most 2^32 - 1 work-items along x (workgroups times
+// threads per workgroup): the largest grid of `threads`-thread workgroups.
+constexpr uint64_t grid_max_blocks(uint32_t threads) { return 0xffffffffull / threads; }
+
+
 // Forward (inverse = false) or inverse NTT, in place, of n_rns_polys RNS
 // polynomials [n][L][N], N = 2^logN, logN in [10, 14]; 2^loge words per
 // thread (loge 3 or 4; 3 needs logN <= 13, else 4 is used).  nt: the

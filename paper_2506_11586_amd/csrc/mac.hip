@@ -81,7 +81,7 @@ static hipError_t mac_go(const uint64_t* in, const uint64_t* w, uint64_t* out, u
                          uint32_t L, uint32_t N, uint32_t rows, const LimbConst* lc, hipStream_t st) {
   const uint32_t n_mt = (M + MT - 1) / MT, n_rt = (rows + RT - 1) / RT;
   const uint64_t blocks = (uint64_t)L * (N / MAC_THREADS) * n_mt * n_rt;
-  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (blocks > grid_max_blocks(MAC_THREADS)) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((mac_kernel<MT, RT>), dim3((uint32_t)blocks), dim3(MAC_THREADS), 0, st, in, w, out, CB, S, M,
                      L, N, rows, n_mt, n_rt, lc);
   return hipGetLastError();

@@ -33,9 +33,9 @@ template <int LOGN, int LOGE>
 static hipError_t launch_ntt(bool inverse, uint64_t* polys, uint64_t nlimbpolys, uint32_t L, const Tw* tw,
                              const LimbConst* lc, hipStream_t st, bool nt) {
   constexpr int T = (1 << LOGN) >> LOGE;
-  // grid.x is limited to 2^31-1 workgroups: split larger batches into chunks
-  // of whole RNS polynomials so that blockIdx.x % L stays the limb index
-  const uint64_t max_blocks = (1ull << 30) / L * L;
+  // one launch covers at most 2^32 - 1 work-items: split larger batches into
+  // chunks of whole RNS polynomials so that blockIdx.x % L stays the limb index
+  const uint64_t max_blocks = grid_max_blocks(T) / L * L;
   for (uint64_t off = 0; off < nlimbpolys; off += max_blocks) {
     uint64_t cnt = nlimbpolys - off < max_blocks ? nlimbpolys - off : max_blocks;
     uint64_t* base = polys + off * (1ull << LOGN);

@@ -175,7 +175,7 @@ template <int LOGN, int LOGE>
 static hipError_t go_f64(bool inverse, uint64_t* polys, uint64_t nlp, uint32_t L, const double* tw,
                          const F64Const* fc, hipStream_t st) {
   constexpr int T = (1 << LOGN) >> LOGE;
-  const uint64_t max_blocks = (1ull << 30) / L * L;
+  const uint64_t max_blocks = grid_max_blocks(T) / L * L;  // whole RNS polynomials per launch
   for (uint64_t off = 0; off < nlp; off += max_blocks) {
     const uint64_t cnt = nlp - off < max_blocks ? nlp - off : max_blocks;
     uint64_t* base = polys + off * (1ull << LOGN);

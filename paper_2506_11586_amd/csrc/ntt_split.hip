@@ -184,7 +184,7 @@ static hipError_t inv_split_go(uint64_t* polys, uint64_t nlp, uint32_t L, const 
                                hipStream_t st) {
   constexpr uint32_t W = (1 << LOGN) / 1024;
   const uint64_t blocks = nlp * W;
-  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (blocks > grid_max_blocks(SPLIT_T)) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((ntt_inv_split_c<LOGN>), dim3((uint32_t)blocks), dim3(SPLIT_T), 0, st, polys, (uint32_t)nlp, L,
                      tw, lc);
   hipLaunchKernelGGL((ntt_inv_split_d<LOGN>), dim3((uint32_t)blocks), dim3(SPLIT_T), 0, st, polys, (uint32_t)nlp, L,
@@ -211,7 +211,7 @@ static hipError_t split_go(uint64_t* polys, uint64_t nlp, uint32_t L, const Tw* 
                            hipStream_t st) {
   constexpr uint32_t W = (1 << LOGN) / 1024;
   const uint64_t blocks = nlp * W;
-  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (blocks > grid_max_blocks(SPLIT_T)) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((ntt_fwd_split_a<LOGN>), dim3((uint32_t)blocks), dim3(SPLIT_T), 0, st, polys, (uint32_t)nlp, L,
                      tw, lc);
   hipLaunchKernelGGL((ntt_fwd_split_b<LOGN>), dim3((uint32_t)blocks), dim3(SPLIT_T), 0, st, polys, (uint32_t)nlp, L,

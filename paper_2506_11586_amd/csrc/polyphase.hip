@@ -46,7 +46,7 @@ __global__ __launch_bounds__(PP_THREADS) void polyphase_input_kernel(const int64
 hipError_t polyphase_weights_launch(const int64_t* K, int64_t* Kp, const PolyGeom& g, hipStream_t st) {
   const uint64_t total = (uint64_t)g.M * g.Cp * g.khp * g.kwp;
   const uint64_t blocks = (total + PP_THREADS - 1) / PP_THREADS;
-  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (blocks > grid_max_blocks(PP_THREADS)) return hipErrorInvalidConfiguration;
   if (!blocks) return hipSuccess;
   hipLaunchKernelGGL(polyphase_weights_kernel, dim3((uint32_t)blocks), dim3(PP_THREADS), 0, st, K, Kp, g);
   return hipGetLastError();
@@ -55,7 +55,7 @@ hipError_t polyphase_weights_launch(const int64_t* K, int64_t* Kp, const PolyGeo
 hipError_t polyphase_input_launch(const int64_t* x, int64_t* X, const PolyGeom& g, uint64_t B, hipStream_t st) {
   const uint64_t total = B * g.Cp * g.Hp * g.Wp;
   const uint64_t blocks = (total + PP_THREADS - 1) / PP_THREADS;
-  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (blocks > grid_max_blocks(PP_THREADS)) return hipErrorInvalidConfiguration;
   if (!blocks) return hipSuccess;
   hipLaunchKernelGGL(polyphase_input_kernel, dim3((uint32_t)blocks), dim3(PP_THREADS), 0, st, x, X, g, total);
   return hipGetLastError();

@@ -85,7 +85,7 @@ hipError_t add_share_launch(uint64_t* in, const int64_t* share, const ProtoGeom&
                             hipStream_t st) {
   const uint64_t blocks = (uint64_t)g.B * g.CB * g.S * (g.N / PROTO_THREADS);
   if (blocks == 0) return hipSuccess;
-  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (blocks > grid_max_blocks(PROTO_THREADS)) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(add_share_kernel, dim3((uint32_t)blocks), dim3(PROTO_THREADS), 0, st, in, share, g, lc);
   return hipGetLastError();
 }
@@ -95,7 +95,7 @@ hipError_t mask_extract_launch(const uint64_t* out, const int64_t* mask, const i
   const uint64_t per_row = ((uint64_t)g.Ho * g.Wo + PROTO_THREADS - 1) / PROTO_THREADS;
   const uint64_t blocks = (uint64_t)g.B * g.M * g.L * per_row;
   if (blocks == 0) return hipSuccess;
-  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (blocks > grid_max_blocks(PROTO_THREADS)) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(mask_extract_kernel, dim3((uint32_t)blocks), dim3(PROTO_THREADS), 0, st, out, mask, noise, y,
                      g, lc);
   return hipGetLastError();

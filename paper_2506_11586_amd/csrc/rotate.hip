@@ -384,7 +384,7 @@ namespace {
 
 hipError_t rows_grid(uint64_t rows, uint32_t N, uint32_t& blocks) {
   const uint64_t b = rows * (N / ROT_THREADS);
-  if (b > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (b > grid_max_blocks(ROT_THREADS)) return hipErrorInvalidConfiguration;
   blocks = (uint32_t)b;
   return hipSuccess;
 }
@@ -433,7 +433,7 @@ bool ks_fwd_supported(uint32_t logN) { return logN >= 10 && logN <= 13; }
 hipError_t ks_fwd_launch(uint32_t logN, const uint64_t* ct, const uint64_t* ksk, uint64_t* acc, uint64_t n, uint32_t L,
                          uint32_t ginv, const Tw* tw, const LimbConst* ext, hipStream_t st) {
   const uint64_t blocks = (n + 7) / 8 * 8 * (L + 1);
-  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (blocks > grid_max_blocks(1024)) return hipErrorInvalidConfiguration;  // up to N/8 = 1024 threads
   if (!blocks) return hipSuccess;
   const dim3 grid((uint32_t)blocks);
   switch (logN) {
@@ -449,7 +449,7 @@ hipError_t ks_fwd_launch(uint32_t logN, const uint64_t* ct, const uint64_t* ksk,
 hipError_t modup_ntt_launch(uint32_t logN, const uint64_t* ct, uint64_t* digits, uint64_t n, uint32_t L, uint32_t ginv,
                             const Tw* tw, const LimbConst* ext, hipStream_t st) {
   const uint64_t blocks = (n * L + 7) / 8 * 8 * (L + 1);
-  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (blocks > grid_max_blocks(1024)) return hipErrorInvalidConfiguration;  // up to N/8 = 1024 threads
   if (!blocks) return hipSuccess;
   const dim3 grid((uint32_t)blocks);
   switch (logN) {
@@ -467,7 +467,7 @@ hipError_t inner_intt_launch(uint32_t logN, const uint64_t* digits, const uint64
                              uint64_t w_stride, const Tw* tw_inv, const LimbConst* ext, hipStream_t st) {
   if (chain_cts == 0) chain_cts = n ? n : 1;
   const uint64_t blocks = (n * (L + 1) + 7) / 8 * 8 * 2;
-  if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  if (blocks > grid_max_blocks(1024)) return hipErrorInvalidConfiguration;  // up to N/8 = 1024 threads
   if (!blocks) return hipSuccess;
   const dim3 grid((uint32_t)blocks);
   switch (logN) {

@@ -140,6 +140,25 @@ def test_batch_rejects_disabled_and_bad_input(ctx4096):
         assert e.value.status == heconv.HE_EINVAL
 
 
+def test_batch_rejects_grids_beyond_one_launch(ctx4096):
+    """A batch whose MAC grid would exceed 2^32 - 1 work-items (here 300,000
+    images of the small layer with 2x2 tiles: 19.2 million tiles of 256
+    threads) is refused with HE_ESHAPE when it is created; nothing is
+    launched, so the buffer addresses are never used."""
+    import ctypes
+    from paper_2506_11586_amd import heconv
+    ctx, prm = ctx4096
+    d = ctx.plan(SHAPES_4096[0][0])
+    before = ctx.get_tuning().as_dict()
+    ctx.set_tuning(mac_mt=2, mac_rt=2)
+    arr = (heconv._Job * 1)()
+    arr[0] = heconv._Job(d, 300000, 0x1000, 0x2000, 0x3000)
+    h = ctypes.c_void_p()
+    s = heconv.lib().he_batch_create(ctx.handle, arr, 1, 1, ctypes.byref(h))
+    ctx.set_tuning(**before)
+    assert s == heconv.HE_ESHAPE and not h.value
+
+
 def test_batch_cfg2_and_fire_layers():
     """N=8192, L=3: the 64->64 layer plus three fire-module layers in one
     batch (two chains, graph) equal their standalone layer calls."""
