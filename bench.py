@@ -57,6 +57,7 @@ PAPER_CONTEXT = {
 VALU_PEAK_GIPS = 256 * 2.4  # G full-rate wave64 VALU instructions/s: one per CU per cycle, 256 CUs at 2.4 GHz
 VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9  # full-rate 32-bit lane operations/s: 256 CUs x 64 lanes x 2.4 GHz
 MAD_RATE_FRAC = 1.0  # v_mad_u64_u32 issues at the full rate on gfx950 (the probe's mad_u64_u32 field: 0.975)
+SCHEDULE_NAMES = {1: "one chain", 2: "two chains", 3: "pipelined in 4 groups", 4: "pipelined in 8 groups"}
 # layer solves (image 0) the oracle recomputes in the CPU-baseline leg
 ORACLE_SAMPLE_LAYERS = [0, 2, 3, 12, 14, 16, 25, 26, 29, 44, 45, 48]
 
@@ -68,7 +69,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3, help="untimed batched passes first")
     ap.add_argument("--plain-steps", type=int, default=20, help="timed passes of the plain and per-layer forms")
     ap.add_argument("--kernel-reps", type=int, default=5, help="instrumented passes for the per-grid durations")
-    ap.add_argument("--schedule", type=int, default=1, choices=[1, 2], help="chains of the headline batch")
+    ap.add_argument("--schedule", type=int, default=1, choices=[1, 2, 3, 4],
+                    help="schedule of the headline batch (1 one chain, 2 two chains, 3/4 pipelined in 4/8 groups)")
     ap.add_argument("--single-steps", type=int, default=200, help="timed steps of the 64->64 single layer")
     ap.add_argument("--single-warmup", type=int, default=500)
     ap.add_argument("--workload", default="conv64_56x56", choices=["conv4_16x16", "conv64_56x56"],
@@ -423,8 +425,10 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
         for j in jobs:
             ctx.conv_layer(j[0], 1, j[2], j[3], j[4])
 
-    t_plain = _timed(torch, plain, 10)
-    t_batch = _timed(torch, lambda: b.launch(graph=True), 10)
+    stream = torch.cuda.current_stream()
+    st_plain = _passes(torch, plain, 40, 2, stream)
+    st_batch = _passes(torch, lambda: b.launch(graph=True), 40, 2, stream)
+    t_plain, t_batch = st_plain["mean_ms"], st_batch["mean_ms"]
     n = len(jobs)
     b.close()
     tuned = None
@@ -439,11 +443,13 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
         bt.launch(graph=True)
         bt.status()
         same = all(torch.equal(j[4], o) for j, o in zip(jobs, plain_out))
-        t_tuned = _timed(torch, lambda: bt.launch(graph=True), 10)
+        st_tuned = _passes(torch, lambda: bt.launch(graph=True), 40, 2, stream)
+        t_tuned = st_tuned["mean_ms"]
         bt.close()
-        tuned = {"schedule": "two chains" if tr.schedule == heconv.SCHED_TWO_CHAINS else "one chain",
-                 "tuning": {k: tr.tuning[k] for k in ("mac_mt", "mac_rt", "ntt_loge_small", "ntt_loge_large")},
+        tuned = {"schedule": SCHEDULE_NAMES[tr.schedule],
+                 "tuning": {k: tr.tuning[k] for k in ("mac_mt", "mac_rt", "mac_lds", "ntt_loge_small", "ntt_loge_large")},
                  "batched_ms": t_tuned, "batched_layers_per_s": n / t_tuned * 1e3,
+                 "batched_p50_ms": st_tuned["p50_ms"], "batched_p99_ms": st_tuned["p99_ms"],
                  "candidates_timed": len(tr.evaluations), "bit_exact_vs_plain": bool(same)}
     del plain_out
     ctx.close()
@@ -456,17 +462,22 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
     # the batched form is the autotuner's pick when it ran (schedule, MAC
     # tile and NTT grouping chosen by measurement), else the fixed form
     fixed = {"batched_ms": t_batch, "batched_layers_per_s": n / t_batch * 1e3,
+             "batched_p50_ms": st_batch["p50_ms"], "batched_p99_ms": st_batch["p99_ms"],
              "form": "two chains of three grids, tiles by shape, one hipGraph", "bit_exact_vs_plain": bool(exact)}
     if tuned is not None:
         mt, rt = tuned["tuning"]["mac_mt"], tuned["tuning"]["mac_rt"]
         tile = "by shape" if mt == 0 else f"{mt}x{rt}"
+        p50, p99 = tuned["batched_p50_ms"], tuned["batched_p99_ms"]
         t_b, ok, form = tuned["batched_ms"], tuned["bit_exact_vs_plain"] and exact, (
             f"autotuned: {tuned['schedule']} of three grids (forward NTTs, MAC tiles {tile}, inverse NTTs), "
             "one hipGraph")
     else:
+        p50, p99 = st_batch["p50_ms"], st_batch["p99_ms"]
         t_b, ok, form = t_batch, exact, fixed["form"]
     return {"workload": cfg["name"], "layers": n, "ctpt_macs_per_pass": macs, "out_cts_per_pass": out_cts,
             "plain_ms": t_plain, "batched_ms": t_b,
+            "plain_p50_ms": st_plain["p50_ms"], "plain_p99_ms": st_plain["p99_ms"],
+            "batched_p50_ms": p50, "batched_p99_ms": p99, "passes_timed": 40,
             "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_b * 1e3,
             "plain_ctpt_macs_per_s": macs / t_plain * 1e3, "batched_ctpt_macs_per_s": macs / t_b * 1e3,
             "speedup": t_plain / t_b, "bit_exact_vs_plain": bool(ok), "batched_form": form,
@@ -630,12 +641,13 @@ def run_bottleneck_main(torch, heconv, args, probes):
     # same kernels as the graph), HIP events around every grid on its stream
     grid_ms = [bt.launch_timed(stream) for _ in range(args.kernel_reps)]
     n_ch = bt.n_chains
+    # grids of each kind per pass: one per chain, or one per group when pipelined
+    launches = {1: 1, 2: n_ch, 3: min(len(descs), 4), 4: min(len(descs), 8)}[args.schedule]
     kavg = {}
     for p, name in enumerate(("batch_fwd", "batch_mac", "batch_inv")):
-        per_launch = [grid_ms[r][c][p] for r in range(len(grid_ms)) for c in range(n_ch)]
-        kavg[name] = {"avg_ms_per_launch": float(np.mean(per_launch)), "launches_per_pass": n_ch,
-                      "ms_per_pass": float(np.mean([sum(grid_ms[r][c][p] for c in range(n_ch))
-                                                    for r in range(len(grid_ms))]))}
+        per_pass = float(np.mean([sum(grid_ms[r][c][p] for c in range(n_ch)) for r in range(len(grid_ms))]))
+        kavg[name] = {"avg_ms_per_launch": per_pass / launches, "launches_per_pass": launches,
+                      "ms_per_pass": per_pass}
     in_cts = sum(B * s.in_cts for s in sizes)
     out_cts = sum(B * s.out_cts for s in sizes)
     logN = N.bit_length() - 1
@@ -690,7 +702,7 @@ def run_bottleneck_main(torch, heconv, args, probes):
                    "layers": len(descs), "layer_solves_per_step": n_solves, "ctpt_macs_per_step": macs,
                    "in_cts_per_step": in_cts, "out_cts_per_step": out_cts, "resident_GiB": round(resident, 1),
                    "path": f"batched: {len(descs)} layer jobs x {B} images, "
-                           f"{'one chain' if n_ch == 1 else 'two chains'} of three grids, one hipGraph launch"},
+                           f"{SCHEDULE_NAMES[args.schedule]} of three grids, one hipGraph launch"},
         "layers_per_s": n_solves / (batched["mean_ms"] * 1e-3),
         "p50_ms": batched["p50_ms"], "p99_ms": batched["p99_ms"],
         "plain": {"path": "plain per-layer: one he_conv_layer call per layer solve (one image)",

@@ -146,7 +146,17 @@ void he_ctx_destroy(he_ctx* ctx);
  * limb polynomials, 14.4 against 14.2 for 144, 16.8 against 14.8 for 192.
  * At N = 2^12 one workgroup per polynomial was faster at every count (7.5
  * against 9.7 us), so that size never splits.
- * Defaults: {3, 3, 512, 0, 0, 0, 1, 160, 1, 1, 128}: 8 words per thread was measured faster
+ * mac_lds: 0 = the MAC loads its operands into registers, 4 channel
+ * blocks at a time; 2, 3 or 4 = each wave stages its operands in a private
+ * LDS ring that many channel blocks ahead with direct buffer-to-LDS loads,
+ * so the loads in flight hold no registers (tiles with even mac_mt and
+ * mac_rt, and layers whose two output channels' weights stay below 2^31
+ * bytes; others keep the register loads).  Used by he_conv_ntt_mac,
+ * he_conv_layer and batches created after it is set.  Measured with the
+ * 4x4 tile: three stages take the 64->64 3x3 layer's MAC from 71 to 57 us
+ * with the caches flushed (46.8 to 43.9 us warm) and the 16-image
+ * bottleneck CNN's MAC grid from 129.6 to 121.1 ms.
+ * Defaults: {3, 3, 512, 0, 0, 0, 1, 160, 1, 1, 128, 3}: 8 words per thread was measured faster
  * than 16 at every count at N = 8192 (768 limb polys: 47.7 against 51.4 us
  * inverse); N = 16384 always uses 16.  The channel pipeline (layer_split)
  * was measured slower than the plain order on 64->64, 128->128 and
@@ -162,6 +172,7 @@ typedef struct {
   uint32_t ntt_fp64;
   uint32_t ks_fused;
   uint32_t ntt_inv_split_below;
+  uint32_t mac_lds;
 } he_tuning;
 
 he_status he_ctx_get_tuning(const he_ctx* ctx, he_tuning* out);
@@ -535,8 +546,13 @@ typedef struct {
 typedef struct he_batch he_batch;
 
 enum {
-  HE_SCHED_ONE_CHAIN = 1, /* one stream: all forward NTTs, all MACs, all inverse NTTs */
-  HE_SCHED_TWO_CHAINS = 2 /* two chains of jobs on two streams */
+  HE_SCHED_ONE_CHAIN = 1,   /* one stream: all forward NTTs, all MACs, all inverse NTTs */
+  HE_SCHED_TWO_CHAINS = 2,  /* two chains of jobs on two streams */
+  HE_SCHED_PIPELINED_4 = 3, /* consecutive jobs in up to 4 groups of about equal MAC work: each
+                               group's forward NTTs and MAC tiles on the caller's stream, its
+                               inverse NTTs on a second stream once its MAC is done, beside the
+                               next group's MAC */
+  HE_SCHED_PIPELINED_8 = 4  /* the same in up to 8 groups */
 };
 
 /* Validate the jobs, build the work lists and copy them and the job table
@@ -561,7 +577,10 @@ he_status he_batch_launch(he_batch* b, void* stream, int use_graph);
 /* One eager execution of the batch on `stream`, with HIP events around
  * each of its grids, for measurement: ms[3*c + p] receives the duration of
  * grid p (0 forward NTT, 1 MAC, 2 inverse NTT) of chain c, c < the chains
- * used (he_batch_info); an empty grid reads 0.  Same results as
+ * used (he_batch_info); an empty grid reads 0.  For the pipelined schedules
+ * ms[0] and ms[1] are the sums of every group's forward-NTT and MAC grids
+ * (caller's stream) and ms[5] the sum of the inverse-NTT grids (second
+ * stream), each measured on its own; they overlap.  Same results as
  * he_batch_launch; synchronises `stream`.  Must not overlap another
  * execution of the batch. */
 he_status he_batch_launch_timed(he_batch* b, void* stream, float* ms);
@@ -569,7 +588,7 @@ he_status he_batch_launch_timed(he_batch* b, void* stream, float* ms);
 /* Synchronise `stream`; HE_EDEVICE if the device reported an error. */
 he_status he_batch_status(he_batch* b, void* stream);
 
-/* Work items over all grids, and chains used. */
+/* Work items over all grids, and streams used (1 or 2). */
 he_status he_batch_info(const he_batch* b, uint64_t* n_items, uint32_t* n_chains);
 
 void he_batch_destroy(he_batch* b);

@@ -6,13 +6,15 @@ What it picks:
   butterfly stages per register pass and one LDS exchange per pass; chosen
   separately for small and large calls;
 - the MAC's register tile: output channels x ciphertext rows per thread;
+- whether the MAC stages its operands in LDS, and how many blocks ahead;
 - the output-channel MAC/iNTT pipeline of a one-image layer;
 - the two-grid forward and inverse NTTs for small calls;
 - the MAC and inverse NTT as one fused kernel or two (one launch fewer on
   small layers);
 - double-precision transforms where every prime is below 2^50 (the switch
   is ignored otherwise);
-- for a batch: the schedule (one or two chains) and the MAC tile.
+- for a batch: the schedule (one or two chains, or the pipeline of 4 or 8
+  groups) and the MAC tile.
 
 A tuning changes only launch shapes, never a result word, so the tuner can
 time candidates on whatever the buffers hold.  A layer clobbers its input
@@ -55,6 +57,7 @@ def layer_space(N: int) -> list[tuple[str, list[dict]]]:
         ("ntt_loge_small", [{"ntt_loge_small": v} for v in loges]),
         ("ntt_loge_large", [{"ntt_loge_large": v} for v in loges]),
         ("mac", [{"mac_mt": a, "mac_rt": b} for a, b in MAC_TILES]),
+        ("mac_lds", [{"mac_lds": v} for v in (0, 2, 3, 4)]),
         ("layer_split", [{"layer_split": v} for v in (1, 2, 4)]),
         ("ntt_split_below", [{"ntt_split_below": v} for v in (0, 96, 160, 224, 320)]),
         ("ntt_inv_split_below", [{"ntt_inv_split_below": v} for v in (0, 64, 128, 192)]),
@@ -71,6 +74,7 @@ def batch_space(N: int) -> list[tuple[str, list[dict]]]:
     loges = (3, 4) if N <= 8192 else (4,)
     return [
         ("mac", [{"mac_mt": a, "mac_rt": b} for a, b in ((0, 0), (2, 2), (4, 4), (4, 2), (2, 4))]),
+        ("mac_lds", [{"mac_lds": v} for v in (0, 2, 3, 4)]),
         ("ntt_loge_small", [{"ntt_loge_small": v} for v in loges]),
         ("ntt_loge_large", [{"ntt_loge_large": v} for v in loges]),
     ]
@@ -230,7 +234,8 @@ def tune_batch(torch, ctx, jobs, cache: TuneCache | None = None, schedules=None,
     start = ctx.get_tuning().as_dict()
     key = batch_key(torch.cuda.get_device_name(), ctx, jobs)
     if schedules is None:
-        schedules = (heconv.SCHED_ONE_CHAIN, heconv.SCHED_TWO_CHAINS)
+        schedules = (heconv.SCHED_ONE_CHAIN, heconv.SCHED_TWO_CHAINS, heconv.SCHED_PIPELINED_4,
+                     heconv.SCHED_PIPELINED_8)
     if cache is not None:
         hit = cache.get(key)
         if hit is not None:

@@ -43,6 +43,7 @@ struct BatchArgs {
   uint32_t L, N, logN;
   uint32_t loge_small, loge_large;  // NTT words per thread below / from 512 limb polys
   uint32_t mac_mt, mac_rt;          // MAC register tile, see batch_tile_supported
+  uint32_t mac_lds;                 // 0, or LDS stages of the staged MAC (mac_tile_dma)
 };
 
 // Register tiles the batch MAC is built for: (4,4), (4,2), (2,4), (2,2).

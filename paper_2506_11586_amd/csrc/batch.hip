@@ -61,6 +61,24 @@ __global__ __launch_bounds__(BATCH_MAC_THREADS) void batch_mac_kernel(const Batc
                                       jd.rows, kc, mt, rt, c, threadIdx.x);
 }
 
+template <int MT, int RT, int P>
+__global__ __launch_bounds__(BATCH_MAC_THREADS) void batch_mac_dma_kernel(const BatchItem* __restrict__ items,
+                                                                           const BatchJob* __restrict__ jobs,
+                                                                           const LimbConst* __restrict__ lcs,
+                                                                           uint32_t L, uint32_t N) {
+  __shared__ uint64_t lds[mac_dma_lds_words<MT, RT, BATCH_MAC_THREADS, P>()];
+  const BatchItem it = items[blockIdx.x];
+  if (it.job == BATCH_NO_JOB) return;
+  const BatchJob jd = jobs[it.job];
+  const uint32_t per_chunk = jd.n_mt * jd.n_rt;
+  const uint32_t kc = it.idx / per_chunk;
+  const uint32_t mt = (it.idx % per_chunk) / jd.n_rt;
+  const uint32_t rt = it.idx % jd.n_rt;
+  const LimbConst c = lcs[kc / (N / BATCH_MAC_THREADS)];
+  mac_tile_dma<MT, RT, BATCH_MAC_THREADS, P>(as_global(jd.in), as_global(jd.w), as_global(jd.out), jd.CB, jd.S, jd.M, L,
+                                             N, jd.rows, kc, mt, rt, c, threadIdx.x, lds);
+}
+
 template <int LOGN, int LOGE>
 static void launch_ntt_phase(bool inverse, const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
   constexpr uint32_t T = (1u << LOGN) >> LOGE;
@@ -97,8 +115,18 @@ static hipError_t ntt_phase_n(bool inverse, uint32_t logN, uint32_t loge, const 
 
 template <int MT, int RT>
 static hipError_t mac_go(const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((batch_mac_kernel<MT, RT>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs, a.lcs,
-                     a.L, a.N);
+  if (a.mac_lds == 2)
+    hipLaunchKernelGGL((batch_mac_dma_kernel<MT, RT, 2>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs,
+                       a.lcs, a.L, a.N);
+  else if (a.mac_lds == 3)
+    hipLaunchKernelGGL((batch_mac_dma_kernel<MT, RT, 3>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs,
+                       a.lcs, a.L, a.N);
+  else if (a.mac_lds == 4)
+    hipLaunchKernelGGL((batch_mac_dma_kernel<MT, RT, 4>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs,
+                       a.lcs, a.L, a.N);
+  else
+    hipLaunchKernelGGL((batch_mac_kernel<MT, RT>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs,
+                       a.lcs, a.L, a.N);
   return hipGetLastError();
 }
 

@@ -17,16 +17,25 @@ using heconv::BatchChain;
 using heconv::BatchItem;
 using heconv::BatchJob;
 
+// Groups of jobs ("chains"): one for HE_SCHED_ONE_CHAIN, two run on two
+// streams for HE_SCHED_TWO_CHAINS, up to BATCH_MAX_GROUPS run as a pipeline
+// for the pipelined schedules (each group's forward NTTs and MAC tiles on the
+// caller's stream, its inverse NTTs on a second stream once its MAC is done).
+constexpr uint32_t BATCH_MAX_GROUPS = 8;
+
 struct he_batch {
   const he_ctx* ctx = nullptr;
-  uint32_t n_chains = 1;
+  uint32_t schedule = HE_SCHED_ONE_CHAIN;
+  uint32_t n_chains = 1;  // groups of jobs
   uint32_t mac_mt = 4, mac_rt = 4;
+  uint32_t mac_lds = 0;
   uint64_t n_items = 0;
   BatchJob* d_jobs = nullptr;
   BatchItem* d_items = nullptr;
-  BatchChain chains[2] = {};
+  BatchChain chains[BATCH_MAX_GROUPS] = {};
   hipStream_t side = nullptr, cap0 = nullptr, cap1 = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t mac_done[BATCH_MAX_GROUPS] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -41,6 +50,8 @@ void free_batch(he_batch* b) {
     if (s) (void)hipStreamDestroy(s);
   for (hipEvent_t e : {b->fork, b->join})
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : b->mac_done)
+    if (e) (void)hipEventDestroy(e);
   if (b->d_jobs) (void)hipFree(b->d_jobs);
   if (b->d_items) (void)hipFree(b->d_items);
   delete b;
@@ -49,13 +60,31 @@ void free_batch(he_batch* b) {
 heconv::BatchArgs args_of(const he_batch* b) {
   const he_ctx* c = b->ctx;
   return heconv::BatchArgs{b->d_jobs, c->d_fwd, c->d_inv, c->d_lc, c->L, c->N, c->logN,
-                           c->tune.ntt_loge_small, c->tune.ntt_loge_large, b->mac_mt, b->mac_rt};
+                           c->tune.ntt_loge_small, c->tune.ntt_loge_large, b->mac_mt, b->mac_rt, b->mac_lds};
 }
 
+bool pipelined(const he_batch* b) { return b->schedule == HE_SCHED_PIPELINED_4 || b->schedule == HE_SCHED_PIPELINED_8; }
+
 // All chains on `main` (chain 1, if any, on `second`, forked from and
-// joined back into `main` with events).
+// joined back into `main` with events).  Pipelined: group g's forward NTTs
+// and MAC tiles on `main`, its inverse NTTs on `second` after an event
+// recorded behind its MAC, so they overlap group g+1's MAC.
 hipError_t enqueue(const he_batch* b, hipStream_t main, hipStream_t second) {
   const heconv::BatchArgs a = args_of(b);
+  if (pipelined(b)) {
+    hipError_t e = hipEventRecord(b->fork, main);
+    if (e == hipSuccess) e = hipStreamWaitEvent(second, b->fork, 0);
+    for (uint32_t g = 0; g < b->n_chains && e == hipSuccess; g++) {
+      e = heconv::batch_phase(b->chains[g], a, 0, main);
+      if (e == hipSuccess) e = heconv::batch_phase(b->chains[g], a, 1, main);
+      if (e == hipSuccess) e = hipEventRecord(b->mac_done[g], main);
+      if (e == hipSuccess) e = hipStreamWaitEvent(second, b->mac_done[g], 0);
+      if (e == hipSuccess) e = heconv::batch_phase(b->chains[g], a, 2, second);
+    }
+    if (e == hipSuccess) e = hipEventRecord(b->join, second);
+    if (e == hipSuccess) e = hipStreamWaitEvent(main, b->join, 0);
+    return e;
+  }
   if (b->n_chains == 1) return heconv::batch_chain(b->chains[0], a, main);
   hipError_t e = hipEventRecord(b->fork, main);
   if (e == hipSuccess) e = hipStreamWaitEvent(second, b->fork, 0);
@@ -73,11 +102,16 @@ extern "C" {
 he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, uint32_t schedule, he_batch** out) {
   if (out) *out = nullptr;
   if (!c || !jobs || !out || n_jobs == 0 || n_jobs >= (1u << 24)) return HE_EINVAL;
-  if (schedule != HE_SCHED_ONE_CHAIN && schedule != HE_SCHED_TWO_CHAINS) return HE_EINVAL;
+  if (schedule != HE_SCHED_ONE_CHAIN && schedule != HE_SCHED_TWO_CHAINS && schedule != HE_SCHED_PIPELINED_4 &&
+      schedule != HE_SCHED_PIPELINED_8)
+    return HE_EINVAL;
   he_batch* b = new (std::nothrow) he_batch;
   if (!b) return HE_ENOMEM;
   b->ctx = c;
-  b->n_chains = (schedule == HE_SCHED_TWO_CHAINS && n_jobs > 1) ? 2 : 1;
+  b->schedule = schedule;
+  if (schedule == HE_SCHED_TWO_CHAINS) b->n_chains = n_jobs > 1 ? 2 : 1;
+  if (schedule == HE_SCHED_PIPELINED_4) b->n_chains = std::min<uint32_t>(n_jobs, 4);
+  if (schedule == HE_SCHED_PIPELINED_8) b->n_chains = std::min<uint32_t>(n_jobs, 8);
 
   // validate, and pick the MAC tile: the context's tile when the batch
   // kernel is built for it, else (4,4) unless a job has fewer than 4
@@ -96,6 +130,10 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
     }
     small |= (uint64_t)jb.B * geo[j].S * 2 < 4 || jb.desc.M < 4;
   }
+  // the LDS-staged MAC when the context asks for it and every job fits it
+  bool dma = c->tune.mac_lds >= 2;
+  for (uint32_t j = 0; j < n_jobs; j++) dma &= heconv::mac_dma_fits(geo[j].CB, c->L, c->N);
+  b->mac_lds = dma ? c->tune.mac_lds : 0;
   if (heconv::batch_tile_supported(c->tune.mac_mt, c->tune.mac_rt)) {
     b->mac_mt = c->tune.mac_mt, b->mac_rt = c->tune.mac_rt;
   } else {
@@ -122,21 +160,44 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
                      (uint32_t)n_rt};
   }
 
-  // chain assignment: largest weight streams first, each to the chain with
-  // fewer weight bytes so far (both chains then stream about equally)
-  std::vector<uint32_t> order(n_jobs), chain_of(n_jobs, 0);
-  std::iota(order.begin(), order.end(), 0u);
-  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return wbytes[x] > wbytes[y]; });
-  uint64_t load[2] = {0, 0};
-  for (uint32_t j : order) {
-    const uint32_t ch = (b->n_chains == 2 && load[1] < load[0]) ? 1 : 0;
-    chain_of[j] = ch;
-    load[ch] += wbytes[j];
+  std::vector<uint32_t> chain_of(n_jobs, 0);
+  if (pipelined(b)) {
+    // groups of consecutive jobs with about equal MAC work (weight bytes plus
+    // the bytes of every image's inputs and outputs): group g ends once the
+    // running total passes (g+1)/G of the whole
+    std::vector<uint64_t> cost(n_jobs);
+    uint64_t total = 0;
+    for (uint32_t j = 0; j < n_jobs; j++) {
+      cost[j] = wbytes[j] + (uint64_t)jobs[j].B * (geo[j].CB + jobs[j].desc.M) * geo[j].S * 2 * c->L * c->N * 8;
+      total += cost[j];
+    }
+    uint64_t run = 0;
+    uint32_t g = 0;
+    for (uint32_t j = 0; j < n_jobs; j++) {
+      chain_of[j] = g;
+      run += cost[j];
+      const uint32_t left = n_jobs - 1 - j, groups_left = b->n_chains - 1 - g;
+      if (g + 1 < b->n_chains && (left == groups_left || (long double)run * b->n_chains >= (long double)total * (g + 1)))
+        g++;
+    }
+    b->n_chains = g + 1;
+  } else {
+    // chain assignment: largest weight streams first, each to the chain with
+    // fewer weight bytes so far (both chains then stream about equally)
+    std::vector<uint32_t> order(n_jobs);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return wbytes[x] > wbytes[y]; });
+    uint64_t load[2] = {0, 0};
+    for (uint32_t j : order) {
+      const uint32_t ch = (b->n_chains == 2 && load[1] < load[0]) ? 1 : 0;
+      chain_of[j] = ch;
+      load[ch] += wbytes[j];
+    }
   }
 
   // work lists, chain by chain: forward NTT items, MAC tiles, inverse NTT items
   std::vector<BatchItem> items;
-  uint64_t off[2][3] = {}, cnt[2][3] = {};
+  uint64_t off[BATCH_MAX_GROUPS][3] = {}, cnt[BATCH_MAX_GROUPS][3] = {};
   const std::vector<uint64_t>* counts[3] = {&n_fwd, &n_mac, &n_inv};
   for (uint32_t ch = 0; ch < b->n_chains; ch++) {
     for (int ph = 0; ph < 3; ph++) {
@@ -187,12 +248,18 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
     heconv::BatchPhase* ph[3] = {&b->chains[ch].fwd, &b->chains[ch].mac, &b->chains[ch].inv};
     for (int p = 0; p < 3; p++) *ph[p] = heconv::BatchPhase{b->d_items + off[ch][p], (uint32_t)cnt[ch][p]};
   }
-  if (b->n_chains == 2 && (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
-                           hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
-                           hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess)) {
+  if ((b->n_chains == 2 || pipelined(b)) &&
+      (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess)) {
     free_batch(b);
     return HE_EDEVICE;
   }
+  for (uint32_t g = 0; pipelined(b) && g < b->n_chains; g++)
+    if (hipEventCreateWithFlags(&b->mac_done[g], hipEventDisableTiming) != hipSuccess) {
+      free_batch(b);
+      return HE_EDEVICE;
+    }
   *out = b;
   return HE_OK;
 }
@@ -204,7 +271,8 @@ he_status he_batch_launch(he_batch* b, void* stream, int use_graph) {
     // capture every kernel of the batch once, on private streams; the
     // instantiated graph is then replayed on the caller's stream
     if (!b->cap0 && hipStreamCreateWithFlags(&b->cap0, hipStreamNonBlocking) != hipSuccess) return HE_EDEVICE;
-    if (b->n_chains == 2 && !b->cap1 && hipStreamCreateWithFlags(&b->cap1, hipStreamNonBlocking) != hipSuccess)
+    if ((b->n_chains == 2 || pipelined(b)) && !b->cap1 &&
+        hipStreamCreateWithFlags(&b->cap1, hipStreamNonBlocking) != hipSuccess)
       return HE_EDEVICE;
     if (hipStreamBeginCapture(b->cap0, hipStreamCaptureModeThreadLocal) != hipSuccess) return HE_EDEVICE;
     const hipError_t le = enqueue(b, b->cap0, b->cap1);
@@ -219,6 +287,42 @@ he_status he_batch_launch_timed(he_batch* b, void* stream, float* ms) {
   if (!b || !ms) return HE_EINVAL;
   hipStream_t main = (hipStream_t)stream;
   const heconv::BatchArgs a = args_of(b);
+  if (pipelined(b)) {
+    // per group: events around its forward and MAC grids on `main` and its
+    // inverse grid on the side stream; the sums per stream are reported
+    hipEvent_t ev[BATCH_MAX_GROUPS][5] = {};
+    he_status s = HE_OK;
+    for (uint32_t g = 0; g < b->n_chains && !s; g++)
+      for (int k = 0; k < 5 && !s; k++)
+        if (hipEventCreate(&ev[g][k]) != hipSuccess) s = HE_EDEVICE;
+    if (!s && (hipEventRecord(b->fork, main) != hipSuccess || hipStreamWaitEvent(b->side, b->fork, 0) != hipSuccess))
+      s = HE_EDEVICE;
+    for (uint32_t g = 0; g < b->n_chains && !s; g++) {
+      if (hipEventRecord(ev[g][0], main) != hipSuccess || heconv::batch_phase(b->chains[g], a, 0, main) != hipSuccess ||
+          hipEventRecord(ev[g][1], main) != hipSuccess || heconv::batch_phase(b->chains[g], a, 1, main) != hipSuccess ||
+          hipEventRecord(ev[g][2], main) != hipSuccess || hipStreamWaitEvent(b->side, ev[g][2], 0) != hipSuccess ||
+          hipEventRecord(ev[g][3], b->side) != hipSuccess ||
+          heconv::batch_phase(b->chains[g], a, 2, b->side) != hipSuccess ||
+          hipEventRecord(ev[g][4], b->side) != hipSuccess)
+        s = HE_EDEVICE;
+    }
+    if (!s && (hipEventRecord(b->join, b->side) != hipSuccess || hipStreamWaitEvent(main, b->join, 0) != hipSuccess))
+      s = HE_EDEVICE;
+    if (!s && hipStreamSynchronize(main) != hipSuccess) s = HE_EDEVICE;
+    for (int k = 0; k < 6; k++) ms[k] = 0;
+    for (uint32_t g = 0; g < b->n_chains && !s; g++) {
+      float f = 0, m = 0, v = 0;
+      if (hipEventElapsedTime(&f, ev[g][0], ev[g][1]) != hipSuccess ||
+          hipEventElapsedTime(&m, ev[g][1], ev[g][2]) != hipSuccess ||
+          hipEventElapsedTime(&v, ev[g][3], ev[g][4]) != hipSuccess)
+        s = HE_EDEVICE;
+      ms[0] += f, ms[1] += m, ms[5] += v;
+    }
+    for (auto& row : ev)
+      for (hipEvent_t e : row)
+        if (e) (void)hipEventDestroy(e);
+    return s;
+  }
   hipEvent_t ev[2][4] = {};
   he_status s = HE_OK;
   for (uint32_t c = 0; c < b->n_chains && !s; c++)
@@ -258,7 +362,7 @@ he_status he_batch_status(he_batch* b, void* stream) {
 he_status he_batch_info(const he_batch* b, uint64_t* n_items, uint32_t* n_chains) {
   if (!b) return HE_EINVAL;
   if (n_items) *n_items = b->n_items;
-  if (n_chains) *n_chains = b->n_chains;
+  if (n_chains) *n_chains = pipelined(b) ? 2 : b->n_chains;
   return HE_OK;
 }
 

@@ -76,6 +76,47 @@ __global__ __launch_bounds__(MAC_THREADS) void mac_kernel(const uint64_t* __rest
   mac_tile<MT, RT, MAC_THREADS>(as_global(in), as_global(w), as_global(out), CB, S, M, L, N, rows, kc, mt, rt, c, threadIdx.x);
 }
 
+// (Bounding the 4x4 tile to three workgroups per compute unit, 168 VGPRs,
+// spills part of the fold and measured slower: 128.6 against 121.1 ms on the
+// 16-image bottleneck CNN's MAC grid, 69.7 against 57.0 us on the 64->64
+// layer's MAC with the caches flushed.)
+template <int MT, int RT, int P>
+__global__ __launch_bounds__(MAC_THREADS) void mac_dma_kernel(const uint64_t* __restrict__ in,
+                                                              const uint64_t* __restrict__ w,
+                                                              uint64_t* __restrict__ out, uint32_t CB, uint32_t S,
+                                                              uint32_t M, uint32_t L, uint32_t N, uint32_t rows,
+                                                              uint32_t n_mt, uint32_t n_rt,
+                                                              const LimbConst* __restrict__ lcs) {
+  __shared__ uint64_t lds[mac_dma_lds_words<MT, RT, MAC_THREADS, P>()];
+  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t per_chunk = n_mt * n_rt;
+  const uint32_t kc = tile / per_chunk;
+  const uint32_t mt = (tile % per_chunk) / n_rt;
+  const uint32_t rt = tile % n_rt;
+  const LimbConst c = lcs[kc / (N / MAC_THREADS)];
+  mac_tile_dma<MT, RT, MAC_THREADS, P>(as_global(in), as_global(w), as_global(out), CB, S, M, L, N, rows, kc, mt, rt,
+                                       c, threadIdx.x, lds);
+}
+
+template <int MT, int RT, int P>
+static hipError_t mac_dma_go(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t CB, uint32_t S, uint32_t M,
+                             uint32_t L, uint32_t N, uint32_t rows, const LimbConst* lc, hipStream_t st) {
+  const uint32_t n_mt = (M + MT - 1) / MT, n_rt = (rows + RT - 1) / RT;
+  const uint64_t blocks = (uint64_t)L * (N / MAC_THREADS) * n_mt * n_rt;
+  if (blocks > grid_max_blocks(MAC_THREADS)) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((mac_dma_kernel<MT, RT, P>), dim3((uint32_t)blocks), dim3(MAC_THREADS), 0, st, in, w, out, CB, S,
+                     M, L, N, rows, n_mt, n_rt, lc);
+  return hipGetLastError();
+}
+
+template <int MT, int RT>
+static hipError_t mac_dma_p(uint32_t P, const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t CB, uint32_t S,
+                            uint32_t M, uint32_t L, uint32_t N, uint32_t rows, const LimbConst* lc, hipStream_t st) {
+  if (P == 2) return mac_dma_go<MT, RT, 2>(in, w, out, CB, S, M, L, N, rows, lc, st);
+  if (P == 3) return mac_dma_go<MT, RT, 3>(in, w, out, CB, S, M, L, N, rows, lc, st);
+  return mac_dma_go<MT, RT, 4>(in, w, out, CB, S, M, L, N, rows, lc, st);
+}
+
 template <int MT, int RT>
 static hipError_t mac_go(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t CB, uint32_t S, uint32_t M,
                          uint32_t L, uint32_t N, uint32_t rows, const LimbConst* lc, hipStream_t st) {
@@ -89,11 +130,20 @@ static hipError_t mac_go(const uint64_t* in, const uint64_t* w, uint64_t* out, u
 
 hipError_t mac_launch(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t B, uint32_t CB, uint32_t S,
                       uint32_t M, uint32_t L, uint32_t N, const LimbConst* lc, uint32_t mt, uint32_t rt,
-                      hipStream_t st) {
+                      uint32_t lds_stages, hipStream_t st) {
   const uint32_t rows = B * S * 2;
   if (mt == 0 || rt == 0) {  // default tile by shape
     if (rows >= 4 && M >= 4) mt = 4, rt = 4;
     else mt = 2, rt = 2;
+  }
+  if (lds_stages >= 2 && mac_dma_fits(CB, L, N)) {
+#define HECONV_MAC_DMA(A, Bt) \
+  if (mt == A && rt == Bt) return mac_dma_p<A, Bt>(lds_stages, in, w, out, CB, S, M, L, N, rows, lc, st);
+    HECONV_MAC_DMA(4, 4)
+    HECONV_MAC_DMA(4, 2)
+    HECONV_MAC_DMA(2, 4)
+    HECONV_MAC_DMA(2, 2)
+#undef HECONV_MAC_DMA
   }
 #define HECONV_MAC_TILE(A, Bt) \
   if (mt == A && rt == Bt) return mac_go<A, Bt>(in, w, out, CB, S, M, L, N, rows, lc, st);

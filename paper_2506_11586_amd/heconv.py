@@ -30,7 +30,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in ("ntt_loge_small", "ntt_loge_large", "ntt_small_below",
                                                "mac_mt", "mac_rt", "layer_fused", "layer_split",
                                                "ntt_split_below", "ntt_fp64", "ks_fused",
-                                               "ntt_inv_split_below")]
+                                               "ntt_inv_split_below", "mac_lds")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -61,7 +61,7 @@ class _Job(ctypes.Structure):
                 ("d_out", ctypes.c_void_p)]
 
 
-SCHED_ONE_CHAIN, SCHED_TWO_CHAINS = 1, 2
+SCHED_ONE_CHAIN, SCHED_TWO_CHAINS, SCHED_PIPELINED_4, SCHED_PIPELINED_8 = 1, 2, 3, 4
 # he_probe_valu probes (include/heconv_probe.h)
 PROBE_MAD_U64_U32, PROBE_MUL_HI_U32, PROBE_MUL_LO_U32, PROBE_ADD_U32, PROBE_MAC_MIX, PROBE_INTT_MIX, PROBE_NTT_MIX = range(7)
 

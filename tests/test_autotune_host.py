@@ -70,7 +70,7 @@ def test_spaces_hold_only_supported_values():
                         if k in v:
                             assert v[k] in ((3, 4) if N <= 8192 else (4,))
     names = [n for n, _ in autotune.layer_space(8192)]
-    assert names == ["ntt_loge_small", "ntt_loge_large", "mac", "layer_split", "ntt_split_below",
+    assert names == ["ntt_loge_small", "ntt_loge_large", "mac", "mac_lds", "layer_split", "ntt_split_below",
                      "ntt_inv_split_below", "layer_fused", "ntt_fp64"]
 
 

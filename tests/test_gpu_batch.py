@@ -50,14 +50,14 @@ def ctx4096():
     return heconv.Context(4096, heconv.gen_primes(4096, 50, 2)), prm
 
 
-@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("schedule", [1, 2, 3, 4])
 @pytest.mark.parametrize("graph", [False, True])
 def test_batch_equals_layer_and_oracle(ctx4096, schedule, graph):
     from paper_2506_11586_amd import heconv
     ctx, prm = ctx4096
     jobs, host = make_jobs(ctx, prm, SHAPES_4096, 100 + schedule)
     b = heconv.Batch(ctx, jobs, schedule=schedule)
-    assert b.n_items > 0 and b.n_chains == schedule
+    assert b.n_items > 0 and b.n_chains == min(schedule, 2)
     b.launch(graph=graph)
     b.status()
     for (d, B, d_in, wntt, d_out), (cv, _, _, x, K) in zip(jobs, host):
@@ -72,15 +72,16 @@ def test_batch_equals_layer_and_oracle(ctx4096, schedule, graph):
     b.close()
 
 
+@pytest.mark.parametrize("lds", [0, 3])
 @pytest.mark.parametrize("tile", [(4, 2), (2, 4), (2, 2), (4, 4)])
-def test_batch_forced_tiles_and_timed_launch(ctx4096, tile):
+def test_batch_forced_tiles_and_timed_launch(ctx4096, tile, lds):
     """Every register tile the batch MAC is built for, forced through the
     context's tuning, gives the oracle's words; the timed eager launch gives
     the same words and one duration per grid."""
     from paper_2506_11586_amd import heconv
     ctx, prm = ctx4096
     before = ctx.get_tuning().as_dict()
-    ctx.set_tuning(mac_mt=tile[0], mac_rt=tile[1])
+    ctx.set_tuning(mac_mt=tile[0], mac_rt=tile[1], mac_lds=lds)
     jobs, host = make_jobs(ctx, prm, SHAPES_4096, 200 + tile[0] * 10 + tile[1])
     pristine = [j[2].clone() for j in jobs]
     b = heconv.Batch(ctx, jobs, schedule=2)
@@ -134,7 +135,7 @@ def test_batch_rejects_disabled_and_bad_input(ctx4096):
     from paper_2506_11586_amd import heconv
     ctx, prm = ctx4096
     jobs, _ = make_jobs(ctx, prm, SHAPES_4096[:1], 400)
-    for sched in (0, 3):
+    for sched in (0, 5):
         with pytest.raises(heconv.HeError) as e:
             heconv.Batch(ctx, jobs, schedule=sched)
         assert e.value.status == heconv.HE_EINVAL

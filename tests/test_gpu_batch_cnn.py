@@ -118,6 +118,29 @@ def test_fire_cnn_batched_layer(fire_run, idx):
     fire_run.check(idx)
 
 
+def test_fire_cnn_other_schedules_equal(fire_run):
+    """The same 26 jobs as one chain and pipelined in 4 and 8 groups (inverse
+    NTTs of a group beside the next group's MAC, hipGraph and eager): every
+    output word equals the two-chain batch's, which the tests above compare
+    with the oracle."""
+    import torch
+    from paper_2506_11586_amd import heconv
+    run = fire_run
+    want = [run.layers[i]["d_out"].clone() for i in sorted(run.layers)]
+    for sched in (1, 3, 4):
+        b = heconv.Batch(run.ctx, run.jobs, schedule=sched)
+        for graph in (True, False):
+            for i, (d, B, d_in, wntt, d_out) in zip(sorted(run.layers), run.jobs):
+                d_in.copy_(to_dev(run.layers[i]["ct"]))
+                d_out.fill_(-1)
+            torch.cuda.synchronize()
+            b.launch(graph=graph)
+            b.status()
+            for (d, B, d_in, wntt, d_out), w in zip(run.jobs, want):
+                assert torch.equal(d_out, w), (sched, graph)
+        b.close()
+
+
 @pytest.mark.parametrize("idx", BOTTLENECK_SUBSET)
 def test_bottleneck_b16_batched_layer(bottleneck_run, idx):
     bottleneck_run.check(idx)

@@ -134,13 +134,14 @@ def test_conv_ntt_mac(shape, params, packing, B):
         w[:] = np.array(prm.q, dtype=np.uint64)[:, None] - np.uint64(1)
     want = oracle.conv_mac(x, w, B, g, cv.M, prm)
     dx, dw = to_dev(x), to_dev(w)
-    for mt, rt in MAC_TILES:
-        ctx.set_tuning(mac_mt=mt, mac_rt=rt)
-        out = empty_words(want.size)
-        out.fill_(-1)
-        ctx.conv_ntt_mac(d, B, dx, dw, out)
-        assert np.array_equal(to_host(out).reshape(want.shape), want), (mt, rt)
-    ctx.set_tuning(mac_mt=0, mac_rt=0)
+    for lds in (0, 2, 3, 4):  # register loads, then the LDS ring of 2..4 stages
+        for mt, rt in MAC_TILES:
+            ctx.set_tuning(mac_mt=mt, mac_rt=rt, mac_lds=lds)
+            out = empty_words(want.size)
+            out.fill_(-1)
+            ctx.conv_ntt_mac(d, B, dx, dw, out)
+            assert np.array_equal(to_host(out).reshape(want.shape), want), (mt, rt, lds)
+    ctx.set_tuning(mac_mt=0, mac_rt=0, mac_lds=0)
 
 
 def run_layer(cfg_id):
