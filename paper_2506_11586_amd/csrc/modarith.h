@@ -128,12 +128,13 @@ __host__ __device__ __forceinline__ uint64_t fold30_pm(uint64_t a00, uint64_t a0
   const uint64_t V = a11 + ((mid >> 30) | (mc << 34)) + ((a00 >> 60) + (s >> 60));
   // T = s_lo + V*delta = A + P*2^32 (mod q), with V split into 32-bit halves
   const uint64_t A = (uint64_t)(uint32_t)V * delta + (s & M60);  // < 2^61
-  const uint64_t P = (V >> 32) * (uint64_t)delta;                // < 2^52
+  const uint64_t P = (uint64_t)(uint32_t)(V >> 32) * delta;      // < 2^52
   const uint64_t Wlo = A + (P << 32);
-  const uint64_t Whi = (P >> 32) + (Wlo < A);  // W = Whi*2^64 + Wlo < 2^85
-  const uint64_t t = (Whi << 4) | (Wlo >> 60);  // W >> 60, < 2^25
-  const uint64_t X = (Wlo & M60) + t * delta;  // < 2^60 + 2^45 < 2q
-  return X >= q ? X - q : X;
+  const uint32_t Whi = (uint32_t)(P >> 32) + (Wlo < A);          // W = Whi*2^64 + Wlo < 2^85
+  const uint32_t t = (Whi << 4) | (uint32_t)(Wlo >> 60);          // W >> 60, < 2^25
+  const uint64_t X = (Wlo & M60) + (uint64_t)t * delta;           // < 2^60 + 2^45 < 2q
+  const uint64_t d = X - q;  // X < 2q < 2^62, so the sign of X - q decides
+  return (int64_t)d < 0 ? X : d;
 }
 
 // Exact sum of products in four accumulators: a00 + (a01 + a10)*2^30 +
