@@ -105,7 +105,14 @@ void he_ctx_destroy(he_ctx* ctx);
  * ntt_small_below limb polynomials, else 2^ntt_loge_large; loge is 3 or 4
  * (3 is used only for N <= 2^13).  MAC: each thread accumulates mac_mt
  * output channels x mac_rt ciphertext rows for one NTT point; (0, 0) picks
- * by shape; supported pairs: (4,4) (4,2) (2,4) (8,2) (2,8) (8,1) (1,8) (2,2).
+ * by shape; supported pairs: (4,4) (4,2) (2,4) (8,2) (2,8) (8,1) (1,8) (2,2),
+ * and for batches with the streamed MAC (mac_lds 2-4) also (6,4) (8,4)
+ * (4,8), which he_conv_ntt_mac and he_conv_layer replace by the shape's
+ * default.  A batch takes the context's pair when its MAC is built for it
+ * (streamed: (4,4) (6,4) (8,4) (4,8) (4,2) (2,4) (2,2); register loads:
+ * (4,4) (4,2) (2,4) (2,2)); else (2,2) when a job has fewer than four rows
+ * or output channels, else (6,4) for the streamed MAC when every job has at
+ * least six output channels, else (4,4).
  * layer_fused: 1 = he_conv_layer runs the MAC and the inverse NTT as one
  * kernel (he_conv_mac_intt), 0 = as two (he_conv_ntt_mac, he_ntt_inv).
  * (the fused kernel gives up the MAC's register tiling, so it moves several
@@ -152,11 +159,16 @@ void he_ctx_destroy(he_ctx* ctx);
  * so the loads in flight hold no registers (tiles with even mac_mt and
  * mac_rt, and layers whose two output channels' weights stay below 2^31
  * bytes; others keep the register loads).  Used by he_conv_ntt_mac,
- * he_conv_layer and batches created after it is set.  Measured with the
- * 4x4 tile: three stages take the 64->64 3x3 layer's MAC from 71 to 57 us
- * with the caches flushed (46.8 to 43.9 us warm) and the 16-image
+ * he_conv_layer and batches created after it is set; in a batch it selects
+ * the streamed MAC: each workgroup runs mac_tiles tiles (0 = 4) decoded on
+ * the host, its loads running ahead across tile boundaries, with three
+ * accumulators per output (a fold every 8 channel blocks).  Measured with
+ * the 4x4 tile: three stages take the 64->64 3x3 layer's MAC from 71 to
+ * 57 us with the caches flushed (46.8 to 43.9 us warm) and the 16-image
  * bottleneck CNN's MAC grid from 129.6 to 121.1 ms.
- * Defaults: {3, 3, 512, 0, 0, 0, 1, 160, 1, 1, 128, 3}: 8 words per thread was measured faster
+ * mac_tiles: tiles per workgroup of a batch's streamed MAC (0 = 4, at most
+ * 64).
+ * Defaults: {3, 3, 512, 0, 0, 0, 1, 160, 1, 1, 128, 3, 0}: 8 words per thread was measured faster
  * than 16 at every count at N = 8192 (768 limb polys: 47.7 against 51.4 us
  * inverse); N = 16384 always uses 16.  The channel pipeline (layer_split)
  * was measured slower than the plain order on 64->64, 128->128 and
@@ -173,6 +185,7 @@ typedef struct {
   uint32_t ks_fused;
   uint32_t ntt_inv_split_below;
   uint32_t mac_lds;
+  uint32_t mac_tiles;
 } he_tuning;
 
 he_status he_ctx_get_tuning(const he_ctx* ctx, he_tuning* out);

@@ -328,12 +328,13 @@ he_status he_ctx_set_tuning(he_ctx* c, const he_tuning* t) {
   if (check_ctx(c) || !t) return HE_EINVAL;
   auto loge_ok = [](uint32_t v) { return v == 3 || v == 4; };
   if (!loge_ok(t->ntt_loge_small) || !loge_ok(t->ntt_loge_large)) return HE_EINVAL;
-  static const uint32_t tiles[][2] = {{0, 0}, {4, 4}, {4, 2}, {2, 4}, {8, 2}, {2, 8}, {8, 1}, {1, 8}, {2, 2}};
+  static const uint32_t tiles[][2] = {{0, 0}, {4, 4}, {4, 2}, {2, 4}, {8, 2}, {2, 8}, {8, 1}, {1, 8}, {2, 2},
+                                      {6, 4}, {8, 4}, {4, 8}};
   bool ok = false;
   for (auto& p : tiles) ok |= (p[0] == t->mac_mt && p[1] == t->mac_rt);
   if (!ok || t->layer_fused > 1 || t->ntt_fp64 > 1 || t->ks_fused > 2) return HE_EINVAL;
   if (t->layer_split != 1 && t->layer_split != 2 && t->layer_split != 4) return HE_EINVAL;
-  if (t->mac_lds == 1 || t->mac_lds > 4) return HE_EINVAL;
+  if (t->mac_lds == 1 || t->mac_lds > 4 || t->mac_tiles > 64) return HE_EINVAL;
   c->tune = *t;
   return HE_OK;
 }

@@ -25,9 +25,20 @@ struct BatchItem {
   uint32_t idx;  // limb polynomial (NTT phases) or MAC tile index
 };
 
+// One MAC tile of a batch job for the streamed MAC, decoded on the host so
+// that the kernel divides nothing: k-chunk kc (256 NTT points of limb
+// kc >> (logN - 8)), output channels mt*MT.., rows rt*RT.., and the image b0
+// and spatial tile s0 of its first row pair (row pair rt*RT/2 = b0*S + s0).
+struct MacItem {
+  uint32_t job;  // BATCH_NO_JOB: padding (only after a workgroup's last tile)
+  uint32_t kc, mt, rt, b0, s0;
+};
+
 struct BatchPhase {
   const BatchItem* items;  // device
-  uint32_t n;
+  uint32_t n;              // items; for the streamed MAC, workgroups
+  const MacItem* mitems;   // streamed MAC: per_wg consecutive tiles per workgroup
+  uint32_t per_wg;
 };
 
 // The three phases of one chain of jobs.
@@ -43,11 +54,13 @@ struct BatchArgs {
   uint32_t L, N, logN;
   uint32_t loge_small, loge_large;  // NTT words per thread below / from 512 limb polys
   uint32_t mac_mt, mac_rt;          // MAC register tile, see batch_tile_supported
-  uint32_t mac_lds;                 // 0, or LDS stages of the staged MAC (mac_tile_dma)
+  uint32_t mac_lds;                 // 0, or LDS stages of the streamed MAC (mac_stream)
+  uint32_t all_pm;                  // every q_l = 2^60 - delta, delta < 2^20 (the MAC's short fold)
 };
 
-// Register tiles the batch MAC is built for: (4,4), (4,2), (2,4), (2,2).
-bool batch_tile_supported(uint32_t mt, uint32_t rt);
+// Register tiles the batch MAC is built for: with register loads (lds 0)
+// (4,4), (4,2), (2,4), (2,2); streamed (lds 2-4) also (8,4) and (4,8).
+bool batch_tile_supported(uint32_t mt, uint32_t rt, uint32_t lds);
 
 // Forward-NTT grid, MAC grid, inverse-NTT grid of one chain, on stream st.
 hipError_t batch_chain(const BatchChain& ch, const BatchArgs& a, hipStream_t st);

@@ -5,6 +5,7 @@
 // boundaries order the steps; no workgroup waits on another.
 #include "batch.h"
 #include "mac_impl.h"
+#include "mac_stream.h"
 #include "ntt_impl.h"
 
 namespace heconv {
@@ -61,22 +62,16 @@ __global__ __launch_bounds__(BATCH_MAC_THREADS) void batch_mac_kernel(const Batc
                                       jd.rows, kc, mt, rt, c, threadIdx.x);
 }
 
-template <int MT, int RT, int P>
-__global__ __launch_bounds__(BATCH_MAC_THREADS) void batch_mac_dma_kernel(const BatchItem* __restrict__ items,
-                                                                           const BatchJob* __restrict__ jobs,
-                                                                           const LimbConst* __restrict__ lcs,
-                                                                           uint32_t L, uint32_t N) {
+// Streamed MAC: workgroup b runs tiles mitems[b*per_wg ..] (see mac_stream).
+template <int MT, int RT, int P, bool PM>
+__global__ __launch_bounds__(BATCH_MAC_THREADS) void batch_mac_stream_kernel(const MacItem* __restrict__ items,
+                                                                              uint32_t per_wg,
+                                                                              const BatchJob* __restrict__ jobs,
+                                                                              const LimbConst* __restrict__ lcs,
+                                                                              uint32_t L, uint32_t logN) {
   __shared__ uint64_t lds[mac_dma_lds_words<MT, RT, BATCH_MAC_THREADS, P>()];
-  const BatchItem it = items[blockIdx.x];
-  if (it.job == BATCH_NO_JOB) return;
-  const BatchJob jd = jobs[it.job];
-  const uint32_t per_chunk = jd.n_mt * jd.n_rt;
-  const uint32_t kc = it.idx / per_chunk;
-  const uint32_t mt = (it.idx % per_chunk) / jd.n_rt;
-  const uint32_t rt = it.idx % jd.n_rt;
-  const LimbConst c = lcs[kc / (N / BATCH_MAC_THREADS)];
-  mac_tile_dma<MT, RT, BATCH_MAC_THREADS, P>(as_global(jd.in), as_global(jd.w), as_global(jd.out), jd.CB, jd.S, jd.M, L,
-                                             N, jd.rows, kc, mt, rt, c, threadIdx.x, lds);
+  mac_stream<MT, RT, BATCH_MAC_THREADS, P, PM>(items + (uint64_t)blockIdx.x * per_wg, per_wg, jobs, lcs, L, logN, lds,
+                                           threadIdx.x);
 }
 
 template <int LOGN, int LOGE>
@@ -114,33 +109,58 @@ static hipError_t ntt_phase_n(bool inverse, uint32_t logN, uint32_t loge, const 
 }
 
 template <int MT, int RT>
-static hipError_t mac_go(const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
-  if (a.mac_lds == 2)
-    hipLaunchKernelGGL((batch_mac_dma_kernel<MT, RT, 2>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs,
-                       a.lcs, a.L, a.N);
-  else if (a.mac_lds == 3)
-    hipLaunchKernelGGL((batch_mac_dma_kernel<MT, RT, 3>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs,
-                       a.lcs, a.L, a.N);
-  else if (a.mac_lds == 4)
-    hipLaunchKernelGGL((batch_mac_dma_kernel<MT, RT, 4>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs,
-                       a.lcs, a.L, a.N);
+static hipError_t mac_regs(const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((batch_mac_kernel<MT, RT>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs, a.lcs,
+                     a.L, a.N);
+  return hipGetLastError();
+}
+
+template <int MT, int RT, int P>
+static void mac_streamed_p(const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
+  if (a.all_pm)
+    hipLaunchKernelGGL((batch_mac_stream_kernel<MT, RT, P, true>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.mitems,
+                       p.per_wg, a.jobs, a.lcs, a.L, a.logN);
   else
-    hipLaunchKernelGGL((batch_mac_kernel<MT, RT>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.items, a.jobs,
-                       a.lcs, a.L, a.N);
+    hipLaunchKernelGGL((batch_mac_stream_kernel<MT, RT, P, false>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st,
+                       p.mitems, p.per_wg, a.jobs, a.lcs, a.L, a.logN);
+}
+
+template <int MT, int RT>
+static hipError_t mac_streamed(const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
+  if (a.mac_lds == 2)
+    mac_streamed_p<MT, RT, 2>(p, a, st);
+  else if (a.mac_lds == 3)
+    mac_streamed_p<MT, RT, 3>(p, a, st);
+  else if (a.mac_lds == 4)
+    mac_streamed_p<MT, RT, 4>(p, a, st);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 static hipError_t mac_phase(const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
   if (p.n == 0) return hipSuccess;
-  if (a.mac_mt == 4 && a.mac_rt == 4) return mac_go<4, 4>(p, a, st);
-  if (a.mac_mt == 4 && a.mac_rt == 2) return mac_go<4, 2>(p, a, st);
-  if (a.mac_mt == 2 && a.mac_rt == 4) return mac_go<2, 4>(p, a, st);
-  if (a.mac_mt == 2 && a.mac_rt == 2) return mac_go<2, 2>(p, a, st);
+  const uint32_t mt = a.mac_mt, rt = a.mac_rt;
+  if (a.mac_lds == 0) {
+    if (mt == 4 && rt == 4) return mac_regs<4, 4>(p, a, st);
+    if (mt == 4 && rt == 2) return mac_regs<4, 2>(p, a, st);
+    if (mt == 2 && rt == 4) return mac_regs<2, 4>(p, a, st);
+    if (mt == 2 && rt == 2) return mac_regs<2, 2>(p, a, st);
+    return hipErrorInvalidValue;
+  }
+  if (mt == 4 && rt == 4) return mac_streamed<4, 4>(p, a, st);
+  if (mt == 8 && rt == 4) return mac_streamed<8, 4>(p, a, st);
+  if (mt == 6 && rt == 4) return mac_streamed<6, 4>(p, a, st);
+  if (mt == 4 && rt == 8) return mac_streamed<4, 8>(p, a, st);
+  if (mt == 4 && rt == 2) return mac_streamed<4, 2>(p, a, st);
+  if (mt == 2 && rt == 4) return mac_streamed<2, 4>(p, a, st);
+  if (mt == 2 && rt == 2) return mac_streamed<2, 2>(p, a, st);
   return hipErrorInvalidValue;
 }
 
-bool batch_tile_supported(uint32_t mt, uint32_t rt) {
-  return (mt == 4 && rt == 4) || (mt == 4 && rt == 2) || (mt == 2 && rt == 4) || (mt == 2 && rt == 2);
+bool batch_tile_supported(uint32_t mt, uint32_t rt, uint32_t lds) {
+  const bool base = (mt == 4 && rt == 4) || (mt == 4 && rt == 2) || (mt == 2 && rt == 4) || (mt == 2 && rt == 2);
+  return base || (lds >= 2 && ((mt == 8 && rt == 4) || (mt == 4 && rt == 8)));
 }
 
 hipError_t batch_phase(const BatchChain& ch, const BatchArgs& a, int phase, hipStream_t st) {

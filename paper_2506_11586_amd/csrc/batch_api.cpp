@@ -16,6 +16,7 @@
 using heconv::BatchChain;
 using heconv::BatchItem;
 using heconv::BatchJob;
+using heconv::MacItem;
 
 // Groups of jobs ("chains"): one for HE_SCHED_ONE_CHAIN, two run on two
 // streams for HE_SCHED_TWO_CHAINS, up to BATCH_MAX_GROUPS run as a pipeline
@@ -29,9 +30,11 @@ struct he_batch {
   uint32_t n_chains = 1;  // groups of jobs
   uint32_t mac_mt = 4, mac_rt = 4;
   uint32_t mac_lds = 0;
+  uint32_t mac_tiles = 1;  // streamed MAC: tiles per workgroup
   uint64_t n_items = 0;
   BatchJob* d_jobs = nullptr;
   BatchItem* d_items = nullptr;
+  MacItem* d_mitems = nullptr;  // streamed MAC tiles (mac_lds >= 2)
   BatchChain chains[BATCH_MAX_GROUPS] = {};
   hipStream_t side = nullptr, cap0 = nullptr, cap1 = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
@@ -54,13 +57,16 @@ void free_batch(he_batch* b) {
     if (e) (void)hipEventDestroy(e);
   if (b->d_jobs) (void)hipFree(b->d_jobs);
   if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_mitems) (void)hipFree(b->d_mitems);
   delete b;
 }
 
 heconv::BatchArgs args_of(const he_batch* b) {
   const he_ctx* c = b->ctx;
+  uint32_t all_pm = 1;
+  for (const heconv::LimbConst& k : c->lc) all_pm &= k.pmd != 0;
   return heconv::BatchArgs{b->d_jobs, c->d_fwd, c->d_inv, c->d_lc, c->L, c->N, c->logN,
-                           c->tune.ntt_loge_small, c->tune.ntt_loge_large, b->mac_mt, b->mac_rt, b->mac_lds};
+                           c->tune.ntt_loge_small, c->tune.ntt_loge_large, b->mac_mt, b->mac_rt, b->mac_lds, all_pm};
 }
 
 bool pipelined(const he_batch* b) { return b->schedule == HE_SCHED_PIPELINED_4 || b->schedule == HE_SCHED_PIPELINED_8; }
@@ -114,10 +120,11 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
   if (schedule == HE_SCHED_PIPELINED_8) b->n_chains = std::min<uint32_t>(n_jobs, 8);
 
   // validate, and pick the MAC tile: the context's tile when the batch
-  // kernel is built for it, else (4,4) unless a job has fewer than 4
-  // ciphertext rows or output channels
+  // kernel is built for it, else (2,2) when a job has fewer than 4
+  // ciphertext rows or output channels, else (6,4) for the streamed MAC
+  // when every job has at least 6 output channels, else (4,4)
   std::vector<heconv::Geo> geo(n_jobs);
-  bool small = false;
+  bool small = false, narrow = false;
   for (uint32_t j = 0; j < n_jobs; j++) {
     const he_job& jb = jobs[j];
     if (!heconv::geo_of(jb.desc, c->N, geo[j]) || !heconv::mac_offsets_fit(geo[j], c->L, c->N)) {
@@ -129,15 +136,19 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
       return HE_EINVAL;
     }
     small |= (uint64_t)jb.B * geo[j].S * 2 < 4 || jb.desc.M < 4;
+    narrow |= jb.desc.M < 6;
   }
   // the LDS-staged MAC when the context asks for it and every job fits it
   bool dma = c->tune.mac_lds >= 2;
   for (uint32_t j = 0; j < n_jobs; j++) dma &= heconv::mac_dma_fits(geo[j].CB, c->L, c->N);
   b->mac_lds = dma ? c->tune.mac_lds : 0;
-  if (heconv::batch_tile_supported(c->tune.mac_mt, c->tune.mac_rt)) {
+  b->mac_tiles = c->tune.mac_tiles ? c->tune.mac_tiles : 4;
+  if (heconv::batch_tile_supported(c->tune.mac_mt, c->tune.mac_rt, b->mac_lds)) {
     b->mac_mt = c->tune.mac_mt, b->mac_rt = c->tune.mac_rt;
+  } else if (small) {
+    b->mac_mt = b->mac_rt = 2;
   } else {
-    b->mac_mt = b->mac_rt = small ? 2 : 4;
+    b->mac_mt = b->mac_lds >= 2 && !narrow ? 6 : 4, b->mac_rt = 4;
   }
 
   const uint64_t n_kc = (uint64_t)c->L * c->N / heconv::BATCH_MAC_THREADS;
@@ -197,11 +208,48 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
 
   // work lists, chain by chain: forward NTT items, MAC tiles, inverse NTT items
   std::vector<BatchItem> items;
-  uint64_t off[BATCH_MAX_GROUPS][3] = {}, cnt[BATCH_MAX_GROUPS][3] = {};
+  std::vector<MacItem> mitems;  // streamed MAC: mac_tiles per workgroup
+  uint64_t off[BATCH_MAX_GROUPS][3] = {}, cnt[BATCH_MAX_GROUPS][3] = {}, moff_of[BATCH_MAX_GROUPS] = {};
   const std::vector<uint64_t>* counts[3] = {&n_fwd, &n_mac, &n_inv};
   for (uint32_t ch = 0; ch < b->n_chains; ch++) {
     for (int ph = 0; ph < 3; ph++) {
       off[ch][ph] = items.size();
+      if (ph == 1 && b->mac_lds >= 2) {
+        // streamed MAC: XCD x takes the x-th eighth of every job's tiles, as
+        // below; each of its workgroups runs mac_tiles consecutive tiles of
+        // that list (valid ones first), and the workgroups of the eight
+        // lists are interleaved (workgroup 8i+x runs on XCD x)
+        const uint32_t T = b->mac_tiles;
+        std::vector<MacItem> per[heconv::BATCH_XCDS];
+        for (uint32_t j = 0; j < n_jobs; j++) {
+          if (chain_of[j] != ch) continue;
+          const uint64_t n = n_mac[j];
+          const uint32_t n_rt = dj[j].n_rt, per_chunk = dj[j].n_mt * dj[j].n_rt, S = dj[j].S;
+          for (uint32_t x = 0; x < heconv::BATCH_XCDS; x++)
+            for (uint64_t i = n * x / heconv::BATCH_XCDS; i < n * (x + 1) / heconv::BATCH_XCDS; i++) {
+              const uint32_t kc = (uint32_t)(i / per_chunk), rem = (uint32_t)(i % per_chunk);
+              const uint32_t mt = rem / n_rt, rt = rem % n_rt, bs0 = rt * b->mac_rt / 2;
+              per[x].push_back(MacItem{j, kc, mt, rt, bs0 / S, bs0 % S});
+            }
+        }
+        size_t wgs = 0;
+        for (const auto& v : per) wgs = std::max(wgs, (v.size() + T - 1) / T);
+        const uint64_t moff = mitems.size();
+        for (size_t w = 0; w < wgs; w++)
+          for (const auto& v : per)
+            for (uint32_t t = 0; t < T; t++) {
+              const size_t i = w * T + t;
+              mitems.push_back(i < v.size() ? v[i] : MacItem{heconv::BATCH_NO_JOB, 0, 0, 0, 0, 0});
+            }
+        // the phase's workgroup count; its tiles start at mitems[moff] (kept in off/cnt below)
+        moff_of[ch] = moff;
+        cnt[ch][ph] = wgs * heconv::BATCH_XCDS;
+        if (cnt[ch][ph] > heconv::grid_max_blocks(heconv::BATCH_MAC_THREADS)) {
+          free_batch(b);
+          return HE_ESHAPE;
+        }
+        continue;
+      }
       if (ph == 1) {
         // MAC tiles: XCD x takes the x-th eighth of every job's tiles (tiles
         // are k-chunk-major, so that is a contiguous range of k-chunks); the
@@ -233,20 +281,29 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
       }
     }
   }
-  b->n_items = items.size();
+  b->n_items = items.size() + mitems.size();
   if (hipMalloc(&b->d_jobs, sizeof(BatchJob) * n_jobs) != hipSuccess ||
-      hipMalloc(&b->d_items, sizeof(BatchItem) * std::max<size_t>(1, items.size())) != hipSuccess) {
+      hipMalloc(&b->d_items, sizeof(BatchItem) * std::max<size_t>(1, items.size())) != hipSuccess ||
+      (!mitems.empty() && hipMalloc(&b->d_mitems, sizeof(MacItem) * mitems.size()) != hipSuccess)) {
     free_batch(b);
     return HE_ENOMEM;
   }
   if (hipMemcpy(b->d_jobs, dj.data(), sizeof(BatchJob) * n_jobs, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      (!mitems.empty() &&
+       hipMemcpy(b->d_mitems, mitems.data(), sizeof(MacItem) * mitems.size(), hipMemcpyHostToDevice) != hipSuccess)) {
     free_batch(b);
     return HE_EDEVICE;
   }
   for (uint32_t ch = 0; ch < b->n_chains; ch++) {
     heconv::BatchPhase* ph[3] = {&b->chains[ch].fwd, &b->chains[ch].mac, &b->chains[ch].inv};
-    for (int p = 0; p < 3; p++) *ph[p] = heconv::BatchPhase{b->d_items + off[ch][p], (uint32_t)cnt[ch][p]};
+    for (int p = 0; p < 3; p++)
+      *ph[p] = heconv::BatchPhase{b->d_items + off[ch][p], (uint32_t)cnt[ch][p], nullptr, 0};
+    if (b->mac_lds >= 2) {
+      b->chains[ch].mac.items = nullptr;
+      b->chains[ch].mac.mitems = b->d_mitems ? b->d_mitems + moff_of[ch] : nullptr;
+      b->chains[ch].mac.per_wg = b->mac_tiles;
+    }
   }
   if ((b->n_chains == 2 || pipelined(b)) &&
       (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||

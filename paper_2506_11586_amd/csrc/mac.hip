@@ -132,6 +132,7 @@ hipError_t mac_launch(const uint64_t* in, const uint64_t* w, uint64_t* out, uint
                       uint32_t M, uint32_t L, uint32_t N, const LimbConst* lc, uint32_t mt, uint32_t rt,
                       uint32_t lds_stages, hipStream_t st) {
   const uint32_t rows = B * S * 2;
+  if ((mt == 6 || mt == 8 || mt == 4) && rt == (mt == 4 ? 8u : 4u)) mt = rt = 0;  // batch-only tiles
   if (mt == 0 || rt == 0) {  // default tile by shape
     if (rows >= 4 && M >= 4) mt = 4, rt = 4;
     else mt = 2, rt = 2;

@@ -94,7 +94,7 @@ __device__ __forceinline__ void mac_fold(uint64_t (&a00)[MT][RT], uint64_t (&a01
     for (int j = 0; j < MT; j++)
 #pragma unroll
       for (int i = 0; i < RT; i++) {
-        const uint64_t r = fold30_pm(a00[j][i], a01[j][i], a10[j][i], a11[j][i], c.q, (uint32_t)c.pmd);
+        const uint64_t r = fold30_pm(a00[j][i], a01[j][i], a10[j][i], a11[j][i], (uint32_t)c.pmd, (uint32_t)c.c30);
         a00[j][i] = r & 0x3fffffffu, a01[j][i] = r >> 30, a10[j][i] = 0, a11[j][i] = 0;
       }
   } else {
@@ -106,6 +106,30 @@ __device__ __forceinline__ void mac_fold(uint64_t (&a00)[MT][RT], uint64_t (&a01
         a00[j][i] = r & 0x3fffffffu, a01[j][i] = r >> 30, a10[j][i] = 0, a11[j][i] = 0;
       }
   }
+}
+
+// The tile's residues, each folded once more and stored non-temporally
+// (streamed past the caches, which keep the weights).  Output (row i,
+// channel j) starts at a uniform address, obase[i] + j * mstride words, and
+// the lane adds its own word: the store takes the scalar-base form.  The
+// fold is chosen once for the whole tile (PM: q = 2^60 - delta).
+template <int MT, int RT, bool PM>
+__device__ __forceinline__ void mac_store(const uint64_t (&a00)[MT][RT], const uint64_t (&a01)[MT][RT],
+                                          const uint64_t (&a10)[MT][RT], const uint64_t (&a11)[MT][RT],
+                                          const LimbConst& c, gword* __restrict__ out, const uint64_t (&obase)[RT],
+                                          uint64_t mstride, const bool (&mv)[MT], const bool (&rv)[RT],
+                                          uint32_t lane) {
+#pragma unroll
+  for (int j = 0; j < MT; j++)
+#pragma unroll
+    for (int i = 0; i < RT; i++) {
+      const uint64_t r = PM ? fold30_pm(a00[j][i], a01[j][i], a10[j][i], a11[j][i], (uint32_t)c.pmd, (uint32_t)c.c30)
+                            : fold30(a00[j][i], a01[j][i], a10[j][i], a11[j][i], c);
+      if (mv[j] && rv[i]) {
+        gword* o = out + uniform64(obase[i] + (uint64_t)j * mstride);
+        __builtin_nontemporal_store(r, &o[lane]);
+      }
+    }
 }
 
 // One MAC tile: k-chunk kc (THREADS consecutive NTT points of limb
@@ -186,16 +210,13 @@ __device__ __forceinline__ void mac_tile(cgword* __restrict__ in, cgword* __rest
     }
     if (cb1 < CB) mac_fold<MT, RT>(a00, a01, a10, a11, c);
   }
-  const bool pm = c.pmd != 0;
+  uint64_t obase[RT];
 #pragma unroll
-  for (int j = 0; j < MT; j++)
-#pragma unroll
-    for (int i = 0; i < RT; i++) {
-      const uint64_t r = pm ? fold30_pm(a00[j][i], a01[j][i], a10[j][i], a11[j][i], c.q, (uint32_t)c.pmd)
-                            : fold30(a00[j][i], a01[j][i], a10[j][i], a11[j][i], c);
-      if (mv[j] && rv[i])  // non-temporal: streamed past the caches, which keep the weights
-        __builtin_nontemporal_store(r, &out[out_off[i] + (uint64_t)(mt * MT + j) * out_m_stride + (uint32_t)tid]);
-    }
+  for (int i = 0; i < RT; i++) obase[i] = out_off[i] + (uint64_t)(mt * MT) * out_m_stride;
+  if (c.pmd)
+    mac_store<MT, RT, true>(a00, a01, a10, a11, c, out, obase, out_m_stride, mv, rv, (uint32_t)tid);
+  else
+    mac_store<MT, RT, false>(a00, a01, a10, a11, c, out, obase, out_m_stride, mv, rv, (uint32_t)tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -334,16 +355,13 @@ __device__ __forceinline__ void mac_tile_dma(cgword* __restrict__ in, cgword* __
     __asm__ volatile("" ::: "memory");
   }
   wait_vmcnt<0>();  // no load into LDS outlives the wave
-  const bool pm = c.pmd != 0;
+  uint64_t obase[RT];
 #pragma unroll
-  for (int j = 0; j < MT; j++)
-#pragma unroll
-    for (int i = 0; i < RT; i++) {
-      const uint64_t r = pm ? fold30_pm(a00[j][i], a01[j][i], a10[j][i], a11[j][i], c.q, (uint32_t)c.pmd)
-                            : fold30(a00[j][i], a01[j][i], a10[j][i], a11[j][i], c);
-      if (mv[j] && rv[i])  // non-temporal: streamed past the caches, which keep the weights
-        __builtin_nontemporal_store(r, &out[out_off[i] + (uint64_t)(mt * MT + j) * out_m_stride + lane]);
-    }
+  for (int i = 0; i < RT; i++) obase[i] = out_off[i] + (uint64_t)(mt * MT) * out_m_stride;
+  if (c.pmd)
+    mac_store<MT, RT, true>(a00, a01, a10, a11, c, out, obase, out_m_stride, mv, rv, lane);
+  else
+    mac_store<MT, RT, false>(a00, a01, a10, a11, c, out, obase, out_m_stride, mv, rv, lane);
 }
 
 }  // namespace heconv

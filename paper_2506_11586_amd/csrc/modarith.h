@@ -111,30 +111,70 @@ __device__ __forceinline__ Half30 split30(uint64_t x) {
   return Half30{(uint32_t)x & 0x3fffffffu, (uint32_t)(x >> 30)};
 }
 
+// Bits [s, s+32) of the 64-bit value hi:lo (one v_alignbit_b32).
+__host__ __device__ __forceinline__ uint32_t funnel32(uint32_t hi, uint32_t lo, int s) {
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> s);
+}
+
 // Fold for a prime q = 2^60 - delta with delta < 2^20 (the largest primes
-// below 2^60 are of this form): 2^60 = delta mod q, so a value
-// lo + hi*2^60 is congruent to lo + hi*delta, which two rounds bring below
-// 2^60 + 2^45 < 2q.  Exact for every a00, a01, a10, a11 < 2^64 with
-// a11 + (a01 + a10) / 2^30 + a00 / 2^60 + 1 < 2^64, which sixteen blocks of
+// below 2^60 are of this form): 2^60 = delta mod q, so a value lo + hi*2^60
+// is congruent to lo + hi*delta.  With B = a01 + a10 (65 bits) the sum is
+//   T = L + V*2^60,  L = (a00 mod 2^60) + (B mod 2^30)*2^30 < 2^61,
+//                    V = a11 + (B >> 30) + (a00 >> 60) < 2^64,
+// so T = W = L + V*delta (< 2^85) mod q, then W = X = (W mod 2^60) +
+// (W >> 60)*delta < 2^60 + 2^45 < 2q, and X >= q exactly when X + delta
+// carries into bit 60, where X - q = (X + delta) mod 2^60.  Every product
+// is a 32 x 32 multiply-add; the only carry chain is that of B.  two30 is
+// 2^30, passed in (from the limb constants) so that (B mod 2^30)*2^30 + ...
+// stays one multiply-add instead of a 64-bit shift, a mask and an add.
+// Exact for every a00, a01, a10, a11 < 2^64 with
+// a11 + (a01 + a10) / 2^30 + a00 / 2^60 < 2^64, which sixteen blocks of
 // 30-bit products (each below (2^30-1)^2) plus a carried residue below 2^60
-// satisfy.  Three 32 x 32 multiply-adds and no 64 x 64 products.
+// satisfy.
 __host__ __device__ __forceinline__ uint64_t fold30_pm(uint64_t a00, uint64_t a01, uint64_t a10, uint64_t a11,
-                                                       uint64_t q, uint32_t delta) {
-  constexpr uint64_t M60 = (1ull << 60) - 1, M30 = (1ull << 30) - 1;
-  const uint64_t mid = a01 + a10;  // 65 bits: carry in mc
-  const uint64_t mc = mid < a01;
-  // T = a00 + mid*2^30 + a11*2^60 = s_lo + V*2^60 with s = a00 mod 2^60 + (mid mod 2^30)*2^30
-  const uint64_t s = (a00 & M60) + ((mid & M30) << 30);  // < 2^61
-  const uint64_t V = a11 + ((mid >> 30) | (mc << 34)) + ((a00 >> 60) + (s >> 60));
-  // T = s_lo + V*delta = A + P*2^32 (mod q), with V split into 32-bit halves
-  const uint64_t A = (uint64_t)(uint32_t)V * delta + (s & M60);  // < 2^61
-  const uint64_t P = (uint64_t)(uint32_t)(V >> 32) * delta;      // < 2^52
-  const uint64_t Wlo = A + (P << 32);
-  const uint32_t Whi = (uint32_t)(P >> 32) + (Wlo < A);          // W = Whi*2^64 + Wlo < 2^85
-  const uint32_t t = (Whi << 4) | (uint32_t)(Wlo >> 60);          // W >> 60, < 2^25
-  const uint64_t X = (Wlo & M60) + (uint64_t)t * delta;           // < 2^60 + 2^45 < 2q
-  const uint64_t d = X - q;  // X < 2q < 2^62, so the sign of X - q decides
-  return (int64_t)d < 0 ? X : d;
+                                                       uint32_t delta, uint32_t two30) {
+  constexpr uint32_t M28 = (1u << 28) - 1, M30 = (1u << 30) - 1;
+  const uint64_t b = a01 + a10;
+  const uint32_t bc4 = b < a01 ? 4u : 0u;  // bit 64 of B, as bit 34 of B >> 30
+  const uint32_t b_lo = (uint32_t)b, b_hi = (uint32_t)(b >> 32);
+  const uint32_t a_lo = (uint32_t)a00, a_hi = (uint32_t)(a00 >> 32);
+  const uint64_t a60 = ((uint64_t)(a_hi & M28) << 32) | a_lo;
+  const uint64_t Lv = (uint64_t)(b_lo & M30) * two30 + a60;                          // < 2^61
+  const uint64_t b30 = ((uint64_t)(b_hi >> 30) << 32) | funnel32(b_hi, b_lo, 30);    // (B mod 2^64) >> 30
+  const uint64_t V = a11 + b30 + (((uint64_t)bc4 << 32) | (a_hi >> 28));
+  const uint64_t W1 = (uint64_t)(uint32_t)V * delta + Lv;                           // < 2^62
+  const uint64_t P = (uint64_t)(uint32_t)(V >> 32) * delta + (uint32_t)(W1 >> 32);  // W >> 32, < 2^53
+  const uint32_t wh = funnel32((uint32_t)(P >> 32), (uint32_t)P, 28);               // W >> 60, < 2^25
+  const uint64_t wl = ((uint64_t)((uint32_t)P & M28) << 32) | (uint32_t)W1;          // W mod 2^60
+  const uint64_t X = (uint64_t)wh * delta + wl;                                     // < 2^60 + 2^45
+  const uint32_t ge = (uint32_t)((X + delta) >> 60);                                // X >= q
+  const uint64_t Z = (uint64_t)ge * delta + X;
+  return Z & ((1ull << 60) - 1);
+}
+
+// The same fold for three accumulators, T = a00 + am*2^30 + a11*2^60 (am
+// takes both cross products of 30-bit halves): exact for a00, am < 2^64 and
+// a11 < 2^63, which eight blocks of products (a00, a11 one per block, am
+// two) on top of a carried value below 2^60 + 2^45 in a00 satisfy.  CANON:
+// the result in [0, q); else X in [0, 2^60 + 2^45), congruent to T, which
+// is all a carried value needs.
+template <bool CANON>
+__host__ __device__ __forceinline__ uint64_t fold3_pm(uint64_t a00, uint64_t am, uint64_t a11, uint32_t delta,
+                                                      uint32_t two30) {
+  constexpr uint32_t M28 = (1u << 28) - 1, M30 = (1u << 30) - 1;
+  const uint32_t a_lo = (uint32_t)a00, a_hi = (uint32_t)(a00 >> 32);
+  const uint64_t a60 = ((uint64_t)(a_hi & M28) << 32) | a_lo;
+  const uint64_t Lv = (uint64_t)((uint32_t)am & M30) * two30 + a60;                 // < 2^61
+  const uint64_t V = a11 + (am >> 30) + (a_hi >> 28);                               // < 2^64
+  const uint64_t W1 = (uint64_t)(uint32_t)V * delta + Lv;                           // < 2^62
+  const uint64_t P = (uint64_t)(uint32_t)(V >> 32) * delta + (uint32_t)(W1 >> 32);  // W >> 32, < 2^53
+  const uint32_t wh = funnel32((uint32_t)(P >> 32), (uint32_t)P, 28);               // W >> 60, < 2^25
+  const uint64_t wl = ((uint64_t)((uint32_t)P & M28) << 32) | (uint32_t)W1;          // W mod 2^60
+  const uint64_t X = (uint64_t)wh * delta + wl;                                     // < 2^60 + 2^45
+  if (!CANON) return X;
+  const uint32_t ge = (uint32_t)((X + delta) >> 60);                                // X >= q
+  const uint64_t Z = (uint64_t)ge * delta + X;
+  return Z & ((1ull << 60) - 1);
 }
 
 // Exact sum of products in four accumulators: a00 + (a01 + a10)*2^30 +

@@ -30,7 +30,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in ("ntt_loge_small", "ntt_loge_large", "ntt_small_below",
                                                "mac_mt", "mac_rt", "layer_fused", "layer_split",
                                                "ntt_split_below", "ntt_fp64", "ks_fused",
-                                               "ntt_inv_split_below", "mac_lds")]
+                                               "ntt_inv_split_below", "mac_lds", "mac_tiles")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -73,11 +73,12 @@ def test_batch_equals_layer_and_oracle(ctx4096, schedule, graph):
 
 
 @pytest.mark.parametrize("lds", [0, 3])
-@pytest.mark.parametrize("tile", [(4, 2), (2, 4), (2, 2), (4, 4)])
+@pytest.mark.parametrize("tile", [(4, 2), (2, 4), (2, 2), (4, 4), (6, 4), (8, 4), (4, 8)])
 def test_batch_forced_tiles_and_timed_launch(ctx4096, tile, lds):
     """Every register tile the batch MAC is built for, forced through the
     context's tuning, gives the oracle's words; the timed eager launch gives
-    the same words and one duration per grid."""
+    the same words and one duration per grid.  (6,4), (8,4) and (4,8) exist
+    for the streamed MAC only (lds 0 falls back to (4,4))."""
     from paper_2506_11586_amd import heconv
     ctx, prm = ctx4096
     before = ctx.get_tuning().as_dict()
@@ -209,3 +210,61 @@ def test_full_fire_cnn_batched_sampled_against_oracle():
                 (cv, m, s, c, l, k)
     b.close()
     ctx.close()
+
+
+# Shapes whose channel blocks span one chunk of the streamed MAC (CB <= 8),
+# two (9-16) and three (17-24), so that carries between chunks and tile
+# boundaries inside a workgroup's stream are exercised, and shapes with
+# several spatial tiles (a tile's row pairs then span tiles and images);
+# N=4096, L=2.
+SHAPES_DEEP = [
+    ((256, 12, 12, 8, 3, 3, 1, 1), 2),
+    ((600, 5, 5, 6, 1, 1, 1, 0), 3),
+    ((4000, 4, 4, 7, 1, 1, 1, 0), 2),
+    ((6000, 4, 4, 3, 1, 1, 1, 0), 2),
+    ((40, 9, 9, 10, 3, 3, 2, 1), 4),
+    ((8, 64, 64, 5, 3, 3, 1, 1), 3),   # 3 spatial tiles: row pairs cross tiles and images
+    ((3, 60, 60, 4, 7, 7, 2, 3), 5),   # 2 spatial tiles, 20 rows
+]
+
+
+@pytest.fixture(scope="module")
+def deep_jobs(ctx4096):
+    ctx, prm = ctx4096
+    jobs, host = make_jobs(ctx, prm, SHAPES_DEEP, 500)
+    cbs = sorted({ctx.sizes(j[0]).CB for j in jobs})
+    assert cbs[0] <= 8 and any(8 < c <= 16 for c in cbs) and cbs[-1] > 16, cbs
+    pristine = [j[2].clone() for j in jobs]
+    want = []
+    for (d, B, d_in, wntt, d_out), (cv, _, _, x, K) in zip(jobs, host):
+        g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+        w_ntt = oracle.encode_weights(K, cv, g, prm)
+        want.append(oracle.conv_layer_ntt(x.reshape(B, g.CB, g.S, 2, prm.L, prm.N), w_ntt, B, g, cv.M, prm).reshape(-1))
+    return jobs, pristine, want
+
+
+@pytest.mark.parametrize("tile,lds,tiles", [
+    ((4, 4), 3, 0), ((4, 4), 2, 1), ((4, 4), 4, 3), ((4, 4), 3, 16),
+    ((6, 4), 3, 0), ((6, 4), 2, 2), ((6, 4), 4, 5),
+    ((8, 4), 3, 0), ((4, 8), 3, 2), ((4, 2), 3, 0), ((2, 4), 2, 7), ((2, 2), 4, 1)])
+def test_streamed_mac_chunks_and_tile_lists(ctx4096, deep_jobs, tile, lds, tiles):
+    """The streamed MAC (tiles decoded on the host, several per workgroup,
+    loads running ahead across tile boundaries, a fold every 8 channel blocks
+    carried in registers) on layers of 4 to 24 channel blocks: every output
+    word equals the oracle's, for each tile, LDS depth and tiles per
+    workgroup."""
+    from paper_2506_11586_amd import heconv
+    ctx, prm = ctx4096
+    jobs, pristine, want = deep_jobs
+    before = ctx.get_tuning().as_dict()
+    ctx.set_tuning(mac_mt=tile[0], mac_rt=tile[1], mac_lds=lds, mac_tiles=tiles)
+    b = heconv.Batch(ctx, jobs, schedule=1)
+    ctx.set_tuning(**before)
+    for j, p in zip(jobs, pristine):
+        j[2].copy_(p)
+        j[4].fill_(-1)
+    b.launch(graph=True)
+    b.status()
+    for j, w in zip(jobs, want):
+        assert np.array_equal(to_host(j[4]), w), (tile, lds, tiles, j[0])
+    b.close()
