@@ -227,6 +227,7 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
     k.c60 = (uint64_t)(((u128)1 << 60) % q), k.c60_sh = shoup(k.c60, q);
     k.delta = dl[l], k.delta_sh = shoup(dl[l], q);
     k.negq = 0 - q, k.neg2q = 0 - 2 * q;
+    k.three_q = 3 * q, k.neg3q = 0 - 3 * q;
     // the MAC's fold for q = 2^60 - delta, delta < 2^20 (modarith.h, fold30_pm)
     k.pmd = (q < (1ull << 60) && (1ull << 60) - q < (1ull << 20)) ? (1ull << 60) - q : 0;
     c->lc.push_back(k);

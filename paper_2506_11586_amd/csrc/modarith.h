@@ -23,6 +23,7 @@ struct LimbConst {
   uint64_t negq, neg2q;        // 2^64 - q and 2^64 - 2q
   uint64_t r64_sh63;           // Shoup quotient of 2^64 mod q at scale 2^63
   uint64_t pmd;                // delta when q = 2^60 - delta with delta < 2^20, else 0
+  uint64_t three_q, neg3q;     // 3q and 2^64 - 3q (the inverse transform's lazy bound)
 };
 
 // Device buffers are passed to the transform and MAC bodies as pointers in
@@ -75,7 +76,25 @@ __device__ __forceinline__ uint64_t mul_shoup63(uint64_t x, uint64_t w, uint64_t
   return x * w + hi * negq;
 }
 
-__device__ __forceinline__ uint64_t csub_neg(uint64_t x, uint64_t negm) {
+// The same quotient word without doubling x: top = floor(x*wsh / 2^64)
+// (x < 6q < 2^62.6 and wsh < 2^63 keep the three partial products' sum
+// below 2^64) approximates x*w/(2q) from below by less than 1 + x/2^64, so
+// r = x*w - top*2q lies in [0, 2q(1 + 6q/2^64)) within [0, 2.75q).  Two
+// instructions fewer than mul_shoup63 (no doubling of x), for callers whose
+// lazy bound allows 2.75q.  neg2q = 2^64 - 2q.
+__host__ __device__ __forceinline__ uint64_t mul_shoup_2q(uint64_t x, uint64_t w, uint64_t wsh, uint64_t neg2q) {
+  const uint32_t a0 = (uint32_t)x, a1 = (uint32_t)(x >> 32);
+  const uint32_t b0 = (uint32_t)wsh, b1 = (uint32_t)(wsh >> 32);
+  uint64_t s = (uint64_t)a1 * b0 + __umulhi(a0, b0);
+#ifdef __HIP_DEVICE_COMPILE__
+  __asm__("" : "+v"(s));  // keeps the three multiply-adds in this order (no re-association)
+#endif
+  s += (uint64_t)a0 * b1;
+  const uint64_t top = (uint64_t)a1 * b1 + (s >> 32);
+  return x * w + top * neg2q;
+}
+
+__host__ __device__ __forceinline__ uint64_t csub_neg(uint64_t x, uint64_t negm) {
   const uint64_t d = x + negm;
   return (int64_t)d < 0 ? x : d;
 }

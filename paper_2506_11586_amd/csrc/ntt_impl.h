@@ -7,9 +7,12 @@
 // (j >> (b+1))), n = log2 N; stages run from bit n-1 down to bit 0.  The
 // inverse (Gentleman-Sande) uses the same index with psi^-1 and runs from
 // bit 0 up; its last stage also applies N^-1.  Lazy reduction after Harvey:
-// forward values stay in [0, 4q), inverse values in [0, 2q), and every
-// stored word is canonical.  Every twiddle product has an input below
-// 4q < 2^62, as the scale-2^63 Shoup product (mul_shoup63) requires.
+// forward values stay in [0, 4q) (every twiddle product has an input below
+// 4q < 2^62, as the scale-2^63 Shoup product mul_shoup63 requires), inverse
+// values in [0, 3q): the sum is brought below 3q by one conditional
+// subtraction, the difference X - Y + 3q (below 6q) goes through
+// mul_shoup_2q, whose result stays below 2.75q.  Every stored word is
+// canonical.
 //
 // Thread/element mapping of a pass over bits [lo, lo+LOGE): register k of
 // thread t holds element j = (t mod 2^lo) | k << lo | (t >> lo) << (lo+LOGE).
@@ -70,7 +73,7 @@ template <int LOGN, int LOGE, int LO, int U0, bool LAST>
 __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LOGE], int tid, const Tw* __restrict__ tw,
                                          const LimbConst& c, uint32_t jb = 0) {
   const int high = tid >> LO;
-  const uint64_t q2 = c.two_q;
+  const uint64_t q3 = c.three_q;
 #pragma unroll
   for (int u = LOGE - 1; u >= U0; u--) {
     const int s = LOGN - LOGE - LO + u;
@@ -81,7 +84,7 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LOGE], int tid, cons
         const int k0 = e, k1 = e + half;
         uint64_t X = x[k0], Y = x[k1];
         x[k0] = csub_neg(mul_shoup_neg(X + Y, c.ninv, c.ninv_sh, c.negq), c.negq);
-        x[k1] = csub_neg(mul_shoup_neg(X - Y + q2, c.ninv_w, c.ninv_w_sh, c.negq), c.negq);
+        x[k1] = csub_neg(mul_shoup_neg(X - Y + q3, c.ninv_w, c.ninv_w_sh, c.negq), c.negq);
       }
       continue;
     }
@@ -92,8 +95,8 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LOGE], int tid, cons
       for (int e = 0; e < half; e++) {
         const int k0 = g * 2 * half + e, k1 = k0 + half;
         uint64_t X = x[k0], Y = x[k1];
-        x[k0] = csub_neg(X + Y, c.neg2q);
-        x[k1] = mul_shoup63(X - Y + q2, t.w, t.wsh, c.negq);
+        x[k0] = csub_neg(X + Y, c.neg3q);
+        x[k1] = mul_shoup_2q(X - Y + q3, t.w, t.wsh, c.neg2q);
       }
     }
   }

@@ -164,8 +164,8 @@ __global__ __launch_bounds__(PROBE_THREADS) void probe_bfly_kernel(const uint64_
         const int k0 = e, k1 = e + 8;
         if (INVERSE) {
           const uint64_t X = x[k0], Y = x[k1];
-          x[k0] = csub_neg(X + Y, c.neg2q);
-          x[k1] = mul_shoup63(X - Y + q2, w, wsh, c.negq);
+          x[k0] = csub_neg(X + Y, c.neg3q);
+          x[k1] = mul_shoup_2q(X - Y + c.three_q, w, wsh, c.neg2q);
         } else {
           const uint64_t X = csub_neg(x[k0], c.neg2q);
           const uint64_t T = mul_shoup63(x[k1], w, wsh, c.negq);
