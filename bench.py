@@ -528,7 +528,7 @@ def run_probes(torch, heconv):
             ("mul_hi_u32", heconv.PROBE_MUL_HI_U32, 3000, "lane ops/s"),
             ("mul_lo_u32", heconv.PROBE_MUL_LO_U32, 3000, "lane ops/s"),
             ("add_u32", heconv.PROBE_ADD_U32, 3000, "lane ops/s"),
-            ("mac_mix", heconv.PROBE_MAC_MIX, 300, "modmul-adds/s (4x4 tile, fold per 16 blocks)"),
+            ("mac_mix", heconv.PROBE_MAC_MIX, 300, "modmul-adds/s (6x4 tile, three accumulators, carry per 8 blocks)"),
             ("intt_mix", heconv.PROBE_INTT_MIX, 900, "butterflies/s"),
             ("ntt_mix", heconv.PROBE_NTT_MIX, 900, "butterflies/s")]
     out = {}
@@ -677,7 +677,7 @@ def run_bottleneck_main(torch, heconv, args, probes):
     if probes:
         mix = probes["mac_mix"]["rate"] / 1e9
         roofline["measured_mix_ceiling"] = {"rate": round(mix, 1), "frac": round(achieved / mix, 4),
-                                            "note": "the MAC's own step and fold on registers, 16-block chunks"}
+                                            "note": "the streamed MAC's own step and carry on registers (6x4 tile, 8-block chunks)"}
     roofline_hbm = {"bound": "hbm", "kernel": "batch_mac_kernel", "achieved": kavg["batch_mac"]["GBps"],
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kavg["batch_mac"]["GBps"] / HBM_PEAK_GBS, 4)}
     inv_t = kavg["batch_inv"]["ms_per_pass"] * 1e-3

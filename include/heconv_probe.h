@@ -26,7 +26,7 @@ enum {
   HE_PROBE_MUL_HI_U32 = 1,  /* v_mul_hi_u32, lane operations/s */
   HE_PROBE_MUL_LO_U32 = 2,  /* v_mul_lo_u32, lane operations/s */
   HE_PROBE_ADD_U32 = 3,     /* v_add_u32 (full-rate reference), lane operations/s */
-  HE_PROBE_MAC_MIX = 4,     /* the MAC's 4x4-tile channel-block step and fold, products/s */
+  HE_PROBE_MAC_MIX = 4,     /* the batch MAC's 6x4-tile channel-block step and carry, products/s */
   HE_PROBE_INTT_MIX = 5,    /* the inverse transform's butterfly, butterflies/s */
   HE_PROBE_NTT_MIX = 6      /* the forward transform's butterfly, butterflies/s */
 };

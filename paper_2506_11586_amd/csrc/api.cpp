@@ -228,10 +228,12 @@ he_status he_ctx_create(const he_params* prm, he_ctx** out) {
     k.delta = dl[l], k.delta_sh = shoup(dl[l], q);
     k.negq = 0 - q, k.neg2q = 0 - 2 * q;
     k.three_q = 3 * q, k.neg3q = 0 - 3 * q;
-    // the MAC's fold for q = 2^60 - delta, delta < 2^20 (modarith.h, fold30_pm)
+    // the MAC's folds for q = 2^60 - delta, delta < 2^20 (modarith.h, fold30_pm, fold3_pm)
     k.pmd = (q < (1ull << 60) && (1ull << 60) - q < (1ull << 20)) ? (1ull << 60) - q : 0;
     c->lc.push_back(k);
   }
+  c->all_pm = true;
+  for (const heconv::LimbConst& k : c->lc) c->all_pm &= k.pmd != 0;
   // client-side decoding constants (power-of-two t only)
   std::vector<heconv::DecodeConst> dc(L);
   c->decode_ok = c->proto_ok && c->t >= 2 && c->t < (1ull << 62);
@@ -445,7 +447,7 @@ he_status he_conv_ntt_mac(const he_ctx* c, const he_conv_desc* d, uint32_t B, co
   if (!d_in_ntt || !d_wntt || !d_out_ntt) return HE_EINVAL;
   if ((uint64_t)B * g.S * 2 > 0xffffffffull || !heconv::mac_offsets_fit(g, c->L, c->N)) return HE_ESHAPE;
   return dev_err(heconv::mac_launch(d_in_ntt, d_wntt, d_out_ntt, B, g.CB, g.S, d->M, c->L, c->N, c->d_lc,
-                                    c->tune.mac_mt, c->tune.mac_rt, c->tune.mac_lds, (hipStream_t)stream));
+                                    c->tune.mac_mt, c->tune.mac_rt, c->tune.mac_lds, c->all_pm, (hipStream_t)stream));
 }
 
 he_status he_conv_mac_intt(const he_ctx* c, const he_conv_desc* d, uint32_t B, const uint64_t* d_in_ntt,
@@ -489,7 +491,7 @@ he_status he_conv_layer(const he_ctx* c, const he_conv_desc* d, uint32_t B, uint
     const uint32_t m_end = p + 1 == P ? d->M : (uint32_t)((uint64_t)d->M * (p + 1) / P) & ~3u;
     const uint32_t Mp = m_end - m0;
     s = dev_err(heconv::mac_launch(d_in, d_wntt + m0 * w_per_m, d_out + m0 * out_per_m, 1, g.CB, g.S, Mp, c->L,
-                                   c->N, c->d_lc, c->tune.mac_mt, c->tune.mac_rt, c->tune.mac_lds, st));
+                                   c->N, c->d_lc, c->tune.mac_mt, c->tune.mac_rt, c->tune.mac_lds, c->all_pm, st));
     if (s) return s;
     if (hipEventRecord(c->ev_mac[p], st) != hipSuccess || hipStreamWaitEvent(c->aux, c->ev_mac[p], 0) != hipSuccess)
       return HE_EDEVICE;

@@ -70,8 +70,8 @@ __global__ __launch_bounds__(BATCH_MAC_THREADS) void batch_mac_stream_kernel(con
                                                                               const LimbConst* __restrict__ lcs,
                                                                               uint32_t L, uint32_t logN) {
   __shared__ uint64_t lds[mac_dma_lds_words<MT, RT, BATCH_MAC_THREADS, P>()];
-  mac_stream<MT, RT, BATCH_MAC_THREADS, P, PM>(items + (uint64_t)blockIdx.x * per_wg, per_wg, jobs, lcs, L, logN, lds,
-                                           threadIdx.x);
+  const MacListSrc src{items + (uint64_t)blockIdx.x * per_wg, per_wg, jobs};
+  mac_stream<MT, RT, BATCH_MAC_THREADS, P, PM>(src, lcs, L, logN, lds, threadIdx.x);
 }
 
 template <int LOGN, int LOGE>

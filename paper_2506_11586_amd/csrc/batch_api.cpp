@@ -63,10 +63,9 @@ void free_batch(he_batch* b) {
 
 heconv::BatchArgs args_of(const he_batch* b) {
   const he_ctx* c = b->ctx;
-  uint32_t all_pm = 1;
-  for (const heconv::LimbConst& k : c->lc) all_pm &= k.pmd != 0;
   return heconv::BatchArgs{b->d_jobs, c->d_fwd, c->d_inv, c->d_lc, c->L, c->N, c->logN,
-                           c->tune.ntt_loge_small, c->tune.ntt_loge_large, b->mac_mt, b->mac_rt, b->mac_lds, all_pm};
+                           c->tune.ntt_loge_small, c->tune.ntt_loge_large, b->mac_mt, b->mac_rt, b->mac_lds,
+                           c->all_pm ? 1u : 0u};
 }
 
 bool pipelined(const he_batch* b) { return b->schedule == HE_SCHED_PIPELINED_4 || b->schedule == HE_SCHED_PIPELINED_8; }

@@ -17,6 +17,7 @@ struct he_ctx {
   bool proto_ok = false;  // t usable by the protocol steps (delta_l != 0)
   std::vector<uint64_t> q, psi;
   std::vector<heconv::LimbConst> lc;
+  bool all_pm = false;  // every q_l = 2^60 - delta, delta < 2^20
   heconv::Tw* d_fwd = nullptr;  // [L][N] psi^brv(k) with Shoup quotient
   heconv::Tw* d_inv = nullptr;  // [L][N] psi^-brv(k) with Shoup quotient
   heconv::LimbConst* d_lc = nullptr;

@@ -92,13 +92,15 @@ hipError_t pack_weights_launch(const PackGeom& g, const int64_t* w, uint64_t* ou
                                hipStream_t st);
 
 // out[b][m][s][c][l][k] = sum_cb in[b][cb][s][c][l][k] * w[m][cb][l][k] mod q_l.
-// (mt, rt): output channels x rows per thread; (0, 0) picks by shape.
-// lds_stages: 0 = operands loaded into registers, 2..4 = staged in LDS that
-// many channel blocks ahead (tiles with even mt and rt whose weight pairs
-// fit 32-bit offsets; others take the register loads).
+// (mt, rt): output channels x rows per thread; (0, 0), or a pair the chosen
+// kernel is not built for, picks by shape.  lds_stages: 0 = operands loaded
+// into registers (mac_tile), 2..4 = the streamed MAC (mac_stream) staging
+// them in LDS that many channel blocks ahead, for layers whose weight pairs
+// fit 32-bit offsets (others take the register loads).  all_pm: every q_l is
+// 2^60 - delta, delta < 2^20 (the streamed MAC's short fold).
 hipError_t mac_launch(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t B, uint32_t CB, uint32_t S,
                       uint32_t M, uint32_t L, uint32_t N, const LimbConst* lc, uint32_t mt, uint32_t rt,
-                      uint32_t lds_stages, hipStream_t st);
+                      uint32_t lds_stages, bool all_pm, hipStream_t st);
 
 // Whether the LDS-staged MAC can take a layer: two output channels' weights
 // (2*CB*L*N words) below 2^31 bytes.

@@ -220,17 +220,11 @@ __device__ __forceinline__ void mac_tile(cgword* __restrict__ in, cgword* __rest
 }
 
 // ---------------------------------------------------------------------------
-// The same tile with its operands staged in LDS by direct buffer-to-LDS
-// loads (gfx950 buffer_load_dwordx4 ... lds), P channel blocks ahead.  Every
-// wave streams its own 64 NTT points through a private ring of P stages of
-// MT + RT rows (512 bytes a row), so no workgroup barrier is needed: a
-// wave's loads into LDS count in its own vmcnt, and a stage is read once the
-// loads issued after it are the only ones outstanding.  The loads in flight
-// no longer hold registers, so the register tile keeps its size while P - 1
-// blocks of loads stay in flight during the products.  One load instruction
-// fills two rows: lanes 0-31 read 16 bytes each of the first row's 512,
-// lanes 32-63 of the second's; input rows pair up as the two components of
-// one ciphertext, weight rows as two consecutive output channels.
+// Helpers of the streamed MAC (mac_stream.h), whose operands are staged in
+// LDS by direct buffer-to-LDS loads (gfx950 buffer_load_dwordx4 ... lds):
+// every wave streams its own 64 NTT points through a private ring of P
+// stages of MT + RT rows (512 bytes a row), one load instruction filling two
+// rows (lanes 0-31 the first row's 512 bytes, lanes 32-63 the second's).
 // LDS per workgroup: (THREADS / 64) * P * (MT + RT) * 512 bytes.
 // ---------------------------------------------------------------------------
 template <int MT, int RT, int THREADS, int P>
@@ -250,118 +244,6 @@ template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
   static_assert(N >= 0 && N < 64, "vmcnt is six bits");
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
-
-template <int MT, int RT, int THREADS, int P>
-__device__ __forceinline__ void mac_tile_dma(cgword* __restrict__ in, cgword* __restrict__ w, gword* __restrict__ out,
-                                             uint32_t CB, uint32_t S, uint32_t M, uint32_t L, uint32_t N,
-                                             uint32_t rows, uint32_t kc, uint32_t mt, uint32_t rt, const LimbConst& c,
-                                             int tid, uint64_t* lds) {
-  static_assert(MT % 2 == 0 && RT % 2 == 0 && P >= 2, "rows are loaded in pairs");
-  constexpr int ROWS = MT + RT, PIN = RT / 2, PW = MT / 2, PAIRS = PIN + PW;
-  const uint32_t chunks_per_limb = N / THREADS;
-  const uint32_t l = kc / chunks_per_limb;
-  // wave index in a scalar register: the LDS address of a load into LDS is
-  // one value per wave (M0)
-  const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6), lane = (uint32_t)tid & 63;
-  // the wave's 64 points: k = kofs + lane
-  const uint64_t kofs = (uint64_t)l * N + (kc % chunks_per_limb) * THREADS + wave * 64;
-  const uint64_t LN = (uint64_t)L * N;
-  const uint64_t in_cb_stride = (uint64_t)S * 2 * LN;
-  const uint64_t out_m_stride = (uint64_t)S * 2 * LN;
-  // rows 2p, 2p+1 of the tile are components a and b of one ciphertext
-  // (rows is even, rt*RT is even); pairs past the end read pair 0
-  __amdgpu_buffer_rsrc_t ib[PIN], wb[PW];
-  uint64_t out_off[RT];
-  bool rv[RT];
-#pragma unroll
-  for (int p = 0; p < PIN; p++) {
-    const uint32_t r = rt * RT + 2 * p;
-    const bool ok = r < rows;
-    rv[2 * p] = rv[2 * p + 1] = ok;
-    const uint32_t bs = (ok ? r : 0) >> 1;
-    const uint32_t b = bs / S, s = bs % S;
-    const uint64_t base = ((((uint64_t)b * CB) * S + s) * 2) * LN + kofs;
-    ib[p] = mac_rsrc((const uint64_t*)in + uniform64(base), (uint64_t)CB * in_cb_stride * 8);
-    const uint64_t ob = ((((uint64_t)b * M) * S + s) * 2) * LN + kofs;
-    out_off[2 * p] = ob, out_off[2 * p + 1] = ob + LN;
-  }
-  bool mv[MT];
-  uint32_t w2[PW];  // byte offset of the pair's second channel (0 when it is past the end)
-#pragma unroll
-  for (int p = 0; p < PW; p++) {
-    const uint32_t m = mt * MT + 2 * p;
-    mv[2 * p] = m < M, mv[2 * p + 1] = m + 1 < M;
-    wb[p] = mac_rsrc((const uint64_t*)w + uniform64(((uint64_t)(m < M ? m : 0) * CB) * LN + kofs),
-                     (uint64_t)2 * CB * LN * 8);
-    w2[p] = m + 1 < M ? (uint32_t)(CB * LN * 8) : 0u;
-  }
-  // lanes 0-31 load 16 bytes of the first row, lanes 32-63 of the second
-  const uint32_t half = lane >> 5, lo16 = (lane & 31) * 16;
-  const uint32_t in_lane = lo16 + half * (uint32_t)(LN * 8);
-  uint32_t w_lane[PW];
-#pragma unroll
-  for (int p = 0; p < PW; p++) w_lane[p] = lo16 + half * w2[p];
-  uint64_t* ring = lds + (uint64_t)wave * P * ROWS * 64;
-
-  auto issue = [&](uint32_t cbx, int stage) {
-    uint64_t* st = ring + (uint32_t)stage * ROWS * 64;
-#pragma unroll
-    for (int p = 0; p < PIN; p++) mac_dma_load(ib[p], st + (2 * p) * 64, in_lane, (uint32_t)(cbx * in_cb_stride * 8));
-#pragma unroll
-    for (int p = 0; p < PW; p++)
-      mac_dma_load(wb[p], st + (RT + 2 * p) * 64, w_lane[p], (uint32_t)(cbx * LN * 8));
-  };
-
-  uint64_t a00[MT][RT], a01[MT][RT], a10[MT][RT], a11[MT][RT];
-#pragma unroll
-  for (int j = 0; j < MT; j++)
-#pragma unroll
-    for (int i = 0; i < RT; i++) a00[j][i] = a01[j][i] = a10[j][i] = a11[j][i] = 0;
-
-  // prologue: blocks 0 .. P-2 (the last block again past the end, so that
-  // every iteration has the same number of loads outstanding)
-#pragma unroll
-  for (int s0 = 0; s0 < P - 1; s0++) issue((uint32_t)s0 < CB ? (uint32_t)s0 : CB - 1, s0);
-  uint32_t chunk_end = CB < MAC_CHUNK ? CB : MAC_CHUNK;
-  for (uint32_t cb = 0; cb < CB; cb++) {
-    const uint32_t pf = cb + P - 1;
-    issue(pf < CB ? pf : CB - 1, (int)(pf % P));
-    // block cb's loads were followed by (P - 1) * PAIRS others
-    wait_vmcnt<(P - 1) * PAIRS>();
-    __asm__ volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-    const uint64_t* st = ring + (cb % P) * ROWS * 64 + lane;
-    // the rows' halves, one weight row at a time (fewer live registers)
-    Half30 xs[RT];
-#pragma unroll
-    for (int i = 0; i < RT; i++) xs[i] = split30(st[i * 64]);
-#pragma unroll
-    for (int j = 0; j < MT; j++) {
-      const Half30 ws = split30(st[(RT + j) * 64]);
-#pragma unroll
-      for (int i = 0; i < RT; i++) {
-        a00[j][i] += (uint64_t)xs[i].lo * ws.lo;
-        a01[j][i] += (uint64_t)xs[i].lo * ws.hi;
-        a10[j][i] += (uint64_t)xs[i].hi * ws.lo;
-        a11[j][i] += (uint64_t)xs[i].hi * ws.hi;
-      }
-    }
-    if (cb + 1 == chunk_end && chunk_end < CB) {  // the last chunk's fold is the store's
-      mac_fold<MT, RT>(a00, a01, a10, a11, c);
-      chunk_end = chunk_end + MAC_CHUNK < CB ? chunk_end + MAC_CHUNK : CB;
-    }
-    // the next load into this stage must not pass the reads above
-    __asm__ volatile("" ::: "memory");
-  }
-  wait_vmcnt<0>();  // no load into LDS outlives the wave
-  uint64_t obase[RT];
-#pragma unroll
-  for (int i = 0; i < RT; i++) obase[i] = out_off[i] + (uint64_t)(mt * MT) * out_m_stride;
-  if (c.pmd)
-    mac_store<MT, RT, true>(a00, a01, a10, a11, c, out, obase, out_m_stride, mv, rv, lane);
-  else
-    mac_store<MT, RT, false>(a00, a01, a10, a11, c, out, obase, out_m_stride, mv, rv, lane);
 }
 
 }  // namespace heconv

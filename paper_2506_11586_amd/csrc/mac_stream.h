@@ -1,13 +1,15 @@
-// Streamed channel-block MAC for the batch executor (device part).
+// Streamed channel-block MAC (device part), for the batch executor and the
+// per-layer MAC.
 //
-// Each workgroup runs a short list of MAC tiles (consecutive tiles of one
-// XCD's share, decoded on the host into MacItems) as one continuous stream
+// A batch workgroup runs a short list of MAC tiles (consecutive tiles of one
+// XCD's share, decoded on the host into MacItems; the per-layer kernel runs
+// one tile decoded from its block index) as one continuous stream
 // of channel blocks per wave: the direct buffer-to-LDS loads run P - 1
 // blocks ahead of the products across tile boundaries, so the next tile's
 // first blocks are in flight while the current tile's sums are folded and
 // stored, and a tile costs no start-up latency and no integer division.
 //
-// Same sums as mac_tile / mac_tile_dma (Out[(b,s,c), m] = sum_cb
+// Same sums as mac_tile (Out[(b,s,c), m] = sum_cb
 // In[(b,s,c), cb] * W[cb, m] mod q at every NTT point, Sec. 6.2), with three
 // accumulators per output instead of four: a00 += lo*lo, am += lo*hi +
 // hi*lo, a11 += hi*hi over the operands' 30-bit halves.  The two cross
@@ -19,7 +21,7 @@
 // 2^60 + 2^45), kept whole in a00 (am and a11 restart at zero, so only a00
 // is carried from chunk to chunk in registers).
 //
-// Wave layout as in mac_tile_dma: each wave streams its own 64 NTT points
+// Wave layout (see mac_impl.h): each wave streams its own 64 NTT points
 // of the tile through a private LDS ring of P stages of MT + RT rows (512
 // bytes a row), one load instruction filling two rows (lanes 0-31 the first
 // row's 512 bytes, lanes 32-63 the second's).  No workgroup barrier: a
@@ -110,15 +112,38 @@ __device__ __forceinline__ void mac_stream_wait(uint32_t ahead) {
   wait_vmcnt<0>();
 }
 
-// The tiles items[0 .. n) of the calling workgroup (valid ones first), for
-// the calling wave's 64 points of each.  PM: every limb's prime is
-// 2^60 - delta (fold3_pm), else the Shoup fold of any prime (fold30); a
-// compile-time choice, so that the fold code has one path and the
-// accumulators stay in their registers across it.
-template <int MT, int RT, int THREADS, int P, bool PM>
-__device__ __forceinline__ void mac_stream(const MacItem* __restrict__ items, uint32_t n,
-                                           const BatchJob* __restrict__ jobs, const LimbConst* __restrict__ lcs,
-                                           uint32_t L, uint32_t logN, uint64_t* lds, int tid) {
+// Tile sources: count() tiles, get(i) the tile and its job.
+// A batch workgroup's list: items[0 .. n), valid ones first.
+struct MacListSrc {
+  const MacItem* __restrict__ items;
+  uint32_t n;
+  const BatchJob* __restrict__ jobs;
+  __device__ __forceinline__ uint32_t count() const {
+    uint32_t nv = 0;
+    while (nv < n && items[nv].job != BATCH_NO_JOB) nv++;
+    return nv;
+  }
+  __device__ __forceinline__ void get(uint32_t i, MacItem& it, BatchJob& jd) const {
+    it = items[i];
+    jd = jobs[it.job];
+  }
+};
+
+// One tile of one layer, decoded by the caller.
+struct MacOneSrc {
+  MacItem it;
+  BatchJob jd;
+  __device__ __forceinline__ uint32_t count() const { return 1; }
+  __device__ __forceinline__ void get(uint32_t, MacItem& i, BatchJob& j) const { i = it, j = jd; }
+};
+
+// The source's tiles, for the calling wave's 64 points of each.  PM: every
+// limb's prime is 2^60 - delta (fold3_pm), else the Shoup fold of any prime
+// (fold30); a compile-time choice, so that the fold code has one path and
+// the accumulators stay in their registers across it.
+template <int MT, int RT, int THREADS, int P, bool PM, class Src>
+__device__ __forceinline__ void mac_stream(const Src& src, const LimbConst* __restrict__ lcs, uint32_t L,
+                                           uint32_t logN, uint64_t* lds, int tid) {
   static_assert(MT % 2 == 0 && RT % 2 == 0 && P >= 2 && P <= 4, "rows are loaded in pairs");
   constexpr int PIN = RT / 2, PW = MT / 2, PAIRS = PIN + PW, ROWS = MT + RT;
   const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6), lane = (uint32_t)tid & 63;
@@ -127,9 +152,7 @@ __device__ __forceinline__ void mac_stream(const MacItem* __restrict__ items, ui
   const uint32_t in_lane = lo16 + half * LN8;
   uint64_t* ring = lds + (uint64_t)wave * P * ROWS * 64;
 
-  // tiles of this workgroup: the valid ones come first
-  uint32_t nv = 0;
-  while (nv < n && items[nv].job != BATCH_NO_JOB) nv++;
+  const uint32_t nv = src.count();
   if (nv == 0) return;
 
   // load cursor: tile li, its block lcb
@@ -137,8 +160,10 @@ __device__ __forceinline__ void mac_stream(const MacItem* __restrict__ items, ui
   MacLoad<MT, RT> ld;
   uint32_t w_lane[PW];
   auto load_tile = [&](uint32_t i) {
-    const MacItem it = items[i];
-    mac_stream_decode<MT, RT>(it, jobs[it.job], L, logN, wave, &ld, (MacStore<MT, RT>*)nullptr);
+    MacItem it;
+    BatchJob jd;
+    src.get(i, it, jd);
+    mac_stream_decode<MT, RT>(it, jd, L, logN, wave, &ld, (MacStore<MT, RT>*)nullptr);
 #pragma unroll
     for (int p = 0; p < PW; p++) w_lane[p] = lo16 + half * ld.w2[p];
   };
@@ -159,9 +184,11 @@ __device__ __forceinline__ void mac_stream(const MacItem* __restrict__ items, ui
   // compute cursor: tile ci
   uint32_t ci = 0;
   MacStore<MT, RT> sd;
-  const MacItem it0 = items[0];
-  gword* out = as_global(jobs[it0.job].out);
-  mac_stream_decode<MT, RT>(it0, jobs[it0.job], L, logN, wave, (MacLoad<MT, RT>*)nullptr, &sd);
+  MacItem it0;
+  BatchJob jd0;
+  src.get(0, it0, jd0);
+  gword* out = as_global(jd0.out);
+  mac_stream_decode<MT, RT>(it0, jd0, L, logN, wave, (MacLoad<MT, RT>*)nullptr, &sd);
   LimbConst c = lcs[sd.l];
 
   load_tile(0);
@@ -225,9 +252,11 @@ __device__ __forceinline__ void mac_stream(const MacItem* __restrict__ items, ui
         }
       }
     if (++ci == nv) break;
-    const MacItem it = items[ci];
-    out = as_global(jobs[it.job].out);
-    mac_stream_decode<MT, RT>(it, jobs[it.job], L, logN, wave, (MacLoad<MT, RT>*)nullptr, &sd);
+    MacItem it;
+    BatchJob jd;
+    src.get(ci, it, jd);
+    out = as_global(jd.out);
+    mac_stream_decode<MT, RT>(it, jd, L, logN, wave, (MacLoad<MT, RT>*)nullptr, &sd);
     c = lcs[sd.l];
   }
   wait_vmcnt<0>();  // no load into LDS outlives the wave

@@ -8,11 +8,12 @@
 //  HE_PROBE_MUL_HI_U32   v_mul_hi_u32, lane operations/s
 //  HE_PROBE_MUL_LO_U32   v_mul_lo_u32, lane operations/s
 //  HE_PROBE_ADD_U32      v_add_u32 (a full-rate reference), lane operations/s
-//  HE_PROBE_MAC_MIX      the MAC's channel-block step for a 4x4 register tile
-//                        (30-bit splits, four multiply-adds per product, one
-//                        fold per 16 blocks), products/s
-//  HE_PROBE_INTT_MIX     the inverse transform's butterfly (lazy sum, scale-2^63
-//                        Shoup product of the difference), butterflies/s
+//  HE_PROBE_MAC_MIX      the batch MAC's channel-block step for its 6x4 tile
+//                        (30-bit splits, four multiply-adds per product into
+//                        three accumulators, one carry per 8 blocks),
+//                        products/s
+//  HE_PROBE_INTT_MIX     the inverse transform's butterfly (lazy sum below 3q,
+//                        mul_shoup_2q of the difference), butterflies/s
 //  HE_PROBE_NTT_MIX      the forward transform's butterfly, butterflies/s
 #include <hip/hip_runtime.h>
 
@@ -106,40 +107,61 @@ __global__ __launch_bounds__(PROBE_THREADS) void probe_add_kernel(const uint32_t
   out[t] = s;
 }
 
-// The MAC's compute for a 4x4 tile: per iteration 16 channel blocks of
-// mac_step on operands in registers, then the fold of every (m, row) pair
-// (mac_fold: the fold of the context's first prime) -- the arithmetic of one
-// 16-block chunk of mac_tile without its loads.
+// The batch MAC's compute for its default 6x4 tile (mac_stream): per
+// iteration 8 channel blocks of 30-bit splits and four multiply-adds per
+// product into three accumulators, then the carry of every (m, row) pair
+// (fold3_pm of the context's first prime, the unreduced value seeding a00)
+// -- the arithmetic of one 8-block chunk without its loads.
 __global__ __launch_bounds__(PROBE_THREADS) void probe_mac_kernel(const uint64_t* __restrict__ seed, uint64_t* out,
                                                                   uint32_t iters, const LimbConst* __restrict__ lcs) {
-  constexpr int MT = 4, RT = 4;
+  constexpr int MT = 6, RT = 4;
   const uint32_t t = blockIdx.x * PROBE_THREADS + threadIdx.x;
   const LimbConst c = lcs[0];
+  const uint32_t delta = (uint32_t)c.pmd, two30 = (uint32_t)c.c30;
   uint64_t xr[RT], wr[MT];
 #pragma unroll
   for (int i = 0; i < RT; i++) xr[i] = (seed[(threadIdx.x + i) & 63] + t) % c.q;
 #pragma unroll
   for (int j = 0; j < MT; j++) wr[j] = (seed[(threadIdx.x + 5 * j + 11) & 63] + t) % c.q;
-  uint64_t a00[MT][RT], a01[MT][RT], a10[MT][RT], a11[MT][RT];
+  uint64_t a00[MT][RT], am[MT][RT], a11[MT][RT];
 #pragma unroll
   for (int j = 0; j < MT; j++)
 #pragma unroll
-    for (int i = 0; i < RT; i++) a00[j][i] = a01[j][i] = a10[j][i] = a11[j][i] = 0;
+    for (int i = 0; i < RT; i++) a00[j][i] = am[j][i] = a11[j][i] = 0;
   for (uint32_t it = 0; it < iters; it++) {
-    for (int cb = 0; cb < (int)MAC_CHUNK; cb++) {
-      mac_step<MT, RT>(xr, wr, a00, a01, a10, a11);
+    for (int cb = 0; cb < 8; cb++) {
+      Half30 xs[RT];
+#pragma unroll
+      for (int i = 0; i < RT; i++) xs[i] = split30(xr[i]);
+#pragma unroll
+      for (int j = 0; j < MT; j++) {
+        const Half30 ws = split30(wr[j]);
+#pragma unroll
+        for (int i = 0; i < RT; i++) {
+          a00[j][i] += (uint64_t)xs[i].lo * ws.lo;
+          am[j][i] += (uint64_t)xs[i].lo * ws.hi;
+          am[j][i] += (uint64_t)xs[i].hi * ws.lo;
+          a11[j][i] += (uint64_t)xs[i].hi * ws.hi;
+        }
+      }
       // the next block's operands count as new values (no arithmetic), so
       // every block splits its operands again as the kernel does
       __asm__ volatile("" : "+v"(xr[0]), "+v"(xr[1]), "+v"(xr[2]), "+v"(xr[3]));
-      __asm__ volatile("" : "+v"(wr[0]), "+v"(wr[1]), "+v"(wr[2]), "+v"(wr[3]));
+      __asm__ volatile("" : "+v"(wr[0]), "+v"(wr[1]), "+v"(wr[2]), "+v"(wr[3]), "+v"(wr[4]), "+v"(wr[5]));
     }
-    mac_fold<MT, RT>(a00, a01, a10, a11, c);
+#pragma unroll
+    for (int j = 0; j < MT; j++)
+#pragma unroll
+      for (int i = 0; i < RT; i++) {
+        a00[j][i] = fold3_pm<false>(a00[j][i], am[j][i], a11[j][i], delta, two30);
+        am[j][i] = a11[j][i] = 0;
+      }
   }
   uint64_t s = 0;
 #pragma unroll
   for (int j = 0; j < MT; j++)
 #pragma unroll
-    for (int i = 0; i < RT; i++) s ^= a00[j][i] | (a01[j][i] << 30);
+    for (int i = 0; i < RT; i++) s ^= a00[j][i];
   out[t] = s;
 }
 
@@ -222,7 +244,7 @@ extern "C" he_status he_probe_valu(const he_ctx* ctx, uint32_t which, uint32_t i
       case HE_PROBE_MAC_MIX:
         if (!lc) return hipErrorInvalidValue;
         hipLaunchKernelGGL(probe_mac_kernel, dim3(blocks), dim3(PROBE_THREADS), 0, st, d_seed, d_out, iters, lc);
-        per_thread_iter = 16.0 * MAC_CHUNK;  // 4x4 products per block
+        per_thread_iter = 24.0 * 8;  // 6x4 products per block, 8 blocks
         break;
       case HE_PROBE_INTT_MIX:
         if (!lc) return hipErrorInvalidValue;

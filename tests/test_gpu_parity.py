@@ -117,7 +117,7 @@ MAC_CASES = [  # (shape, params, packing, B)
 ]
 
 
-MAC_TILES = [(0, 0), (4, 4), (4, 2), (2, 4), (8, 2), (2, 8), (8, 1), (1, 8), (2, 2)]
+MAC_TILES = [(0, 0), (4, 4), (4, 2), (2, 4), (8, 2), (2, 8), (8, 1), (1, 8), (2, 2), (6, 4), (8, 4)]
 
 
 @pytest.mark.parametrize("shape,params,packing,B", MAC_CASES)
