@@ -668,7 +668,7 @@ def run_bottleneck_main(torch, heconv, args, probes):
     achieved = alg["batch_mac"]["modmul_adds"] / mac_t / 1e9
     peak = VALU_LANE_OPS_PEAK * MAD_RATE_FRAC / 4 / 1e9
     traffic = load_traffic("batch_mac", cfg["name"])
-    roofline = {"bound": "alu", "kernel": "batch_mac_kernel (MAC grid of the batch)", "achieved": round(achieved, 1),
+    roofline = {"bound": "alu", "kernel": "batch_mac_stream_kernel (the batch's streamed MAC grid)", "achieved": round(achieved, 1),
                 "peak": round(peak, 1), "unit": "G modmul-adds/s", "frac": round(achieved / peak, 4),
                 "traffic": traffic,
                 "peak_derivation": "256 CUs x 64 lanes x 2.4 GHz (v_mad_u64_u32 issues at the full rate) / 4 "
@@ -678,7 +678,7 @@ def run_bottleneck_main(torch, heconv, args, probes):
         mix = probes["mac_mix"]["rate"] / 1e9
         roofline["measured_mix_ceiling"] = {"rate": round(mix, 1), "frac": round(achieved / mix, 4),
                                             "note": "the streamed MAC's own step and carry on registers (6x4 tile, 8-block chunks)"}
-    roofline_hbm = {"bound": "hbm", "kernel": "batch_mac_kernel", "achieved": kavg["batch_mac"]["GBps"],
+    roofline_hbm = {"bound": "hbm", "kernel": "batch_mac_stream_kernel", "achieved": kavg["batch_mac"]["GBps"],
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kavg["batch_mac"]["GBps"] / HBM_PEAK_GBS, 4)}
     inv_t = kavg["batch_inv"]["ms_per_pass"] * 1e-3
     bfly = alg["batch_inv"]["modmuls"] / inv_t / 1e9
