@@ -215,9 +215,14 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
       off[ch][ph] = items.size();
       if (ph == 1 && b->mac_lds >= 2) {
         // streamed MAC: XCD x takes the x-th eighth of every job's tiles, as
-        // below; each of its workgroups runs mac_tiles consecutive tiles of
-        // that list (valid ones first), and the workgroups of the eight
-        // lists are interleaved (workgroup 8i+x runs on XCD x)
+        // below.  Its list is cut into mac_tiles segments of W tiles, and its
+        // workgroup i runs tile i of each segment in turn (valid ones
+        // first): the workgroups advance through the segments together, so
+        // the tiles running at one time stay a contiguous stretch of the
+        // list and share their input and weight words in the XCD's L2 (a
+        // workgroup taking consecutive tiles would reuse a weight row only
+        // one tile later, after the L2 has evicted it).  The workgroups of
+        // the eight lists are interleaved (workgroup 8i+x runs on XCD x).
         const uint32_t T = b->mac_tiles;
         std::vector<MacItem> per[heconv::BATCH_XCDS];
         for (uint32_t j = 0; j < n_jobs; j++) {
@@ -231,13 +236,13 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
               per[x].push_back(MacItem{j, kc, mt, rt, bs0 / S, bs0 % S});
             }
         }
-        size_t wgs = 0;
+        size_t wgs = 0;  // W: workgroups per XCD
         for (const auto& v : per) wgs = std::max(wgs, (v.size() + T - 1) / T);
         const uint64_t moff = mitems.size();
         for (size_t w = 0; w < wgs; w++)
           for (const auto& v : per)
             for (uint32_t t = 0; t < T; t++) {
-              const size_t i = w * T + t;
+              const size_t i = w + t * wgs;
               mitems.push_back(i < v.size() ? v[i] : MacItem{heconv::BATCH_NO_JOB, 0, 0, 0, 0, 0});
             }
         // the phase's workgroup count; its tiles start at mitems[moff] (kept in off/cnt below)
