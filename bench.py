@@ -391,7 +391,7 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
     N, L, bits = cfg["N"], cfg["L"], cfg["bits"]
     ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), 2 ** synth.T_BITS)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64).copy()).cuda()
-    jobs, pristine, macs, out_cts = [], [], 0, 0
+    jobs, pristine, macs, out_cts, mac_bytes = [], [], 0, 0, 0
     for i, shape in enumerate(cfg["layers"]):
         C, H, W, M, kh, kw, stride, pad = shape
         K = Stream(cfg["seed"] * 1000 + i, synth.WEIGHT).ints(M * C * kh * kw, *cfg["w_range"])
@@ -407,6 +407,7 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
         wntt = torch.empty(s.w_words, dtype=torch.int64, device="cuda")
         ctx.encode_weights(d, Kd, wntt)
         out_cts += s.out_cts
+        mac_bytes += s.w_words * 8 + (s.in_cts + s.out_cts) * 2 * L * N * 8
         x = synth.uniform_mod(Stream(cfg["seed"] * 1000 + i, synth.UNIFORM), (s.in_cts * 2, L, N), ctx.q)
         pristine.append(dev(x))
         jobs.append((d, 1, pristine[-1].clone(), wntt, torch.empty(s.out_cts * 2 * L * N, dtype=torch.int64,
@@ -431,6 +432,16 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
     t_plain, t_batch = st_plain["mean_ms"], st_batch["mean_ms"]
     n = len(jobs)
     b.close()
+    # per-grid durations of the same jobs as one chain (HIP events around
+    # each grid, eager): the MAC grid's algorithmic bytes over its duration
+    b1 = heconv.Batch(ctx, jobs, schedule=heconv.SCHED_ONE_CHAIN)
+    g1 = [b1.launch_timed(stream)[0] for _ in range(4)][1:]
+    b1.close()
+    fwd_ms, mac_ms, inv_ms = (float(np.mean([r[p] for r in g1])) for p in range(3))
+    one_chain = {"fwd_ms": round(fwd_ms, 4), "mac_ms": round(mac_ms, 4), "inv_ms": round(inv_ms, 4),
+                 "mac_alg_bytes": mac_bytes, "mac_GBps": round(mac_bytes / (mac_ms * 1e-3) / 1e9, 1),
+                 "mac_hbm_frac": round(mac_bytes / (mac_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "note": "the 26 jobs as one chain, eager, HIP events around each grid (mean of 3)"}
     tuned = None
     if tune:
         # the autotuner over schedule x MAC tile x NTT grouping, then the
@@ -447,7 +458,7 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
         t_tuned = st_tuned["mean_ms"]
         bt.close()
         tuned = {"schedule": SCHEDULE_NAMES[tr.schedule],
-                 "tuning": {k: tr.tuning[k] for k in ("mac_mt", "mac_rt", "mac_lds", "ntt_loge_small", "ntt_loge_large")},
+                 "tuning": {k: tr.tuning[k] for k in ("mac_mt", "mac_rt", "mac_lds", "mac_tiles", "mac_grid", "ntt_loge_small", "ntt_loge_large")},
                  "batched_ms": t_tuned, "batched_layers_per_s": n / t_tuned * 1e3,
                  "batched_p50_ms": st_tuned["p50_ms"], "batched_p99_ms": st_tuned["p99_ms"],
                  "candidates_timed": len(tr.evaluations), "bit_exact_vs_plain": bool(same)}
@@ -481,7 +492,7 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
             "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_b * 1e3,
             "plain_ctpt_macs_per_s": macs / t_plain * 1e3, "batched_ctpt_macs_per_s": macs / t_b * 1e3,
             "speedup": t_plain / t_b, "bit_exact_vs_plain": bool(ok), "batched_form": form,
-            "fixed_form": fixed, **({"autotuned": tuned} if tuned is not None else {})}
+            "one_chain_grids": one_chain, "fixed_form": fixed, **({"autotuned": tuned} if tuned is not None else {})}
 
 
 def run_stem_polyphase(torch, heconv):
@@ -702,7 +713,8 @@ def run_bottleneck_main(torch, heconv, args, probes):
                    "layers": len(descs), "layer_solves_per_step": n_solves, "ctpt_macs_per_step": macs,
                    "in_cts_per_step": in_cts, "out_cts_per_step": out_cts, "resident_GiB": round(resident, 1),
                    "path": f"batched: {len(descs)} layer jobs x {B} images, "
-                           f"{SCHEDULE_NAMES[args.schedule]} of three grids, one hipGraph launch"},
+                           f"{SCHEDULE_NAMES[args.schedule]} of three grids, one hipGraph launch",
+                   "mac_form": bt.mac_form},
         "layers_per_s": n_solves / (batched["mean_ms"] * 1e-3),
         "p50_ms": batched["p50_ms"], "p99_ms": batched["p99_ms"],
         "plain": {"path": "plain per-layer: one he_conv_layer call per layer solve (one image)",

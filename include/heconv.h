@@ -111,8 +111,9 @@ void he_ctx_destroy(he_ctx* ctx);
  * default.  A batch takes the context's pair when its MAC is built for it
  * (streamed: (4,4) (6,4) (8,4) (4,8) (4,2) (2,4) (2,2); register loads:
  * (4,4) (4,2) (2,4) (2,2)); else (2,2) when a job has fewer than four rows
- * or output channels, else (6,4) for the streamed MAC when every job has at
- * least six output channels, else (4,4).
+ * or output channels, else (4,4) on the 2x2 wave grid (mac_grid) when every
+ * job has at least 8 rows and output channels, else (6,4) for the streamed
+ * MAC when every job has at least six output channels, else (4,4).
  * layer_fused: 1 = he_conv_layer runs the MAC and the inverse NTT as one
  * kernel (he_conv_mac_intt), 0 = as two (he_conv_ntt_mac, he_ntt_inv).
  * (the fused kernel gives up the MAC's register tiling, so it moves several
@@ -168,7 +169,14 @@ void he_ctx_destroy(he_ctx* ctx);
  * bottleneck CNN's MAC grid from 129.6 to 121.1 ms.
  * mac_tiles: tiles per workgroup of a batch's streamed MAC (0 = 4, at most
  * 64).
- * Defaults: {3, 3, 512, 0, 0, 0, 1, 160, 1, 1, 128, 3, 0}: 8 words per thread was measured faster
+ * mac_grid: 1 (default) = a batch's streamed MAC runs its workgroup's four
+ * waves as a 2x2 grid over one slice of 64 NTT points, sharing the input and
+ * weight rows they load (tiles of 2*mac_mt channels x 2*mac_rt rows, one
+ * workgroup barrier per channel block), when every job has that many rows
+ * and channels; 0 = each wave its own 64 points.  Measured on the 16-image
+ * bottleneck CNN's MAC grid: 98 ms per wave (6x4 tiles), 90 ms on the grid
+ * (4x4 per wave, three stages), 88 ms with four stages.
+ * Defaults: {3, 3, 512, 0, 0, 0, 1, 160, 1, 1, 128, 3, 0, 1}: 8 words per thread was measured faster
  * than 16 at every count at N = 8192 (768 limb polys: 47.7 against 51.4 us
  * inverse); N = 16384 always uses 16.  The channel pipeline (layer_split)
  * was measured slower than the plain order on 64->64, 128->128 and
@@ -186,6 +194,7 @@ typedef struct {
   uint32_t ntt_inv_split_below;
   uint32_t mac_lds;
   uint32_t mac_tiles;
+  uint32_t mac_grid;
 } he_tuning;
 
 he_status he_ctx_get_tuning(const he_ctx* ctx, he_tuning* out);
@@ -603,6 +612,13 @@ he_status he_batch_status(he_batch* b, void* stream);
 
 /* Work items over all grids, and streams used (1 or 2). */
 he_status he_batch_info(const he_batch* b, uint64_t* n_items, uint32_t* n_chains);
+
+/* The MAC form the batch picked (see he_tuning): the register tile
+ * (mt, rt), the LDS stages (0: register loads), the tiles per workgroup of
+ * the streamed MAC and whether its waves form the 2x2 grid.  Any output
+ * pointer may be NULL. */
+he_status he_batch_mac_form(const he_batch* b, uint32_t* mt, uint32_t* rt, uint32_t* lds, uint32_t* tiles,
+                            uint32_t* grid);
 
 void he_batch_destroy(he_batch* b);
 

@@ -68,13 +68,16 @@ def layer_space(N: int) -> list[tuple[str, list[dict]]]:
 
 def batch_space(N: int) -> list[tuple[str, list[dict]]]:
     """Knobs of a batch: the MAC tile ((0, 0) lets the executor pick by
-    shape; (4, 4), (4, 2), (2, 4) and (2, 2) force that tile) and the NTT
-    grouping; the schedule is a separate argument of Batch and is searched
-    by tune_batch."""
+    shape; the others force that tile where the chosen kernel has it), the
+    LDS stages, the streamed MAC's tiles per workgroup and 2x2 wave grid,
+    and the NTT grouping; the schedule is a separate argument of Batch and
+    is searched by tune_batch."""
     loges = (3, 4) if N <= 8192 else (4,)
     return [
-        ("mac", [{"mac_mt": a, "mac_rt": b} for a, b in ((0, 0), (2, 2), (4, 4), (4, 2), (2, 4))]),
+        ("mac", [{"mac_mt": a, "mac_rt": b} for a, b in ((0, 0), (2, 2), (4, 4), (4, 2), (2, 4), (6, 4))]),
         ("mac_lds", [{"mac_lds": v} for v in (0, 2, 3, 4)]),
+        ("mac_grid", [{"mac_grid": v} for v in (0, 1)]),
+        ("mac_tiles", [{"mac_tiles": v} for v in (0, 1, 2, 8)]),
         ("ntt_loge_small", [{"ntt_loge_small": v} for v in loges]),
         ("ntt_loge_large", [{"ntt_loge_large": v} for v in loges]),
     ]

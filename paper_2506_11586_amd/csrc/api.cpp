@@ -337,7 +337,7 @@ he_status he_ctx_set_tuning(he_ctx* c, const he_tuning* t) {
   for (auto& p : tiles) ok |= (p[0] == t->mac_mt && p[1] == t->mac_rt);
   if (!ok || t->layer_fused > 1 || t->ntt_fp64 > 1 || t->ks_fused > 2) return HE_EINVAL;
   if (t->layer_split != 1 && t->layer_split != 2 && t->layer_split != 4) return HE_EINVAL;
-  if (t->mac_lds == 1 || t->mac_lds > 4 || t->mac_tiles > 64) return HE_EINVAL;
+  if (t->mac_lds == 1 || t->mac_lds > 4 || t->mac_tiles > 64 || t->mac_grid > 1) return HE_EINVAL;
   c->tune = *t;
   return HE_OK;
 }

@@ -29,6 +29,9 @@ struct BatchItem {
 // that the kernel divides nothing: k-chunk kc (256 NTT points of limb
 // kc >> (logN - 8)), output channels mt*MT.., rows rt*RT.., and the image b0
 // and spatial tile s0 of its first row pair (row pair rt*RT/2 = b0*S + s0).
+// (With the 2x2 wave grid, kc is a chunk of 64 points, limb kc >> (logN - 6),
+// and the tile covers channels mt*2MT.. and rows rt*2RT.., first row pair
+// rt*RT = b0*S + s0.)
 struct MacItem {
   uint32_t job;  // BATCH_NO_JOB: padding (only after a workgroup's last tile)
   uint32_t kc, mt, rt, b0, s0;
@@ -56,6 +59,7 @@ struct BatchArgs {
   uint32_t mac_mt, mac_rt;          // MAC register tile, see batch_tile_supported
   uint32_t mac_lds;                 // 0, or LDS stages of the streamed MAC (mac_stream)
   uint32_t all_pm;                  // every q_l = 2^60 - delta, delta < 2^20 (the MAC's short fold)
+  uint32_t mac_grid;                // streamed MAC on a 2x2 wave grid (mac_grid): tiles of 2*mac_mt x 2*mac_rt
 };
 
 // Register tiles the batch MAC is built for: with register loads (lds 0)

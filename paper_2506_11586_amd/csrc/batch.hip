@@ -5,6 +5,7 @@
 // boundaries order the steps; no workgroup waits on another.
 #include "batch.h"
 #include "mac_impl.h"
+#include "mac_grid.h"
 #include "mac_stream.h"
 #include "ntt_impl.h"
 
@@ -115,9 +116,28 @@ static hipError_t mac_regs(const BatchPhase& p, const BatchArgs& a, hipStream_t 
   return hipGetLastError();
 }
 
+// Streamed MAC on a 2x2 wave grid: workgroup b runs tiles mitems[b*per_wg ..]
+// (see mac_grid).
+template <int MT, int RT, int P, bool PM>
+__global__ __launch_bounds__(BATCH_MAC_THREADS) void batch_mac_grid_kernel(const MacItem* __restrict__ items,
+                                                                            uint32_t per_wg,
+                                                                            const BatchJob* __restrict__ jobs,
+                                                                            const LimbConst* __restrict__ lcs,
+                                                                            uint32_t L, uint32_t logN) {
+  __shared__ uint64_t lds[P * MacGridShape<MT, RT>::ROWS * 64];
+  const MacListSrc src{items + (uint64_t)blockIdx.x * per_wg, per_wg, jobs};
+  mac_grid<MT, RT, BATCH_MAC_THREADS, P, PM>(src, lcs, L, logN, lds, threadIdx.x);
+}
+
 template <int MT, int RT, int P>
 static void mac_streamed_p(const BatchPhase& p, const BatchArgs& a, hipStream_t st) {
-  if (a.all_pm)
+  if (a.mac_grid && a.all_pm)
+    hipLaunchKernelGGL((batch_mac_grid_kernel<MT, RT, P, true>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.mitems,
+                       p.per_wg, a.jobs, a.lcs, a.L, a.logN);
+  else if (a.mac_grid)
+    hipLaunchKernelGGL((batch_mac_grid_kernel<MT, RT, P, false>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st,
+                       p.mitems, p.per_wg, a.jobs, a.lcs, a.L, a.logN);
+  else if (a.all_pm)
     hipLaunchKernelGGL((batch_mac_stream_kernel<MT, RT, P, true>), dim3(p.n), dim3(BATCH_MAC_THREADS), 0, st, p.mitems,
                        p.per_wg, a.jobs, a.lcs, a.L, a.logN);
   else
@@ -149,6 +169,7 @@ static hipError_t mac_phase(const BatchPhase& p, const BatchArgs& a, hipStream_t
     return hipErrorInvalidValue;
   }
   if (mt == 4 && rt == 4) return mac_streamed<4, 4>(p, a, st);
+  if (a.mac_grid && (mt == 8 || rt == 8)) return hipErrorInvalidValue;
   if (mt == 8 && rt == 4) return mac_streamed<8, 4>(p, a, st);
   if (mt == 6 && rt == 4) return mac_streamed<6, 4>(p, a, st);
   if (mt == 4 && rt == 8) return mac_streamed<4, 8>(p, a, st);

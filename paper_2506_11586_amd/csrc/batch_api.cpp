@@ -31,6 +31,7 @@ struct he_batch {
   uint32_t mac_mt = 4, mac_rt = 4;
   uint32_t mac_lds = 0;
   uint32_t mac_tiles = 1;  // streamed MAC: tiles per workgroup
+  uint32_t mac_grid = 0;   // streamed MAC on a 2x2 wave grid
   uint64_t n_items = 0;
   BatchJob* d_jobs = nullptr;
   BatchItem* d_items = nullptr;
@@ -65,7 +66,7 @@ heconv::BatchArgs args_of(const he_batch* b) {
   const he_ctx* c = b->ctx;
   return heconv::BatchArgs{b->d_jobs, c->d_fwd, c->d_inv, c->d_lc, c->L, c->N, c->logN,
                            c->tune.ntt_loge_small, c->tune.ntt_loge_large, b->mac_mt, b->mac_rt, b->mac_lds,
-                           c->all_pm ? 1u : 0u};
+                           c->all_pm ? 1u : 0u, b->mac_grid};
 }
 
 bool pipelined(const he_batch* b) { return b->schedule == HE_SCHED_PIPELINED_4 || b->schedule == HE_SCHED_PIPELINED_8; }
@@ -149,6 +150,20 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
   } else {
     b->mac_mt = b->mac_lds >= 2 && !narrow ? 6 : 4, b->mac_rt = 4;
   }
+  // the 2x2 wave grid when asked for and every job fills the waves' rows
+  // and channels (2*mac_rt rows, 2*mac_mt channels); by default with the
+  // 4x4 tile per wave (an 8x8 workgroup tile)
+  auto fills = [&](uint32_t mt, uint32_t rt) {
+    bool f = true;
+    for (uint32_t j = 0; j < n_jobs; j++)
+      f &= (uint64_t)jobs[j].B * geo[j].S * 2 >= 2 * rt && jobs[j].desc.M >= 2 * mt;
+    return f;
+  };
+  if (b->mac_lds >= 2 && c->tune.mac_grid) {
+    if (!heconv::batch_tile_supported(c->tune.mac_mt, c->tune.mac_rt, b->mac_lds) && !small && fills(4, 4))
+      b->mac_mt = b->mac_rt = 4;
+    b->mac_grid = b->mac_mt != 8 && b->mac_rt != 8 && fills(b->mac_mt, b->mac_rt) ? 1 : 0;
+  }
 
   const uint64_t n_kc = (uint64_t)c->L * c->N / heconv::BATCH_MAC_THREADS;
   std::vector<BatchJob> dj(n_jobs);
@@ -157,9 +172,13 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
     const he_job& jb = jobs[j];
     const heconv::Geo& g = geo[j];
     const uint64_t rows = (uint64_t)jb.B * g.S * 2;
-    const uint64_t n_mt = (jb.desc.M + b->mac_mt - 1) / b->mac_mt, n_rt = (rows + b->mac_rt - 1) / b->mac_rt;
+    // MAC tiles: the 2x2 wave grid's cover 2*mac_mt channels x 2*mac_rt rows
+    // of 64 points, the others mac_mt x mac_rt of 256
+    const uint32_t gm = b->mac_grid ? 2 : 1;
+    const uint64_t n_mt = (jb.desc.M + gm * b->mac_mt - 1) / (gm * b->mac_mt),
+                   n_rt = (rows + gm * b->mac_rt - 1) / (gm * b->mac_rt);
     n_fwd[j] = (uint64_t)jb.B * g.CB * g.S * 2 * c->L;
-    n_mac[j] = n_kc * n_mt * n_rt;
+    n_mac[j] = (b->mac_grid ? n_kc * 4 : n_kc) * n_mt * n_rt;
     n_inv[j] = (uint64_t)jb.B * jb.desc.M * g.S * 2 * c->L;
     wbytes[j] = (uint64_t)jb.desc.M * g.CB * c->L * c->N * 8;
     if (rows > 0xffffffffull || n_fwd[j] > 0x7fffffffull || n_mac[j] > 0x7fffffffull || n_inv[j] > 0x7fffffffull) {
@@ -232,7 +251,7 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
           for (uint32_t x = 0; x < heconv::BATCH_XCDS; x++)
             for (uint64_t i = n * x / heconv::BATCH_XCDS; i < n * (x + 1) / heconv::BATCH_XCDS; i++) {
               const uint32_t kc = (uint32_t)(i / per_chunk), rem = (uint32_t)(i % per_chunk);
-              const uint32_t mt = rem / n_rt, rt = rem % n_rt, bs0 = rt * b->mac_rt / 2;
+              const uint32_t mt = rem / n_rt, rt = rem % n_rt, bs0 = rt * b->mac_rt * (b->mac_grid ? 2 : 1) / 2;
               per[x].push_back(MacItem{j, kc, mt, rt, bs0 / S, bs0 % S});
             }
         }
@@ -424,6 +443,17 @@ he_status he_batch_info(const he_batch* b, uint64_t* n_items, uint32_t* n_chains
   if (!b) return HE_EINVAL;
   if (n_items) *n_items = b->n_items;
   if (n_chains) *n_chains = pipelined(b) ? 2 : b->n_chains;
+  return HE_OK;
+}
+
+he_status he_batch_mac_form(const he_batch* b, uint32_t* mt, uint32_t* rt, uint32_t* lds, uint32_t* tiles,
+                            uint32_t* grid) {
+  if (!b) return HE_EINVAL;
+  if (mt) *mt = b->mac_mt;
+  if (rt) *rt = b->mac_rt;
+  if (lds) *lds = b->mac_lds;
+  if (tiles) *tiles = b->mac_lds >= 2 ? b->mac_tiles : 1;
+  if (grid) *grid = b->mac_grid;
   return HE_OK;
 }
 

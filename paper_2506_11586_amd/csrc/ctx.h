@@ -29,7 +29,7 @@ struct he_ctx {
   void* d_fc = nullptr;       // per-limb F64Const
   bool decode_ok = false;
   heconv::LimbConst tlc{};  // reduction constants of t (decryption)
-  he_tuning tune{3, 3, 512, 0, 0, 0, 1, 160, 1, 1, 128, 3, 0};
+  he_tuning tune{3, 3, 512, 0, 0, 0, 1, 160, 1, 1, 128, 3, 0, 1};
   // internal stream and events of the output-channel pipeline of he_conv_layer
   hipStream_t aux = nullptr;
   hipEvent_t ev_mac[4] = {nullptr, nullptr, nullptr, nullptr};

@@ -30,7 +30,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in ("ntt_loge_small", "ntt_loge_large", "ntt_small_below",
                                                "mac_mt", "mac_rt", "layer_fused", "layer_split",
                                                "ntt_split_below", "ntt_fp64", "ks_fused",
-                                               "ntt_inv_split_below", "mac_lds", "mac_tiles")]
+                                               "ntt_inv_split_below", "mac_lds", "mac_tiles", "mac_grid")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -127,9 +127,11 @@ def _lib_handle():
         L.he_batch_launch_timed.argtypes = [vp, vp, P(ctypes.c_float)]
         L.he_batch_status.argtypes = [vp, vp]
         L.he_batch_info.argtypes = [vp, P(u64), P(u32)]
+        L.he_batch_mac_form.argtypes = [vp, P(u32), P(u32), P(u32), P(u32), P(u32)]
         L.he_batch_destroy.argtypes = [vp]
         L.he_batch_destroy.restype = None
-        for name in ("he_batch_create", "he_batch_launch", "he_batch_launch_timed", "he_batch_status", "he_batch_info"):
+        for name in ("he_batch_create", "he_batch_launch", "he_batch_launch_timed", "he_batch_status", "he_batch_info",
+                     "he_batch_mac_form"):
             getattr(L, name).restype = i32
         for name in ("he_gen_primes", "he_ctx_create", "he_ctx_psi", "he_ctx_get_tuning", "he_ctx_set_tuning", "he_plan_conv", "he_plan_conv_host", "he_min_root", "he_conv_sizes",
                      "he_encode_weights", "he_ntt_fwd", "he_ntt_inv", "he_conv_ntt_mac", "he_conv_layer",
@@ -566,6 +568,11 @@ class Batch:
         n, c = ctypes.c_uint64(), ctypes.c_uint32()
         _check(lib().he_batch_info(self._h, ctypes.byref(n), ctypes.byref(c)), "he_batch_info")
         self.n_items, self.n_chains = n.value, c.value
+        f = [ctypes.c_uint32() for _ in range(5)]
+        _check(lib().he_batch_mac_form(self._h, *[ctypes.byref(v) for v in f]), "he_batch_mac_form")
+        # the MAC form the batch picked: register tile, LDS stages, tiles per
+        # workgroup of the streamed MAC, 2x2 wave grid
+        self.mac_form = dict(zip(("mt", "rt", "lds", "tiles", "grid"), (v.value for v in f)))
 
     def launch(self, stream=None, graph: bool = True):
         _check(lib().he_batch_launch(self._h, _stream(stream), int(bool(graph))), "he_batch_launch")

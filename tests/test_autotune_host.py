@@ -59,7 +59,7 @@ def test_min_gain_keeps_the_start_on_small_differences():
 def test_spaces_hold_only_supported_values():
     """MAC tiles are the library's supported pairs or (0, 0) (by shape); 8
     words per thread is offered only where N/8 threads fit a workgroup."""
-    supported = {(4, 4), (4, 2), (2, 4), (8, 2), (2, 8), (8, 1), (1, 8), (2, 2), (0, 0)}
+    supported = {(4, 4), (4, 2), (2, 4), (8, 2), (2, 8), (8, 1), (1, 8), (2, 2), (0, 0), (6, 4)}
     for N in (4096, 8192, 16384):
         for space in (autotune.layer_space(N), autotune.batch_space(N)):
             for name, values in space:
@@ -72,6 +72,8 @@ def test_spaces_hold_only_supported_values():
     names = [n for n, _ in autotune.layer_space(8192)]
     assert names == ["ntt_loge_small", "ntt_loge_large", "mac", "mac_lds", "layer_split", "ntt_split_below",
                      "ntt_inv_split_below", "layer_fused", "ntt_fp64"]
+    assert [n for n, _ in autotune.batch_space(8192)] == ["mac", "mac_lds", "mac_grid", "mac_tiles",
+                                                         "ntt_loge_small", "ntt_loge_large"]
 
 
 class _Desc:

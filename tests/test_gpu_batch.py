@@ -268,3 +268,67 @@ def test_streamed_mac_chunks_and_tile_lists(ctx4096, deep_jobs, tile, lds, tiles
     for j, w in zip(jobs, want):
         assert np.array_equal(to_host(j[4]), w), (tile, lds, tiles, j[0])
     b.close()
+
+
+# Jobs that fill a 2x2 wave grid of the streamed MAC (at least 8 rows and
+# 12 output channels each): one to three chunks of channel blocks, ragged
+# rows and channels, several spatial tiles; N=4096, L=2.
+SHAPES_GRID = [
+    ((64, 12, 12, 16, 3, 3, 1, 1), 4),
+    ((600, 5, 5, 13, 1, 1, 1, 0), 5),
+    ((4000, 4, 4, 12, 1, 1, 1, 0), 4),
+    ((6000, 4, 4, 14, 1, 1, 1, 0), 4),
+    ((8, 64, 64, 12, 3, 3, 1, 1), 3),
+    ((3, 60, 60, 16, 7, 7, 2, 3), 5),
+]
+
+
+@pytest.fixture(scope="module")
+def grid_jobs(ctx4096):
+    ctx, prm = ctx4096
+    jobs, host = make_jobs(ctx, prm, SHAPES_GRID, 700)
+    pristine = [j[2].clone() for j in jobs]
+    want = []
+    for (d, B, d_in, wntt, d_out), (cv, _, _, x, K) in zip(jobs, host):
+        g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+        w_ntt = oracle.encode_weights(K, cv, g, prm)
+        want.append(oracle.conv_layer_ntt(x.reshape(B, g.CB, g.S, 2, prm.L, prm.N), w_ntt, B, g, cv.M, prm).reshape(-1))
+    return jobs, pristine, want
+
+
+@pytest.mark.parametrize("tile,lds,tiles", [
+    ((6, 4), 3, 0), ((6, 4), 2, 3), ((6, 4), 4, 1), ((4, 4), 3, 0), ((4, 4), 2, 5), ((4, 2), 3, 2),
+    ((2, 4), 4, 0), ((2, 2), 3, 1)])
+def test_streamed_mac_wave_grid(ctx4096, grid_jobs, tile, lds, tiles):
+    """The streamed MAC with its four waves as a 2x2 grid sharing the rows
+    they load (one workgroup barrier per channel block): the batch picks the
+    grid for these jobs, and every output word equals the oracle's."""
+    from paper_2506_11586_amd import heconv
+    ctx, prm = ctx4096
+    jobs, pristine, want = grid_jobs
+    before = ctx.get_tuning().as_dict()
+    ctx.set_tuning(mac_mt=tile[0], mac_rt=tile[1], mac_lds=lds, mac_tiles=tiles, mac_grid=1)
+    b = heconv.Batch(ctx, jobs, schedule=1)
+    ctx.set_tuning(**before)
+    assert b.mac_form["grid"] == 1 and (b.mac_form["mt"], b.mac_form["rt"]) == tile, b.mac_form
+    for j, p in zip(jobs, pristine):
+        j[2].copy_(p)
+        j[4].fill_(-1)
+    b.launch(graph=True)
+    b.status()
+    for j, w in zip(jobs, want):
+        assert np.array_equal(to_host(j[4]), w), (tile, lds, tiles, j[0])
+    b.close()
+
+
+def test_wave_grid_falls_back_when_jobs_do_not_fill_it(ctx4096):
+    """A job with fewer rows than the grid covers keeps the per-wave stream."""
+    from paper_2506_11586_amd import heconv
+    ctx, prm = ctx4096
+    jobs, host = make_jobs(ctx, prm, [((8, 11, 9, 16, 3, 3, 2, 1), 1)], 800)  # 2 rows
+    before = ctx.get_tuning().as_dict()
+    ctx.set_tuning(mac_mt=4, mac_rt=4, mac_lds=3, mac_grid=1)
+    b = heconv.Batch(ctx, jobs, schedule=1)
+    ctx.set_tuning(**before)
+    assert b.mac_form["grid"] == 0
+    b.close()
