@@ -57,6 +57,9 @@ PAPER_CONTEXT = {
 VALU_PEAK_GIPS = 256 * 2.4  # G full-rate wave64 VALU instructions/s: one per CU per cycle, 256 CUs at 2.4 GHz
 VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9  # full-rate 32-bit lane operations/s: 256 CUs x 64 lanes x 2.4 GHz
 MAD_RATE_FRAC = 1.0  # v_mad_u64_u32 issues at the full rate on gfx950 (the probe's mad_u64_u32 field: 0.975)
+# VALU instructions of one butterfly in the compiled transforms (the
+# probes' butterfly loops: 672 per 32 inverse, 768 per 32 forward)
+BFLY_VALU_INSTS = {"batch_inv": 21, "batch_fwd": 24}
 SCHEDULE_NAMES = {1: "one chain", 2: "two chains", 3: "pipelined in 4 groups", 4: "pipelined in 8 groups"}
 # layer solves (image 0) the oracle recomputes in the CPU-baseline leg
 ORACLE_SAMPLE_LAYERS = [0, 2, 3, 12, 14, 16, 25, 26, 29, 44, 45, 48]
@@ -215,7 +218,7 @@ def run_single_layer(torch, heconv, args):
     # The flush only reads, so it leaves no dirty lines to write back.
     flush = torch.ones(64 << 20, dtype=torch.int64, device="cuda")
     cold = []
-    for _ in range(10):
+    for _ in range(30):
         flush.sum()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
@@ -223,7 +226,8 @@ def run_single_layer(torch, heconv, args):
         b.record(stream)
         cold.append((a, b))
     torch.cuda.synchronize()
-    mac_cold_us = float(np.mean([p.elapsed_time(q) for p, q in cold])) * 1e3
+    cold_us = np.array([p.elapsed_time(q) for p, q in cold]) * 1e3
+    mac_cold_us, mac_cold_p50 = float(np.mean(cold_us)), float(np.median(cold_us))
     del flush
 
     limb_polys_in, limb_polys_out = n_in * 2 * L, n_out * 2 * L
@@ -247,9 +251,9 @@ def run_single_layer(torch, heconv, args):
     # integer-VALU side: wave64 VALU instructions per launch from the SQ
     # counters of the committed profile, over this run's live average
     # duration, against one full-rate wave64 VALU instruction per CU per
-    # cycle (256 CUs x 2.4 GHz).  The 32-bit multiplies issue at half rate,
-    # so this counts each instruction once and is a lower bound on how busy
-    # the VALU is.
+    # cycle (256 CUs x 2.4 GHz).  The clock under a long integer load runs
+    # below 2.4 GHz, so the VALU's busy fraction of the cycles actually run
+    # is higher than this.
     for k in ks:
         rec = load_counters(k, wl_name)
         if rec and rec.get("valu_insts_per_launch"):
@@ -263,8 +267,8 @@ def run_single_layer(torch, heconv, args):
         v = kernels[valu_k]["valu"]
         roofline_valu = {"bound": "alu", "kernel": valu_k, "achieved": v["achieved"], "peak": VALU_PEAK_GIPS,
                          "unit": v["unit"], "frac": v["issue_frac"],
-                         "note": "each VALU instruction counted once; half-rate 32-bit multiplies make the "
-                                 "busy fraction higher"}
+                         "note": "each VALU instruction counted once, against 2.4 GHz; the clock under "
+                                 "sustained integer load is lower, so the busy fraction is higher"}
 
     # the autotuner on the same layer, after the timed region: it starts from
     # the context's defaults (which time the headline above) and reports its
@@ -297,10 +301,13 @@ def run_single_layer(torch, heconv, args):
         "wall_s": wall,
         "offline_encode_ms": encode_ms,
         "kernels": kernels,
-        "mac_cold_cache": {"avg_us": round(mac_cold_us, 3),
+        "mac_cold_cache": {"avg_us": round(mac_cold_us, 3), "p50_us": round(mac_cold_p50, 3),
+                           "min_us": round(float(cold_us.min()), 3), "max_us": round(float(cold_us.max()), 3),
                            "GBps": round(kbytes["mac"] / (mac_cold_us * 1e-6) / 1e9, 1),
                            "frac": round(kbytes["mac"] / (mac_cold_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-                           "note": "512 MiB read between launches (Infinity Cache 256 MB)"},
+                           "p50_GBps": round(kbytes["mac"] / (mac_cold_p50 * 1e-6) / 1e9, 1),
+                           "note": "30 launches, 512 MiB read before each (Infinity Cache 256 MB); "
+                                   "GBps and frac from the mean"},
         "roofline": roofline,
     }
     if roofline_valu is not None:
@@ -670,7 +677,9 @@ def run_bottleneck_main(torch, heconv, args, probes):
         t = kavg[k]["ms_per_pass"] * 1e-3
         kavg[k]["alg"] = alg[k]
         kavg[k]["GBps"] = round(alg[k]["bytes"] / t / 1e9, 1)
-    dom = max(kavg, key=lambda k: kavg[k]["ms_per_pass"])
+    form = bt.mac_form
+    mac_kernel = ("batch_mac_grid_kernel (streamed MAC, 2x2 wave grid)" if form["grid"] else
+                  "batch_mac_stream_kernel (streamed MAC)" if form["lds"] >= 2 else "batch_mac_kernel")
     # the MAC at 16 images is bound by integer multiply-adds: each modmul-add
     # is four v_mad_u64_u32 of 30-bit halves, so the ceiling is the chip's
     # v_mad_u64_u32 rate / 4 (256 CUs x 64 lanes x 2.4 GHz; the probe
@@ -678,28 +687,41 @@ def run_bottleneck_main(torch, heconv, args, probes):
     mac_t = kavg["batch_mac"]["ms_per_pass"] * 1e-3
     achieved = alg["batch_mac"]["modmul_adds"] / mac_t / 1e9
     peak = VALU_LANE_OPS_PEAK * MAD_RATE_FRAC / 4 / 1e9
-    traffic = load_traffic("batch_mac", cfg["name"])
-    roofline = {"bound": "alu", "kernel": "batch_mac_stream_kernel (the batch's streamed MAC grid)", "achieved": round(achieved, 1),
-                "peak": round(peak, 1), "unit": "G modmul-adds/s", "frac": round(achieved / peak, 4),
-                "traffic": traffic,
-                "peak_derivation": "256 CUs x 64 lanes x 2.4 GHz (v_mad_u64_u32 issues at the full rate) / 4 "
-                                   "multiply-adds per modmul-add",
-                "avg_launch_ms": round(kavg["batch_mac"]["avg_ms_per_launch"], 4)}
+    roofline_mac = {"bound": "alu", "kernel": mac_kernel, "achieved": round(achieved, 1),
+                    "peak": round(peak, 1), "unit": "G modmul-adds/s", "frac": round(achieved / peak, 4),
+                    "traffic": load_traffic("batch_mac", cfg["name"]),
+                    "peak_derivation": "256 CUs x 64 lanes x 2.4 GHz (v_mad_u64_u32 issues at the full rate) / 4 "
+                                       "multiply-adds per modmul-add",
+                    "avg_launch_ms": round(kavg["batch_mac"]["avg_ms_per_launch"], 4)}
     if probes:
         mix = probes["mac_mix"]["rate"] / 1e9
-        roofline["measured_mix_ceiling"] = {"rate": round(mix, 1), "frac": round(achieved / mix, 4),
-                                            "note": "the streamed MAC's own step and carry on registers (6x4 tile, 8-block chunks)"}
-    roofline_hbm = {"bound": "hbm", "kernel": "batch_mac_stream_kernel", "achieved": kavg["batch_mac"]["GBps"],
+        roofline_mac["measured_mix_ceiling"] = {
+            "rate": round(mix, 1), "frac": round(achieved / mix, 4),
+            "note": "the streamed MAC's channel-block step and carry on registers (6x4 tile, 8-block chunks)"}
+    roofline_hbm = {"bound": "hbm", "kernel": mac_kernel, "achieved": kavg["batch_mac"]["GBps"],
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kavg["batch_mac"]["GBps"] / HBM_PEAK_GBS, 4)}
-    inv_t = kavg["batch_inv"]["ms_per_pass"] * 1e-3
-    bfly = alg["batch_inv"]["modmuls"] / inv_t / 1e9
-    roofline_valu = None
-    if probes:
-        ceil = probes["intt_mix"]["rate"] / 1e9
-        roofline_valu = {"bound": "alu", "kernel": "batch_inv_kernel (inverse NTTs)", "achieved": round(bfly, 1),
-                         "peak": round(ceil, 1), "unit": "G butterflies/s", "frac": round(bfly / ceil, 4),
-                         "peak_kind": "measured ceiling of the inverse butterfly's own instruction mix "
-                                      "(he_probe_valu, registers only)"}
+    # the transforms are bound by integer VALU issue: the peak is the chip's
+    # full-rate lane operations over the VALU instructions of one butterfly
+    # as compiled (inverse 21, forward 24)
+    ntt_roof = {}
+    for k, kname, mix_key in (("batch_inv", "batch_inv_kernel (inverse NTTs)", "intt_mix"),
+                              ("batch_fwd", "batch_fwd_kernel (forward NTTs)", "ntt_mix")):
+        t = kavg[k]["ms_per_pass"] * 1e-3
+        bfly = alg[k]["modmuls"] / t / 1e9
+        peak_b = VALU_LANE_OPS_PEAK / BFLY_VALU_INSTS[k] / 1e9
+        r = {"bound": "alu", "kernel": kname, "achieved": round(bfly, 1), "peak": round(peak_b, 1),
+             "unit": "G butterflies/s", "frac": round(bfly / peak_b, 4), "traffic": load_traffic(k, cfg["name"]),
+             "peak_derivation": f"256 CUs x 64 lanes x 2.4 GHz / {BFLY_VALU_INSTS[k]} VALU instructions per "
+                                "butterfly (compiled)",
+             "avg_launch_ms": round(kavg[k]["avg_ms_per_launch"], 4)}
+        if probes:
+            ceil = probes[mix_key]["rate"] / 1e9
+            r["measured_mix_ceiling"] = {"rate": round(ceil, 1), "frac": round(bfly / ceil, 4),
+                                         "note": "the butterfly's own instruction mix on registers (he_probe_valu)"}
+        ntt_roof[k] = r
+    # the headline roofline is the dominant grid's: the longest of the three
+    dom = max(kavg, key=lambda k: kavg[k]["ms_per_pass"])
+    roofline = roofline_mac if dom == "batch_mac" else ntt_roof[dom]
     resident = sum(t.numel() * 8 for t in wntts + ins + outs) / 2 ** 30
     res = {
         "metric": METRIC,
@@ -730,11 +752,12 @@ def run_bottleneck_main(torch, heconv, args, probes):
         "layers_compared_all_words": equal_layers,
         "kernels": kavg,
         "roofline": roofline,
+        "roofline_mac": roofline_mac,
         "roofline_hbm": roofline_hbm,
+        "roofline_ntt_inv": ntt_roof["batch_inv"],
+        "roofline_ntt_fwd": ntt_roof["batch_fwd"],
         "offline_encode_ms": t_enc * 1e3,
     }
-    if roofline_valu:
-        res["roofline_valu"] = roofline_valu
     pending = {"q": list(ctx.q), "samples": {j: (samples[j], sample_out[j], Ks[j], (descs[j].Cw, descs[j].Hw,
                                                                                       descs[j].Ww))
                                              for j in sample_layers}}

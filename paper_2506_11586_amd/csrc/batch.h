@@ -63,7 +63,7 @@ struct BatchArgs {
 };
 
 // Register tiles the batch MAC is built for: with register loads (lds 0)
-// (4,4), (4,2), (2,4), (2,2); streamed (lds 2-4) also (8,4) and (4,8).
+// (4,4), (4,2), (2,4), (2,2); streamed (lds 2-4) also (6,4), (8,4) and (4,8).
 bool batch_tile_supported(uint32_t mt, uint32_t rt, uint32_t lds);
 
 // Forward-NTT grid, MAC grid, inverse-NTT grid of one chain, on stream st.

@@ -181,7 +181,7 @@ static hipError_t mac_phase(const BatchPhase& p, const BatchArgs& a, hipStream_t
 
 bool batch_tile_supported(uint32_t mt, uint32_t rt, uint32_t lds) {
   const bool base = (mt == 4 && rt == 4) || (mt == 4 && rt == 2) || (mt == 2 && rt == 4) || (mt == 2 && rt == 2);
-  return base || (lds >= 2 && ((mt == 8 && rt == 4) || (mt == 4 && rt == 8)));
+  return base || (lds >= 2 && ((mt == 6 && rt == 4) || (mt == 8 && rt == 4) || (mt == 4 && rt == 8)));
 }
 
 hipError_t batch_phase(const BatchChain& ch, const BatchArgs& a, int phase, hipStream_t st) {
