@@ -58,8 +58,8 @@ VALU_PEAK_GIPS = 256 * 2.4  # G full-rate wave64 VALU instructions/s: one per CU
 VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9  # full-rate 32-bit lane operations/s: 256 CUs x 64 lanes x 2.4 GHz
 MAD_RATE_FRAC = 1.0  # v_mad_u64_u32 issues at the full rate on gfx950 (the probe's mad_u64_u32 field: 0.975)
 # VALU instructions of one butterfly in the compiled transforms (the
-# probes' butterfly loops: 672 per 32 inverse, 768 per 32 forward)
-BFLY_VALU_INSTS = {"batch_inv": 21, "batch_fwd": 24}
+# probes' butterfly loops: 672 VALU instructions per 32 butterflies, both)
+BFLY_VALU_INSTS = {"batch_inv": 21, "batch_fwd": 21}
 SCHEDULE_NAMES = {1: "one chain", 2: "two chains", 3: "pipelined in 4 groups", 4: "pipelined in 8 groups"}
 # layer solves (image 0) the oracle recomputes in the CPU-baseline leg
 ORACLE_SAMPLE_LAYERS = [0, 2, 3, 12, 14, 16, 25, 26, 29, 44, 45, 48]
@@ -702,7 +702,7 @@ def run_bottleneck_main(torch, heconv, args, probes):
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kavg["batch_mac"]["GBps"] / HBM_PEAK_GBS, 4)}
     # the transforms are bound by integer VALU issue: the peak is the chip's
     # full-rate lane operations over the VALU instructions of one butterfly
-    # as compiled (inverse 21, forward 24)
+    # as compiled (21 in either direction)
     ntt_roof = {}
     for k, kname, mix_key in (("batch_inv", "batch_inv_kernel (inverse NTTs)", "intt_mix"),
                               ("batch_fwd", "batch_fwd_kernel (forward NTTs)", "ntt_mix")):

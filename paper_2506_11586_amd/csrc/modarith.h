@@ -99,6 +99,13 @@ __host__ __device__ __forceinline__ uint64_t csub_neg(uint64_t x, uint64_t negm)
   return (int64_t)d < 0 ? x : d;
 }
 
+// x < 6q brought to [0, q) by three conditional subtractions (3q, 2q, q);
+// neg3q = 2^64 - 3q, and so on.
+__host__ __device__ __forceinline__ uint64_t canon_below6q(uint64_t x, uint64_t neg3q, uint64_t neg2q,
+                                                           uint64_t negq) {
+  return csub_neg(csub_neg(csub_neg(x, neg3q), neg2q), negq);
+}
+
 // x < 2^64 reduced into [0, 2q) (Shoup with w = 1).
 __device__ __forceinline__ uint64_t reduce64_lazy(uint64_t x, uint64_t mu64, uint64_t q) {
   return x - __umul64hi(x, mu64) * q;

@@ -6,13 +6,14 @@
 // butterfly on bit b pairs j and j + 2^b with twiddle psi^brv(2^(n-1-b) +
 // (j >> (b+1))), n = log2 N; stages run from bit n-1 down to bit 0.  The
 // inverse (Gentleman-Sande) uses the same index with psi^-1 and runs from
-// bit 0 up; its last stage also applies N^-1.  Lazy reduction after Harvey:
-// forward values stay in [0, 4q) (every twiddle product has an input below
-// 4q < 2^62, as the scale-2^63 Shoup product mul_shoup63 requires), inverse
-// values in [0, 3q): the sum is brought below 3q by one conditional
-// subtraction, the difference X - Y + 3q (below 6q) goes through
-// mul_shoup_2q, whose result stays below 2.75q.  Every stored word is
-// canonical.
+// bit 0 up; its last stage also applies N^-1.  Lazy reduction after Harvey,
+// with the twiddle products by mul_shoup_2q (inputs below 6q, results below
+// 2.75q): forward values stay in [0, 6q) (X = x0 brought below 3q by one
+// conditional subtraction, T = mul_shoup_2q(x1), outputs X + T < 5.75q and
+// X - T + 3q < 6q), inverse values in [0, 3q) (the sum brought below 3q by
+// one conditional subtraction, the difference X - Y + 3q, below 6q, through
+// mul_shoup_2q).  Every stored word is canonical (fwd_canon, or the last
+// inverse stage).
 //
 // Thread/element mapping of a pass over bits [lo, lo+LOGE): register k of
 // thread t holds element j = (t mod 2^lo) | k << lo | (t >> lo) << (lo+LOGE).
@@ -37,6 +38,11 @@ __device__ __forceinline__ int elem_index(int tid, int k) {
   return low | (k << LO) | (high << (LO + LOGE));
 }
 
+// A forward value (below 6q) brought to [0, q).
+__device__ __forceinline__ uint64_t fwd_canon(uint64_t x, const LimbConst& c) {
+  return canon_below6q(x, c.neg3q, c.neg2q, c.negq);
+}
+
 // Forward stages u in [U0, LOGE) of the pass at bit offset LO.  jb: index
 // of the workgroup's first element when it transforms a block of a longer
 // polynomial (the stages on bits below the block size only; jb a multiple of
@@ -45,7 +51,7 @@ template <int LOGN, int LOGE, int LO, int U0>
 __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LOGE], int tid, const Tw* __restrict__ tw,
                                          const LimbConst& c, uint32_t jb = 0) {
   const int high = tid >> LO;
-  const uint64_t q2 = c.two_q;
+  const uint64_t q3 = c.three_q;
 #pragma unroll
   for (int u = U0; u < LOGE; u++) {
     const int s = LOGN - LOGE - LO + u;  // stage index: butterflies on bit LO+LOGE-1-u
@@ -56,10 +62,10 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LOGE], int tid, cons
 #pragma unroll
       for (int e = 0; e < half; e++) {
         const int k0 = g * 2 * half + e, k1 = k0 + half;
-        uint64_t X = csub_neg(x[k0], c.neg2q);
-        uint64_t T = mul_shoup63(x[k1], t.w, t.wsh, c.negq);
+        const uint64_t X = csub_neg(x[k0], c.neg3q);
+        const uint64_t T = mul_shoup_2q(x[k1], t.w, t.wsh, c.neg2q);
         x[k0] = X + T;
-        x[k1] = X - T + q2;
+        x[k1] = X - T + q3;
       }
     }
   }
@@ -178,7 +184,7 @@ __device__ __forceinline__ void ntt_fwd_poly(gword* __restrict__ a, const Tw* __
   for (int k = 0; k < E; k++) x[k] = a[tid + k * T];
   fwd_rest<LOGN, LOGE, 0>(x, lds, tid, tw, c);
 #pragma unroll
-  for (int k = 0; k < E; k++) x[k] = csub_neg(csub_neg(x[k], c.neg2q), c.negq);
+  for (int k = 0; k < E; k++) x[k] = fwd_canon(x[k], c);
   exchange<LOGE, 0, TOP>(lds, x, tid);  // back to j = tid + k*T for a coalesced store
 #pragma unroll
   for (int k = 0; k < E; k++) a[tid + k * T] = x[k];

@@ -99,7 +99,7 @@ __global__ __launch_bounds__(SPLIT_T) void ntt_fwd_split_b(uint64_t* __restrict_
   for (int k = 0; k < 8; k++) x[k] = a[elem_index<3, LO0>(tid, k)];
   split_b_rest<LOGN, 0>(x, lds, tid, tw, c, jb);
 #pragma unroll
-  for (int k = 0; k < 8; k++) x[k] = csub_neg(csub_neg(x[k], c.neg2q), c.negq);
+  for (int k = 0; k < 8; k++) x[k] = fwd_canon(x[k], c);
   exchange<3, 0, 7>(lds, x, tid);  // to local index tid + 128k for a coalesced store
 #pragma unroll
   for (int k = 0; k < 8; k++) a[tid + 128 * k] = x[k];

@@ -177,7 +177,6 @@ __global__ __launch_bounds__(PROBE_THREADS) void probe_bfly_kernel(const uint64_
   for (int i = 0; i < 16; i++) x[i] = (seed[(threadIdx.x + i) & 63] + t) % c.q;
   // a twiddle with its scale-2^63 Shoup quotient: 2^64 mod q from the constants
   const uint64_t w = c.r64, wsh = c.r64_sh63;
-  const uint64_t q2 = c.two_q;
   for (uint32_t it = 0; it < iters; it++) {
 #pragma unroll
     for (int u = 0; u < PROBE_UNROLL / 4; u++)
@@ -189,10 +188,10 @@ __global__ __launch_bounds__(PROBE_THREADS) void probe_bfly_kernel(const uint64_
           x[k0] = csub_neg(X + Y, c.neg3q);
           x[k1] = mul_shoup_2q(X - Y + c.three_q, w, wsh, c.neg2q);
         } else {
-          const uint64_t X = csub_neg(x[k0], c.neg2q);
-          const uint64_t T = mul_shoup63(x[k1], w, wsh, c.negq);
-          x[k0] = X + T;  // [0, 4q), brought back by the next csub_neg
-          x[k1] = X - T + q2;
+          const uint64_t X = csub_neg(x[k0], c.neg3q);
+          const uint64_t T = mul_shoup_2q(x[k1], w, wsh, c.neg2q);
+          x[k0] = X + T;  // [0, 6q), brought back by the next csub_neg
+          x[k1] = X - T + c.three_q;
         }
       }
   }

@@ -198,7 +198,7 @@ __global__ __launch_bounds__((1 << LOGN) >> 3) void ks_fwd_kernel(const uint64_t
     }
     fwd_rest<LOGN, LOGE, 0>(x, lds, tid, tw, c);
 #pragma unroll
-    for (int k = 0; k < E; k++) x[k] = csub_neg(csub_neg(x[k], c.neg2q), c.negq);
+    for (int k = 0; k < E; k++) x[k] = fwd_canon(x[k], c);
     exchange<LOGE, 0, TOP>(lds, x, tid);  // entry tid + k*T, as the key rows are read
     // the key loads are addressed from a value defined here, so they are
     // issued after the transform rather than held in registers through it
@@ -270,7 +270,7 @@ __global__ __launch_bounds__((1 << LOGN) >> 3) void modup_ntt_kernel(const uint6
   }
   fwd_rest<LOGN, LOGE, 0>(x, lds, tid, tw_all + (size_t)m * N, c);
 #pragma unroll
-  for (int k = 0; k < E; k++) x[k] = csub_neg(csub_neg(x[k], c.neg2q), c.negq);
+  for (int k = 0; k < E; k++) x[k] = fwd_canon(x[k], c);
   exchange<LOGE, 0, TOP>(lds, x, tid);
   uint64_t* out = digits + (il * L1 + m) * N;
 #pragma unroll

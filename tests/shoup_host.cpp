@@ -1,8 +1,10 @@
-// Host check of the inverse transform's twiddle product and lazy bound
+// Host check of the transforms' twiddle product and lazy bounds
 // (modarith.h): mul_shoup_2q(x, w, wsh, 2^64 - 2q) with wsh = floor(w*2^63/q)
-// equals x*w mod q and stays below 2.75q for every x < 6q, and the inverse
+// equals x*w mod q and stays below 2.75q for every x < 6q; the inverse
 // butterfly (X + Y brought below 3q, (X - Y + 3q)*w) keeps every value below
-// 3q stage after stage.  Random and extreme operands, against exact 128-bit
+// 3q stage after stage; the forward butterfly (x0 brought below 3q, then
+// X +- x1*w with 3q added to the difference) keeps every value below 6q, and
+// canon_below6q brings such a value to [0, q).  Random and extreme operands, against exact 128-bit
 // arithmetic.  Usage: shoup_host <q> <trials>; prints "ok <n>" or the first
 // failure and exits 1.
 #include <cstdio>
@@ -58,6 +60,38 @@ int main(int argc, char** argv) {
       ex = (st & 1) ? fy : fx, ey = (st & 1) ? fx : fy;
     }
   }
+  // thirteen forward stages (X = x0 below 3q, T = mul_shoup_2q(x1), X + T
+  // and X - T + 3q, every value below 6q), then the canonical step
+  for (long n = 0; n < trials / 16; n++) {
+    uint64_t X = n % 3 == 0 ? 6 * q - 1 : splitmix() % q, Y = n % 3 == 1 ? 6 * q - 1 : splitmix() % q;
+    uint64_t ex = X % q, ey = Y % q;
+    for (int st = 0; st < 13; st++) {
+      const uint64_t w = n % 5 == 0 ? q - 1 : splitmix() % q, wsh = (uint64_t)(((u128)w << 63) / q);
+      const uint64_t A = heconv::csub_neg(X, neg3q);
+      const uint64_t T = heconv::mul_shoup_2q(Y, w, wsh, neg2q);
+      const uint64_t nx = A + T, ny = A - T + q3;
+      const uint64_t t = (uint64_t)((u128)ey * w % q), fx = (ex + t) % q, fy = (ex + q - t) % q;
+      if (A >= q3 || nx >= 6 * q || ny >= 6 * q || nx % q != fx || ny % q != fy) {
+        std::printf("forward butterfly q=%llu n=%ld stage %d\n", (unsigned long long)q, n, st);
+        return 1;
+      }
+      X = (st & 1) ? ny : nx, Y = (st & 1) ? nx : ny;
+      ex = (st & 1) ? fy : fx, ey = (st & 1) ? fx : fy;
+    }
+    const uint64_t negq = 0 - q;
+    if (heconv::canon_below6q(X, neg3q, neg2q, negq) != ex || heconv::canon_below6q(Y, neg3q, neg2q, negq) != ey) {
+      std::printf("canonical step q=%llu n=%ld\n", (unsigned long long)q, n);
+      return 1;
+    }
+  }
+  for (uint64_t x = 0; x < 6 * q; x += q / 7 + 1)
+    for (uint64_t d = 0; d < 3; d++) {
+      const uint64_t v = x + d < 6 * q ? x + d : 6 * q - 1;
+      if (heconv::canon_below6q(v, neg3q, neg2q, 0 - q) != v % q) {
+        std::printf("canon_below6q q=%llu x=%llu\n", (unsigned long long)q, (unsigned long long)v);
+        return 1;
+      }
+    }
   std::printf("ok %ld\n", trials);
   return 0;
 }
