@@ -38,6 +38,18 @@ __device__ __forceinline__ int elem_index(int tid, int k) {
   return low | (k << LO) | (high << (LO + LOGE));
 }
 
+// tid >> LO, the index of the thread's block of 2^LO elements.  From LO = 6
+// up every lane of a wave has the same value (tid = 64w + i gives
+// w >> (LO - 6)); it is then read from the first lane, so the twiddle index
+// is uniform and its loads are scalar loads shared by the wave.
+template <int LO>
+__device__ __forceinline__ int block_of(int tid) {
+  if constexpr (LO >= 6)
+    return __builtin_amdgcn_readfirstlane(tid >> LO);
+  else
+    return tid >> LO;
+}
+
 // A forward value (below 6q) brought to [0, q).
 __device__ __forceinline__ uint64_t fwd_canon(uint64_t x, const LimbConst& c) {
   return canon_below6q(x, c.neg3q, c.neg2q, c.negq);
@@ -50,7 +62,7 @@ __device__ __forceinline__ uint64_t fwd_canon(uint64_t x, const LimbConst& c) {
 template <int LOGN, int LOGE, int LO, int U0>
 __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LOGE], int tid, const Tw* __restrict__ tw,
                                          const LimbConst& c, uint32_t jb = 0) {
-  const int high = tid >> LO;
+  const int high = block_of<LO>(tid);
   const uint64_t q3 = c.three_q;
 #pragma unroll
   for (int u = U0; u < LOGE; u++) {
@@ -78,7 +90,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&x)[1 << LOGE], int tid, cons
 template <int LOGN, int LOGE, int LO, int U0, bool LAST>
 __device__ __forceinline__ void inv_pass(uint64_t (&x)[1 << LOGE], int tid, const Tw* __restrict__ tw,
                                          const LimbConst& c, uint32_t jb = 0) {
-  const int high = tid >> LO;
+  const int high = block_of<LO>(tid);
   const uint64_t q3 = c.three_q;
 #pragma unroll
   for (int u = LOGE - 1; u >= U0; u--) {
