@@ -112,44 +112,31 @@ __device__ __forceinline__ void mac_grid_decode(const MacItem& it, const BatchJo
   }
 }
 
-// Wait until this wave's loads of block g are in LDS: `ahead` blocks
-// (0 .. P-2) were issued after it, n pairs each (n = 1 .. NW).
-template <int P, int NW>
-__device__ __forceinline__ void mac_grid_wait(uint32_t ahead, uint32_t n) {
-  static_assert(NW >= 1 && NW <= 4 && P >= 2 && P <= 4, "wait counts");
-  const uint32_t c = ahead * n;  // at most (P - 2) * NW <= 8
-  switch (c) {
-    case 0: return wait_vmcnt<0>();
-    case 1: return wait_vmcnt<1>();
-    case 2: return wait_vmcnt<2>();
-    case 3: return wait_vmcnt<3>();
-    case 4: return wait_vmcnt<4>();
-    case 5: return wait_vmcnt<5>();
-    case 6: return wait_vmcnt<6>();
-    case 7: return wait_vmcnt<7>();
-    default: return wait_vmcnt<8>();
-  }
-}
-
 template <int MT, int RT, int THREADS, int P, bool PM, class Src>
 __device__ __forceinline__ void mac_grid(const Src& src, const LimbConst* __restrict__ lcs, uint32_t L, uint32_t logN,
                                          uint64_t* lds, int tid) {
   static_assert(THREADS == 256 && MT % 2 == 0 && RT % 2 == 0 && P >= 2 && P <= 4, "four waves, rows in pairs");
   using Sh = MacGridShape<MT, RT>;
-  static_assert((P - 2) * Sh::NW <= 8, "wait counts");
   constexpr int ROWS = Sh::ROWS;
-  const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6), lane = (uint32_t)tid & 63;
+  // loads per block of the wave with the fewest (every wave loads PAIRS / 4
+  // or PAIRS / 4 + 1 row pairs)
+  constexpr int MINE = Sh::PAIRS / 4;
+  static_assert(MINE >= 1 && (P - 2) * MINE <= 63, "wait counts");
+  // (tid < 256: the mask only tells the compiler that wave <= 3, so that the
+  // per-wave load tests of tiles whose pairs divide by four fold away)
+  const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6) & 3u, lane = (uint32_t)tid & 63;
   const uint32_t half = lane >> 5, lo16 = (lane & 31) * 16;
   const uint32_t wi = wave & 1, wj = wave >> 1;
   const uint32_t LN8 = (L << logN) * 8;
-  uint32_t nmine = 0;  // row pairs this wave loads per block
-#pragma unroll
-  for (int k = 0; k < Sh::NW; k++) nmine += wave + 4 * k < (uint32_t)Sh::PAIRS;
 
   const uint32_t nv = src.count();
   if (nv == 0) return;
 
-  uint32_t li = 0, lcb = 0, issued = 0;
+  // load cursor: tile li, its block lcb, the stage it fills; it stays on the
+  // stream's last block once that is issued (li = nv), so that every block
+  // issues the same loads and the wait count is a constant (the P - 1
+  // re-loads at the end fill stages that no block reads)
+  uint32_t li = 0, lcb = 0, lst = 0;
   MacGridLoad<MT, RT> ld;
   auto load_tile = [&](uint32_t i) {
     MacItem it;
@@ -158,16 +145,19 @@ __device__ __forceinline__ void mac_grid(const Src& src, const LimbConst* __rest
     mac_grid_decode<MT, RT>(it, jd, L, logN, wave, half, lo16, &ld, (MacGridStore<MT, RT>*)nullptr);
   };
   auto issue_next = [&]() {
-    if (li == nv) return;
-    uint64_t* st = lds + (issued % P) * ROWS * 64;
+    uint64_t* st = lds + lst * ROWS * 64;
 #pragma unroll
     for (int k = 0; k < Sh::NW; k++)
       if (wave + 4 * k < (uint32_t)Sh::PAIRS)
         mac_dma_load(ld.r[k], st + (wave + 4 * k) * 2 * 64, ld.lane_off[k], lcb * ld.step[k]);
-    issued++;
-    if (++lcb == ld.CB) {
-      lcb = 0;
-      if (++li < nv) load_tile(li);
+    lst = lst + 1 == (uint32_t)P ? 0 : lst + 1;
+    if (li < nv && ++lcb == ld.CB) {
+      if (li + 1 < nv) {
+        lcb = 0;
+        load_tile(++li);
+      } else {
+        lcb = ld.CB - 1, li = nv;
+      }
     }
   };
 
@@ -183,8 +173,8 @@ __device__ __forceinline__ void mac_grid(const Src& src, const LimbConst* __rest
   load_tile(0);
 #pragma unroll
   for (int s0 = 0; s0 < P - 1; s0++) issue_next();
-  uint32_t g = 0;
-  for (;;) {  // tiles
+  uint32_t gst = 0;  // the stage of the block being consumed
+  for (;;) {         // tiles
     uint64_t a00[MT][RT], am[MT][RT], a11[MT][RT];
 #pragma unroll
     for (int j = 0; j < MT; j++)
@@ -192,14 +182,17 @@ __device__ __forceinline__ void mac_grid(const Src& src, const LimbConst* __rest
       for (int i = 0; i < RT; i++) a00[j][i] = am[j][i] = a11[j][i] = 0;
     for (uint32_t ccb = 0;;) {  // chunks of MAC3_CHUNK blocks
       const uint32_t nb = sd.CB - ccb < MAC3_CHUNK ? sd.CB - ccb : MAC3_CHUNK;
-      for (uint32_t k = 0; k < nb; k++, g++) {
-        // own loads of block g, then every wave's (and every wave past block g - 1)
-        mac_grid_wait<P, Sh::NW>(issued - g - 1, nmine);
+      for (uint32_t k = 0; k < nb; k++) {
+        // own loads of block g (P - 2 blocks were issued after it; a wave with
+        // more than MINE loads a block waits for a few more than it needs),
+        // then every wave's, and every wave is past block g - 1
+        wait_vmcnt<(P - 2) * MINE>();
         __builtin_amdgcn_s_barrier();
         __asm__ volatile("" ::: "memory");
         issue_next();  // block g + P - 1, into the stage block g - 1 used
         __builtin_amdgcn_sched_barrier(0);
-        const uint64_t* st = lds + (g % P) * ROWS * 64 + lane;
+        const uint64_t* st = lds + gst * ROWS * 64 + lane;
+        gst = gst + 1 == (uint32_t)P ? 0 : gst + 1;
         Half30 xs[RT];
 #pragma unroll
         for (int i = 0; i < RT; i++) xs[i] = split30(st[(wj * RT + i) * 64]);

@@ -98,20 +98,6 @@ __device__ __forceinline__ void mac_stream_decode(const MacItem& it, const Batch
   }
 }
 
-// Wait until block g's loads are in LDS: `ahead` blocks (0 .. P-1) were
-// issued after it, PAIRS loads each.
-template <int P, int PAIRS>
-__device__ __forceinline__ void mac_stream_wait(uint32_t ahead) {
-  if constexpr (P >= 4) {
-    if (ahead >= 3) return wait_vmcnt<3 * PAIRS>();
-  }
-  if constexpr (P >= 3) {
-    if (ahead >= 2) return wait_vmcnt<2 * PAIRS>();
-  }
-  if (ahead >= 1) return wait_vmcnt<PAIRS>();
-  wait_vmcnt<0>();
-}
-
 // Tile sources: count() tiles, get(i) the tile and its job.
 // A batch workgroup's list: items[0 .. n), valid ones first.
 struct MacListSrc {
@@ -155,8 +141,12 @@ __device__ __forceinline__ void mac_stream(const Src& src, const LimbConst* __re
   const uint32_t nv = src.count();
   if (nv == 0) return;
 
-  // load cursor: tile li, its block lcb
-  uint32_t li = 0, lcb = 0, issued = 0;
+  // load cursor: tile li, its block lcb, the stage it fills.  Once the
+  // stream's last block is issued the cursor stays on it (li = nv): every
+  // block issues the same PAIRS loads, so block g is in LDS once at most
+  // (P - 1) * PAIRS are outstanding, a constant; the P - 1 re-loads at the end
+  // fill stages that no block reads.
+  uint32_t li = 0, lcb = 0, lst = 0;
   MacLoad<MT, RT> ld;
   uint32_t w_lane[PW];
   auto load_tile = [&](uint32_t i) {
@@ -168,16 +158,19 @@ __device__ __forceinline__ void mac_stream(const Src& src, const LimbConst* __re
     for (int p = 0; p < PW; p++) w_lane[p] = lo16 + half * ld.w2[p];
   };
   auto issue_next = [&]() {
-    if (li == nv) return;
-    uint64_t* st = ring + (issued % P) * ROWS * 64;
+    uint64_t* st = ring + lst * ROWS * 64;
 #pragma unroll
     for (int p = 0; p < PIN; p++) mac_dma_load(ld.ib[p], st + (2 * p) * 64, in_lane, lcb * ld.in_step);
 #pragma unroll
     for (int p = 0; p < PW; p++) mac_dma_load(ld.wb[p], st + (RT + 2 * p) * 64, w_lane[p], lcb * LN8);
-    issued++;
-    if (++lcb == ld.CB) {
-      lcb = 0;
-      if (++li < nv) load_tile(li);
+    lst = lst + 1 == (uint32_t)P ? 0 : lst + 1;
+    if (li < nv && ++lcb == ld.CB) {
+      if (li + 1 < nv) {
+        lcb = 0;
+        load_tile(++li);
+      } else {
+        lcb = ld.CB - 1, li = nv;
+      }
     }
   };
 
@@ -194,8 +187,8 @@ __device__ __forceinline__ void mac_stream(const Src& src, const LimbConst* __re
   load_tile(0);
 #pragma unroll
   for (int s0 = 0; s0 < P - 1; s0++) issue_next();
-  uint32_t g = 0;  // blocks consumed
-  for (;;) {       // tiles
+  uint32_t gst = 0;  // the stage of the block being consumed
+  for (;;) {         // tiles
     uint64_t a00[MT][RT], am[MT][RT], a11[MT][RT];
 #pragma unroll
     for (int j = 0; j < MT; j++)
@@ -203,12 +196,13 @@ __device__ __forceinline__ void mac_stream(const Src& src, const LimbConst* __re
       for (int i = 0; i < RT; i++) a00[j][i] = am[j][i] = a11[j][i] = 0;
     for (uint32_t ccb = 0;;) {  // chunks of MAC3_CHUNK blocks
       const uint32_t nb = sd.CB - ccb < MAC3_CHUNK ? sd.CB - ccb : MAC3_CHUNK;
-      for (uint32_t k = 0; k < nb; k++, g++) {
+      for (uint32_t k = 0; k < nb; k++) {
         issue_next();
-        mac_stream_wait<P, PAIRS>(issued - g - 1);
+        wait_vmcnt<(P - 1) * PAIRS>();  // P - 1 blocks were issued after this one
         __asm__ volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
-        const uint64_t* st = ring + (g % P) * ROWS * 64 + lane;
+        const uint64_t* st = ring + gst * ROWS * 64 + lane;
+        gst = gst + 1 == (uint32_t)P ? 0 : gst + 1;
         Half30 xs[RT];
 #pragma unroll
         for (int i = 0; i < RT; i++) xs[i] = split30(st[i * 64]);
