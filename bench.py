@@ -438,6 +438,7 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
     st_batch = _passes(torch, lambda: b.launch(graph=True), 40, 2, stream)
     t_plain, t_batch = st_plain["mean_ms"], st_batch["mean_ms"]
     n = len(jobs)
+    fixed_mac_form = b.mac_form
     b.close()
     # per-grid durations of the same jobs as one chain (HIP events around
     # each grid, eager): the MAC grid's algorithmic bytes over its duration
@@ -463,8 +464,9 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
         same = all(torch.equal(j[4], o) for j, o in zip(jobs, plain_out))
         st_tuned = _passes(torch, lambda: bt.launch(graph=True), 40, 2, stream)
         t_tuned = st_tuned["mean_ms"]
+        tuned_mac_form = bt.mac_form
         bt.close()
-        tuned = {"schedule": SCHEDULE_NAMES[tr.schedule],
+        tuned = {"schedule": SCHEDULE_NAMES[tr.schedule], "mac_form": tuned_mac_form,
                  "tuning": {k: tr.tuning[k] for k in ("mac_mt", "mac_rt", "mac_lds", "mac_tiles", "mac_grid", "ntt_loge_small", "ntt_loge_large")},
                  "batched_ms": t_tuned, "batched_layers_per_s": n / t_tuned * 1e3,
                  "batched_p50_ms": st_tuned["p50_ms"], "batched_p99_ms": st_tuned["p99_ms"],
@@ -481,7 +483,8 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
     # tile and NTT grouping chosen by measurement), else the fixed form
     fixed = {"batched_ms": t_batch, "batched_layers_per_s": n / t_batch * 1e3,
              "batched_p50_ms": st_batch["p50_ms"], "batched_p99_ms": st_batch["p99_ms"],
-             "form": "two chains of three grids, tiles by shape, one hipGraph", "bit_exact_vs_plain": bool(exact)}
+             "form": "two chains of three grids, tiles by shape, one hipGraph", "mac_form": fixed_mac_form,
+             "bit_exact_vs_plain": bool(exact)}
     if tuned is not None:
         mt, rt = tuned["tuning"]["mac_mt"], tuned["tuning"]["mac_rt"]
         tile = "by shape" if mt == 0 else f"{mt}x{rt}"
