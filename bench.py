@@ -346,7 +346,7 @@ def main():
     if not args.no_single:
         result["single_layer"] = run_single_layer(torch, heconv, args)
     if not args.no_batched:
-        result["batched"] = run_batched(torch, heconv, tune=not args.no_autotune)
+        result["batched"] = run_batched(torch, heconv, tune=not args.no_autotune, cpu_args=args)
         result["batched_polyphase"] = run_batched(torch, heconv, polyphase=True)
         result["stem_polyphase_b16"] = run_stem_polyphase(torch, heconv)
     if not args.no_serving:
@@ -389,7 +389,7 @@ def _timed(torch, fn, reps, warm=2, warm_s=0.1):
     return a.elapsed_time(b) / reps
 
 
-def run_batched(torch, heconv, polyphase=False, tune=False):
+def run_batched(torch, heconv, polyphase=False, tune=False, cpu_args=None):
     """Fire-module CNN (26 convs at 224 input, B=1, N=8192, L=3): the 26 layer
     solves one after another through he_conv_layer (plain) vs one batch (two
     chains of three grids, one hipGraph launch).  Outputs compared word for
@@ -401,6 +401,7 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
     ctx = heconv.Context(N, heconv.gen_primes(N, bits, L), 2 ** synth.T_BITS)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64).copy()).cuda()
     jobs, pristine, macs, out_cts, mac_bytes = [], [], 0, 0, 0
+    host = []  # per layer: the input words and kernel the oracle leg takes
     for i, shape in enumerate(cfg["layers"]):
         C, H, W, M, kh, kw, stride, pad = shape
         K = Stream(cfg["seed"] * 1000 + i, synth.WEIGHT).ints(M * C * kh * kw, *cfg["w_range"])
@@ -419,6 +420,8 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
         mac_bytes += s.w_words * 8 + (s.in_cts + s.out_cts) * 2 * L * N * 8
         x = synth.uniform_mod(Stream(cfg["seed"] * 1000 + i, synth.UNIFORM), (s.in_cts * 2, L, N), ctx.q)
         pristine.append(dev(x))
+        if not polyphase:
+            host.append((x, K.reshape(M, C, kh, kw), (d.Cw, d.Hw, d.Ww)))
         jobs.append((d, 1, pristine[-1].clone(), wntt, torch.empty(s.out_cts * 2 * L * N, dtype=torch.int64,
                                                                          device="cuda")))
         macs += M * s.CB * s.S
@@ -473,6 +476,9 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
                  "batched_ms": t_tuned, "batched_layers_per_s": n / t_tuned * 1e3,
                  "batched_p50_ms": st_tuned["p50_ms"], "batched_p99_ms": st_tuned["p99_ms"],
                  "candidates_timed": len(tr.evaluations), "bit_exact_vs_plain": bool(same)}
+    cpu = None
+    if cpu_args is not None and not cpu_args.no_cpu_baseline and not polyphase:
+        cpu = cpu_baseline_fire(cpu_args, cfg, ctx.q, host, plain_out)
     del plain_out
     ctx.close()
     if polyphase:
@@ -504,7 +510,8 @@ def run_batched(torch, heconv, polyphase=False, tune=False):
             "plain_layers_per_s": n / t_plain * 1e3, "batched_layers_per_s": n / t_b * 1e3,
             "plain_ctpt_macs_per_s": macs / t_plain * 1e3, "batched_ctpt_macs_per_s": macs / t_b * 1e3,
             "speedup": t_plain / t_b, "bit_exact_vs_plain": bool(ok), "batched_form": form,
-            "one_chain_grids": one_chain, "fixed_form": fixed, **({"autotuned": tuned} if tuned is not None else {})}
+            "one_chain_grids": one_chain, "fixed_form": fixed, **({"autotuned": tuned} if tuned is not None else {}),
+            **({"cpu_baseline": cpu[0], "oracle_checked_layer_solves": cpu[1]} if cpu is not None else {})}
 
 
 def run_stem_polyphase(torch, heconv):
@@ -790,6 +797,39 @@ def _passes(torch, fn, k, warm, stream):
     per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(k)])
     return {"passes_timed": k, "mean_ms": float(ev[0].elapsed_time(ev[-1]) / k),
             "p50_ms": float(np.percentile(per, 50)), "p99_ms": float(np.percentile(per, 99))}
+
+
+def cpu_baseline_fire(args, cfg, q, host, gpu_out):
+    """The CPU oracle (as it stands) on the fire-module CNN: its layers in
+    order through the oracle's textbook NTT flow (forward NTT, MAC, inverse
+    NTT; OpenMP over limb polynomials) on the same input words and kernels
+    as the GPU pass, until about --cpu-seconds (the whole pass takes about
+    one second), scaled to ct x pt MACs/s; every word of each layer solve is
+    compared with the GPU's output."""
+    import oracle
+
+    prm = oracle.Params(cfg["N"], cfg["L"], cfg["bits"], 2 ** synth.T_BITS)
+    assert prm.q == list(q)
+    spent, macs, done, exact = 0.0, 0, 0, True
+    for j, (x, K, (Cw, Hw, Ww)) in enumerate(host):
+        cv = oracle.Conv(*cfg["layers"][j])
+        g = oracle.geometry(cv, Cw, Hw, Ww)
+        w_ntt = oracle.encode_weights(K, cv, g, prm)
+        t0 = time.perf_counter()
+        want = oracle.conv_layer_ntt(x.reshape(1, g.CB, g.S, 2, prm.L, prm.N), w_ntt, 1, g, cv.M, prm)
+        spent += time.perf_counter() - t0
+        macs += cv.M * g.CB * g.S
+        got = gpu_out[j].cpu().numpy().view(np.uint64)
+        exact &= bool(np.array_equal(got, want.reshape(-1)))
+        done += 1
+        del want, got, w_ntt
+        if spent > args.cpu_seconds:
+            break
+    return ({"value": macs / spent, "unit": "ct×pt MACs/s", "cores": oracle.num_threads(), "kind": "oracle",
+             "sample": f"layers 0-{done - 1} of the fire-module CNN ({macs} ct x pt MACs, one image) through the "
+                       f"oracle's textbook NTT flow (forward NTT, MAC, inverse NTT; OpenMP over limb "
+                       f"polynomials), {spent:.1f} s; weight preprocessing not included"},
+            {"layer_solves": done, "words_equal": exact})
 
 
 def cpu_baseline_bottleneck(args, pending):
