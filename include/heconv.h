@@ -110,8 +110,9 @@ void he_ctx_destroy(he_ctx* ctx);
  * (4,8), which he_conv_ntt_mac and he_conv_layer replace by the shape's
  * default.  A batch takes the context's pair when its MAC is built for it
  * (streamed: (4,4) (6,4) (8,4) (4,8) (4,2) (2,4) (2,2); register loads:
- * (4,4) (4,2) (2,4) (2,2)); else (2,2) when a job has fewer than four rows
- * or output channels, else (4,4) on the 2x2 wave grid (mac_grid) when every
+ * (4,4) (4,2) (2,4) (2,2)); else (2,2) when a job has fewer than four
+ * output channels, (4,2) when a job has fewer than four ciphertext rows,
+ * else (4,4) on the 2x2 wave grid (mac_grid) when every
  * job has at least 8 rows and output channels, else (6,4) for the streamed
  * MAC when every job has at least six output channels, else (4,4).
  * layer_fused: 1 = he_conv_layer runs the MAC and the inverse NTT as one

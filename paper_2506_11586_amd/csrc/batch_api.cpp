@@ -120,11 +120,12 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
   if (schedule == HE_SCHED_PIPELINED_8) b->n_chains = std::min<uint32_t>(n_jobs, 8);
 
   // validate, and pick the MAC tile: the context's tile when the batch
-  // kernel is built for it, else (2,2) when a job has fewer than 4
-  // ciphertext rows or output channels, else (6,4) for the streamed MAC
+  // kernel is built for it, else (2,2) when a job has fewer than 4 output
+  // channels, (4,2) when a job has fewer than 4 ciphertext rows (a job of
+  // one spatial tile and one image has 2), else (6,4) for the streamed MAC
   // when every job has at least 6 output channels, else (4,4)
   std::vector<heconv::Geo> geo(n_jobs);
-  bool small = false, narrow = false;
+  bool few_rows = false, few_m = false, narrow = false;
   for (uint32_t j = 0; j < n_jobs; j++) {
     const he_job& jb = jobs[j];
     if (!heconv::geo_of(jb.desc, c->N, geo[j]) || !heconv::mac_offsets_fit(geo[j], c->L, c->N)) {
@@ -135,7 +136,8 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
       free_batch(b);
       return HE_EINVAL;
     }
-    small |= (uint64_t)jb.B * geo[j].S * 2 < 4 || jb.desc.M < 4;
+    few_rows |= (uint64_t)jb.B * geo[j].S * 2 < 4;
+    few_m |= jb.desc.M < 4;
     narrow |= jb.desc.M < 6;
   }
   // the LDS-staged MAC when the context asks for it and every job fits it
@@ -145,8 +147,10 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
   b->mac_tiles = c->tune.mac_tiles ? c->tune.mac_tiles : 4;
   if (heconv::batch_tile_supported(c->tune.mac_mt, c->tune.mac_rt, b->mac_lds)) {
     b->mac_mt = c->tune.mac_mt, b->mac_rt = c->tune.mac_rt;
-  } else if (small) {
+  } else if (few_m) {
     b->mac_mt = b->mac_rt = 2;
+  } else if (few_rows) {
+    b->mac_mt = 4, b->mac_rt = 2;
   } else {
     b->mac_mt = b->mac_lds >= 2 && !narrow ? 6 : 4, b->mac_rt = 4;
   }
@@ -160,7 +164,7 @@ he_status he_batch_create(const he_ctx* c, const he_job* jobs, uint32_t n_jobs, 
     return f;
   };
   if (b->mac_lds >= 2 && c->tune.mac_grid) {
-    if (!heconv::batch_tile_supported(c->tune.mac_mt, c->tune.mac_rt, b->mac_lds) && !small && fills(4, 4))
+    if (!heconv::batch_tile_supported(c->tune.mac_mt, c->tune.mac_rt, b->mac_lds) && !few_rows && !few_m && fills(4, 4))
       b->mac_mt = b->mac_rt = 4;
     b->mac_grid = b->mac_mt != 8 && b->mac_rt != 8 && fills(b->mac_mt, b->mac_rt) ? 1 : 0;
   }

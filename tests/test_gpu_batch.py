@@ -332,3 +332,29 @@ def test_wave_grid_falls_back_when_jobs_do_not_fill_it(ctx4096):
     ctx.set_tuning(**before)
     assert b.mac_form["grid"] == 0
     b.close()
+
+
+def test_batch_default_tile_for_jobs_of_few_rows(ctx4096):
+    """With the context's tile left to the shape (mac_mt = 0): a job of two
+    ciphertext rows (one image, one spatial tile) gives the batch 4x2 tiles,
+    a job of fewer than four output channels 2x2; every output word equals
+    the oracle's."""
+    from paper_2506_11586_amd import heconv
+    ctx, prm = ctx4096
+    cases = [([((8, 11, 9, 16, 3, 3, 2, 1), 1), ((16, 12, 12, 8, 3, 3, 1, 1), 2)], (4, 2)),
+             ([((8, 11, 9, 3, 3, 3, 1, 1), 2), ((16, 12, 12, 8, 3, 3, 1, 1), 2)], (2, 2))]
+    before = ctx.get_tuning().as_dict()
+    for shapes, tile in cases:
+        jobs, host = make_jobs(ctx, prm, shapes, 990)
+        ctx.set_tuning(mac_mt=0, mac_rt=0)
+        b = heconv.Batch(ctx, jobs, schedule=1)
+        ctx.set_tuning(**before)
+        assert (b.mac_form["mt"], b.mac_form["rt"]) == tile, (shapes, b.mac_form)
+        b.launch(graph=False)
+        b.status()
+        for (d, B, d_in, wntt, d_out), (cv, _, _, x, K) in zip(jobs, host):
+            g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+            want = oracle.conv_layer_ntt(x.reshape(B, g.CB, g.S, 2, prm.L, prm.N), oracle.encode_weights(K, cv, g, prm),
+                                         B, g, cv.M, prm)
+            assert np.array_equal(to_host(d_out), want.reshape(-1)), (shapes, cv)
+        b.close()
