@@ -689,51 +689,8 @@ def run_bottleneck_main(torch, heconv, args, probes):
         t = kavg[k]["ms_per_pass"] * 1e-3
         kavg[k]["alg"] = alg[k]
         kavg[k]["GBps"] = round(alg[k]["bytes"] / t / 1e9, 1)
-    form = bt.mac_form
-    mac_kernel = ("batch_mac_grid_kernel (streamed MAC, 2x2 wave grid)" if form["grid"] else
-                  "batch_mac_stream_kernel (streamed MAC)" if form["lds"] >= 2 else "batch_mac_kernel")
-    # the MAC at 16 images is bound by integer multiply-adds: each modmul-add
-    # is four v_mad_u64_u32 of 30-bit halves, so the ceiling is the chip's
-    # v_mad_u64_u32 rate / 4 (256 CUs x 64 lanes x 2.4 GHz; the probe
-    # measures that instruction at the full rate)
-    mac_t = kavg["batch_mac"]["ms_per_pass"] * 1e-3
-    achieved = alg["batch_mac"]["modmul_adds"] / mac_t / 1e9
-    peak = VALU_LANE_OPS_PEAK * MAD_RATE_FRAC / 4 / 1e9
-    roofline_mac = {"bound": "alu", "kernel": mac_kernel, "achieved": round(achieved, 1),
-                    "peak": round(peak, 1), "unit": "G modmul-adds/s", "frac": round(achieved / peak, 4),
-                    "traffic": load_traffic("batch_mac", cfg["name"]),
-                    "peak_derivation": "256 CUs x 64 lanes x 2.4 GHz (v_mad_u64_u32 issues at the full rate) / 4 "
-                                       "multiply-adds per modmul-add",
-                    "avg_launch_ms": round(kavg["batch_mac"]["avg_ms_per_launch"], 4)}
-    if probes:
-        mix = probes["mac_mix"]["rate"] / 1e9
-        roofline_mac["measured_mix_ceiling"] = {
-            "rate": round(mix, 1), "frac": round(achieved / mix, 4),
-            "note": "the streamed MAC's channel-block step and carry on registers (6x4 tile, 8-block chunks)"}
-    roofline_hbm = {"bound": "hbm", "kernel": mac_kernel, "achieved": kavg["batch_mac"]["GBps"],
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kavg["batch_mac"]["GBps"] / HBM_PEAK_GBS, 4)}
-    # the transforms are bound by integer VALU issue: the peak is the chip's
-    # full-rate lane operations over the VALU instructions of one butterfly
-    # as compiled (21 in either direction)
-    ntt_roof = {}
-    for k, kname, mix_key in (("batch_inv", "batch_inv_kernel (inverse NTTs)", "intt_mix"),
-                              ("batch_fwd", "batch_fwd_kernel (forward NTTs)", "ntt_mix")):
-        t = kavg[k]["ms_per_pass"] * 1e-3
-        bfly = alg[k]["modmuls"] / t / 1e9
-        peak_b = VALU_LANE_OPS_PEAK / BFLY_VALU_INSTS[k] / 1e9
-        r = {"bound": "alu", "kernel": kname, "achieved": round(bfly, 1), "peak": round(peak_b, 1),
-             "unit": "G butterflies/s", "frac": round(bfly / peak_b, 4), "traffic": load_traffic(k, cfg["name"]),
-             "peak_derivation": f"256 CUs x 64 lanes x 2.4 GHz / {BFLY_VALU_INSTS[k]} VALU instructions per "
-                                "butterfly (compiled)",
-             "avg_launch_ms": round(kavg[k]["avg_ms_per_launch"], 4)}
-        if probes:
-            ceil = probes[mix_key]["rate"] / 1e9
-            r["measured_mix_ceiling"] = {"rate": round(ceil, 1), "frac": round(bfly / ceil, 4),
-                                         "note": "the butterfly's own instruction mix on registers (he_probe_valu)"}
-        ntt_roof[k] = r
-    # the headline roofline is the dominant grid's: the longest of the three
-    dom = max(kavg, key=lambda k: kavg[k]["ms_per_pass"])
-    roofline = roofline_mac if dom == "batch_mac" else ntt_roof[dom]
+    roofline, roofline_mac, roofline_hbm, ntt_roof = headline_rooflines(
+        kavg, alg, bt.mac_form, probes, lambda k: load_traffic(k, cfg["name"]))
     resident = sum(t.numel() * 8 for t in wntts + ins + outs) / 2 ** 30
     res = {
         "metric": METRIC,
@@ -777,6 +734,60 @@ def run_bottleneck_main(torch, heconv, args, probes):
     del ins, outs, wntts, jobs
     ctx.close()
     return res, pending
+
+
+def headline_rooflines(kavg, alg, form, probes, traffic):
+    """The bottleneck batch's rooflines from its per-grid durations (kavg:
+    ms_per_pass and avg_ms_per_launch per grid), algorithmic work (alg), the
+    batch's MAC form, the VALU probes (or None) and a traffic lookup by grid
+    name.  Returns (roofline, roofline_mac, roofline_hbm, {grid: roofline})
+    for the transforms; roofline is the longest grid's."""
+    mac_kernel = ("batch_mac_grid_kernel (streamed MAC, 2x2 wave grid)" if form["grid"] else
+                  "batch_mac_stream_kernel (streamed MAC)" if form["lds"] >= 2 else "batch_mac_kernel")
+    # the MAC at 16 images is bound by integer multiply-adds: each modmul-add
+    # is four v_mad_u64_u32 of 30-bit halves, so the ceiling is the chip's
+    # v_mad_u64_u32 rate / 4 (256 CUs x 64 lanes x 2.4 GHz; the probe
+    # measures that instruction at the full rate)
+    mac_t = kavg["batch_mac"]["ms_per_pass"] * 1e-3
+    achieved = alg["batch_mac"]["modmul_adds"] / mac_t / 1e9
+    peak = VALU_LANE_OPS_PEAK * MAD_RATE_FRAC / 4 / 1e9
+    mac_gbps = alg["batch_mac"]["bytes"] / mac_t / 1e9
+    roofline_mac = {"bound": "alu", "kernel": mac_kernel, "achieved": round(achieved, 1),
+                    "peak": round(peak, 1), "unit": "G modmul-adds/s", "frac": round(achieved / peak, 4),
+                    "traffic": traffic("batch_mac"),
+                    "peak_derivation": "256 CUs x 64 lanes x 2.4 GHz (v_mad_u64_u32 issues at the full rate) / 4 "
+                                       "multiply-adds per modmul-add",
+                    "avg_launch_ms": round(kavg["batch_mac"]["avg_ms_per_launch"], 4)}
+    if probes:
+        mix = probes["mac_mix"]["rate"] / 1e9
+        roofline_mac["measured_mix_ceiling"] = {
+            "rate": round(mix, 1), "frac": round(achieved / mix, 4),
+            "note": "the streamed MAC's channel-block step and carry on registers (6x4 tile, 8-block chunks)"}
+    roofline_hbm = {"bound": "hbm", "kernel": mac_kernel, "achieved": round(mac_gbps, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(mac_gbps / HBM_PEAK_GBS, 4)}
+    # the transforms are bound by integer VALU issue: the peak is the chip's
+    # full-rate lane operations over the VALU instructions of one butterfly
+    # as compiled (21 in either direction)
+    ntt_roof = {}
+    for k, kname, mix_key in (("batch_inv", "batch_inv_kernel (inverse NTTs)", "intt_mix"),
+                              ("batch_fwd", "batch_fwd_kernel (forward NTTs)", "ntt_mix")):
+        t = kavg[k]["ms_per_pass"] * 1e-3
+        bfly = alg[k]["modmuls"] / t / 1e9
+        peak_b = VALU_LANE_OPS_PEAK / BFLY_VALU_INSTS[k] / 1e9
+        r = {"bound": "alu", "kernel": kname, "achieved": round(bfly, 1), "peak": round(peak_b, 1),
+             "unit": "G butterflies/s", "frac": round(bfly / peak_b, 4), "traffic": traffic(k),
+             "peak_derivation": f"256 CUs x 64 lanes x 2.4 GHz / {BFLY_VALU_INSTS[k]} VALU instructions per "
+                                "butterfly (compiled)",
+             "avg_launch_ms": round(kavg[k]["avg_ms_per_launch"], 4)}
+        if probes:
+            ceil = probes[mix_key]["rate"] / 1e9
+            r["measured_mix_ceiling"] = {"rate": round(ceil, 1), "frac": round(bfly / ceil, 4),
+                                         "note": "the butterfly's own instruction mix on registers (he_probe_valu)"}
+        ntt_roof[k] = r
+    # the headline roofline is the dominant grid's: the longest of the three
+    dom = max(kavg, key=lambda k: kavg[k]["ms_per_pass"])
+    roofline = roofline_mac if dom == "batch_mac" else ntt_roof[dom]
+    return roofline, roofline_mac, roofline_hbm, ntt_roof
 
 
 def _passes(torch, fn, k, warm, stream):

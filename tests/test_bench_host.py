@@ -48,3 +48,38 @@ def test_oracle_sample_layers_are_bottleneck_layers():
     import synth
     n = len(synth.WORKLOADS["bottleneck_cnn_b16"]["layers"])
     assert bench.ORACLE_SAMPLE_LAYERS and all(0 <= j < n for j in bench.ORACLE_SAMPLE_LAYERS)
+
+
+def _grids(fwd_ms, mac_ms, inv_ms):
+    kavg = {k: {"ms_per_pass": v, "avg_ms_per_launch": v}
+            for k, v in (("batch_fwd", fwd_ms), ("batch_mac", mac_ms), ("batch_inv", inv_ms))}
+    alg = {"batch_fwd": {"bytes": 1.7e10, "modmuls": 6.94e9},
+           "batch_mac": {"bytes": 2.454e11, "modmul_adds": 2.707e11},
+           "batch_inv": {"bytes": 3.414e11, "modmuls": 1.387e11}}
+    return kavg, alg
+
+
+def test_headline_roofline_is_the_longest_grid():
+    """The headline roofline follows the longest of the three grids: the
+    inverse NTT against 21 full-rate VALU instructions per butterfly, or the
+    MAC against four multiply-adds per modmul-add; the MAC's HBM line is its
+    algorithmic bytes over its duration; traffic comes from the lookup."""
+    kavg, alg = _grids(6.0, 84.0, 119.0)
+    form = {"grid": 1, "lds": 3}
+    seen = []
+    roof, mac, hbm, ntt = bench.headline_rooflines(kavg, alg, form, None, lambda k: seen.append(k) or 7)
+    assert roof is ntt["batch_inv"] and roof["bound"] == "alu" and roof["traffic"] == 7
+    assert abs(roof["peak"] - 256 * 64 * 2.4 / 21) < 0.1  # G butterflies/s
+    assert abs(roof["achieved"] - 1.387e11 / 0.119 / 1e9) < 0.1
+    assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-3
+    assert "measured_mix_ceiling" not in roof
+    assert mac["kernel"].startswith("batch_mac_grid_kernel") and abs(mac["peak"] - 9830.4) < 1e-6
+    assert abs(mac["achieved"] - 2.707e11 / 0.084 / 1e9) < 0.1
+    assert abs(hbm["achieved"] - 2.454e11 / 0.084 / 1e9) < 0.1 and hbm["peak"] == 8000.0
+    assert sorted(seen) == ["batch_fwd", "batch_inv", "batch_mac"]
+    kavg, alg = _grids(6.0, 130.0, 119.0)
+    probes = {"mac_mix": {"rate": 5.6e12}, "intt_mix": {"rate": 1.93e12}, "ntt_mix": {"rate": 1.93e12}}
+    roof, mac, hbm, ntt = bench.headline_rooflines(kavg, alg, {"grid": 0, "lds": 0}, probes, lambda k: None)
+    assert roof is mac and mac["kernel"] == "batch_mac_kernel" and mac["traffic"] is None
+    assert abs(mac["measured_mix_ceiling"]["frac"] - mac["achieved"] / 5600.0) < 1e-3
+    assert abs(ntt["batch_inv"]["measured_mix_ceiling"]["rate"] - 1930.0) < 1e-6
