@@ -170,10 +170,11 @@ void he_ctx_destroy(he_ctx* ctx);
  * bottleneck CNN's MAC grid from 129.6 to 121.1 ms.
  * mac_tiles: tiles per workgroup of a batch's streamed MAC (0 = 4, at most
  * 64).
- * mac_grid: 1 (default) = a batch's streamed MAC runs its workgroup's four
- * waves as a 2x2 grid over one slice of 64 NTT points, sharing the input and
- * weight rows they load (tiles of 2*mac_mt channels x 2*mac_rt rows, one
- * workgroup barrier per channel block), when every job has that many rows
+ * mac_grid: 1 (default) = the streamed MAC (a batch's, and that of
+ * he_conv_ntt_mac and he_conv_layer) runs its workgroup's four waves as a
+ * 2x2 grid over one slice of 64 NTT points, sharing the input and weight
+ * rows they load (tiles of 2*mac_mt channels x 2*mac_rt rows, one workgroup
+ * barrier per channel block), when every job (the layer) has that many rows
  * and channels; 0 = each wave its own 64 points.  Measured on the 16-image
  * bottleneck CNN's MAC grid: 98 ms per wave (6x4 tiles), 90 ms on the grid
  * (4x4 per wave, three stages), 88 ms with four stages.

@@ -447,7 +447,8 @@ he_status he_conv_ntt_mac(const he_ctx* c, const he_conv_desc* d, uint32_t B, co
   if (!d_in_ntt || !d_wntt || !d_out_ntt) return HE_EINVAL;
   if ((uint64_t)B * g.S * 2 > 0xffffffffull || !heconv::mac_offsets_fit(g, c->L, c->N)) return HE_ESHAPE;
   return dev_err(heconv::mac_launch(d_in_ntt, d_wntt, d_out_ntt, B, g.CB, g.S, d->M, c->L, c->N, c->d_lc,
-                                    c->tune.mac_mt, c->tune.mac_rt, c->tune.mac_lds, c->all_pm, (hipStream_t)stream));
+                                    c->tune.mac_mt, c->tune.mac_rt, c->tune.mac_lds, c->all_pm, c->tune.mac_grid != 0,
+                                    (hipStream_t)stream));
 }
 
 he_status he_conv_mac_intt(const he_ctx* c, const he_conv_desc* d, uint32_t B, const uint64_t* d_in_ntt,
@@ -491,7 +492,8 @@ he_status he_conv_layer(const he_ctx* c, const he_conv_desc* d, uint32_t B, uint
     const uint32_t m_end = p + 1 == P ? d->M : (uint32_t)((uint64_t)d->M * (p + 1) / P) & ~3u;
     const uint32_t Mp = m_end - m0;
     s = dev_err(heconv::mac_launch(d_in, d_wntt + m0 * w_per_m, d_out + m0 * out_per_m, 1, g.CB, g.S, Mp, c->L,
-                                   c->N, c->d_lc, c->tune.mac_mt, c->tune.mac_rt, c->tune.mac_lds, c->all_pm, st));
+                                   c->N, c->d_lc, c->tune.mac_mt, c->tune.mac_rt, c->tune.mac_lds, c->all_pm,
+                                   c->tune.mac_grid != 0, st));
     if (s) return s;
     if (hipEventRecord(c->ev_mac[p], st) != hipSuccess || hipStreamWaitEvent(c->aux, c->ev_mac[p], 0) != hipSuccess)
       return HE_EDEVICE;

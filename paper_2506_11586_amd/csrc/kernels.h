@@ -97,10 +97,13 @@ hipError_t pack_weights_launch(const PackGeom& g, const int64_t* w, uint64_t* ou
 // into registers (mac_tile), 2..4 = the streamed MAC (mac_stream) staging
 // them in LDS that many channel blocks ahead, for layers whose weight pairs
 // fit 32-bit offsets (others take the register loads).  all_pm: every q_l is
-// 2^60 - delta, delta < 2^20 (the streamed MAC's short fold).
+// 2^60 - delta, delta < 2^20 (the streamed MAC's short fold).  grid: the
+// streamed MAC runs each workgroup's four waves as a 2x2 grid (tiles of
+// 2*mt channels x 2*rt rows, mac_grid.h) when the layer has that many rows
+// and channels.
 hipError_t mac_launch(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t B, uint32_t CB, uint32_t S,
                       uint32_t M, uint32_t L, uint32_t N, const LimbConst* lc, uint32_t mt, uint32_t rt,
-                      uint32_t lds_stages, bool all_pm, hipStream_t st);
+                      uint32_t lds_stages, bool all_pm, bool grid, hipStream_t st);
 
 // Whether the LDS-staged MAC can take a layer: two output channels' weights
 // (2*CB*L*N words) below 2^31 bytes.

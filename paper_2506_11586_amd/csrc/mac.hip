@@ -1,6 +1,7 @@
 // Weight packing and the channel-block multiply-accumulate (NTT domain).
 #include "kernels.h"
 #include "mac_impl.h"
+#include "mac_grid.h"
 #include "mac_stream.h"
 #include "udiv.h"
 
@@ -134,6 +135,55 @@ static hipError_t mac_stream_p(uint32_t P, bool pm, const uint64_t* in, const ui
   return mac_stream_go<MT, RT, 4, false>(in, w, out, CB, S, M, L, N, rows, lc, st);
 }
 
+// Streamed MAC on the 2x2 wave grid for one layer (mac_grid): one tile of
+// 2*MT channels x 2*RT rows over 64 NTT points per workgroup, decoded from
+// the block index as above (k-chunk-major, the tiles of one k-chunk on one
+// XCD).
+template <int MT, int RT, int P, bool PM>
+__global__ __launch_bounds__(MAC_THREADS) void mac_grid_kernel(const uint64_t* __restrict__ in,
+                                                               const uint64_t* __restrict__ w,
+                                                               uint64_t* __restrict__ out, uint32_t CB, uint32_t S,
+                                                               uint32_t M, uint32_t L, uint32_t logN, uint32_t rows,
+                                                               uint32_t n_mt, uint32_t n_rt, MacDivs dv,
+                                                               const LimbConst* __restrict__ lcs) {
+  __shared__ uint64_t lds[P * MacGridShape<MT, RT>::ROWS * 64];
+  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t kc = udiv(tile, dv.chunk), rem = tile - kc * (n_mt * n_rt);
+  const uint32_t mt = udiv(rem, dv.rt), rt = rem - mt * n_rt;
+  const uint32_t bs0 = rt * RT, b0 = udiv(bs0, dv.s), s0 = bs0 - b0 * S;  // first row pair of the tile's 2*RT rows
+  const MacOneSrc src{MacItem{0, kc, mt, rt, b0, s0},
+                      BatchJob{const_cast<uint64_t*>(in), w, out, CB, S, M, rows, n_mt, n_rt}};
+  mac_grid<MT, RT, MAC_THREADS, P, PM>(src, lcs, L, logN, lds, threadIdx.x);
+}
+
+template <int MT, int RT, int P, bool PM>
+static hipError_t mac_grid_go(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t CB, uint32_t S,
+                              uint32_t M, uint32_t L, uint32_t N, uint32_t rows, const LimbConst* lc, hipStream_t st) {
+  const uint32_t n_mt = (M + 2 * MT - 1) / (2 * MT), n_rt = (rows + 2 * RT - 1) / (2 * RT);
+  const uint64_t blocks = (uint64_t)L * (N / 64) * n_mt * n_rt;
+  if (blocks > grid_max_blocks(MAC_THREADS) || blocks >= (1ull << 31)) return hipErrorInvalidConfiguration;
+  uint32_t logN = 0;
+  while ((1u << logN) < N) logN++;
+  const MacDivs dv{udiv_make(n_mt * n_rt), udiv_make(n_rt), udiv_make(S)};
+  hipLaunchKernelGGL((mac_grid_kernel<MT, RT, P, PM>), dim3((uint32_t)blocks), dim3(MAC_THREADS), 0, st, in, w, out,
+                     CB, S, M, L, logN, rows, n_mt, n_rt, dv, lc);
+  return hipGetLastError();
+}
+
+template <int MT, int RT>
+static hipError_t mac_grid_p(uint32_t P, bool pm, const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t CB,
+                             uint32_t S, uint32_t M, uint32_t L, uint32_t N, uint32_t rows, const LimbConst* lc,
+                             hipStream_t st) {
+  if (pm) {
+    if (P == 2) return mac_grid_go<MT, RT, 2, true>(in, w, out, CB, S, M, L, N, rows, lc, st);
+    if (P == 3) return mac_grid_go<MT, RT, 3, true>(in, w, out, CB, S, M, L, N, rows, lc, st);
+    return mac_grid_go<MT, RT, 4, true>(in, w, out, CB, S, M, L, N, rows, lc, st);
+  }
+  if (P == 2) return mac_grid_go<MT, RT, 2, false>(in, w, out, CB, S, M, L, N, rows, lc, st);
+  if (P == 3) return mac_grid_go<MT, RT, 3, false>(in, w, out, CB, S, M, L, N, rows, lc, st);
+  return mac_grid_go<MT, RT, 4, false>(in, w, out, CB, S, M, L, N, rows, lc, st);
+}
+
 template <int MT, int RT>
 static hipError_t mac_go(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t CB, uint32_t S, uint32_t M,
                          uint32_t L, uint32_t N, uint32_t rows, const LimbConst* lc, hipStream_t st) {
@@ -147,13 +197,23 @@ static hipError_t mac_go(const uint64_t* in, const uint64_t* w, uint64_t* out, u
 
 hipError_t mac_launch(const uint64_t* in, const uint64_t* w, uint64_t* out, uint32_t B, uint32_t CB, uint32_t S,
                       uint32_t M, uint32_t L, uint32_t N, const LimbConst* lc, uint32_t mt, uint32_t rt,
-                      uint32_t lds_stages, bool all_pm, hipStream_t st) {
+                      uint32_t lds_stages, bool all_pm, bool grid, hipStream_t st) {
   const uint32_t rows = B * S * 2;
   const bool small = rows < 4 || M < 4;
   if (lds_stages >= 2 && mac_dma_fits(CB, L, N)) {
     // streamed: (4,4) (6,4) (4,2) (2,4) (2,2); others take the shape's default
     const bool ok = (mt == 4 && (rt == 4 || rt == 2)) || (mt == 6 && rt == 4) || (mt == 2 && (rt == 4 || rt == 2));
     if (!ok) mt = small ? 2 : MAC_STREAM_DEFAULT_MT, rt = small ? 2 : 4;
+    if (grid && rows >= 2 * rt && M >= 2 * mt) {
+#define HECONV_MAC_GRID(A, Bt) \
+  if (mt == A && rt == Bt) return mac_grid_p<A, Bt>(lds_stages, all_pm, in, w, out, CB, S, M, L, N, rows, lc, st);
+      HECONV_MAC_GRID(4, 4)
+      HECONV_MAC_GRID(6, 4)
+      HECONV_MAC_GRID(4, 2)
+      HECONV_MAC_GRID(2, 4)
+      HECONV_MAC_GRID(2, 2)
+#undef HECONV_MAC_GRID
+    }
 #define HECONV_MAC_STREAM(A, Bt) \
   if (mt == A && rt == Bt) return mac_stream_p<A, Bt>(lds_stages, all_pm, in, w, out, CB, S, M, L, N, rows, lc, st);
     HECONV_MAC_STREAM(4, 4)

@@ -384,3 +384,36 @@ def test_empty_batch_is_a_noop():
     assert bool((guard == 7).all())
     bad = heconv.ConvDesc(*d.shape(), 5, d.Hw, d.Ww)  # Cw > C
     assert L.he_conv_layer(ctx.handle, heconv.ctypes.byref(bad), 0, None, None, None, None) == heconv.HE_ESHAPE
+
+
+GRID_CASES = [  # (shape, params, packing, B): enough rows and channels for the 2x2 wave grid
+    ((24, 12, 12, 16, 3, 3, 1, 1), (4096, 2, 50), (2, 14, 14), 8),  # Shoup fold (50-bit primes), CB = 12
+    ((20, 10, 10, 12, 3, 3, 1, 1), (8192, 3, 60), (1, 12, 12), 4),  # 2^60 - delta fold, CB = 20: two carries
+    ((40, 9, 9, 13, 1, 1, 1, 0), (8192, 3, 60), (2, 9, 9), 5),      # ragged rows and channels in the tiles
+]
+
+
+@pytest.mark.parametrize("shape,params,packing,B", GRID_CASES)
+def test_conv_ntt_mac_wave_grid(shape, params, packing, B):
+    """The per-layer streamed MAC on the 2x2 wave grid (mac_grid = 1, the
+    default) and per wave (mac_grid = 0), every streamed tile and depth,
+    against the oracle."""
+    ctx, prm = ctx_and_prm(*params)
+    cv = oracle.Conv(*shape)
+    d = ctx.plan(shape, batch=B, packing=packing)
+    g = oracle.geometry(cv, d.Cw, d.Hw, d.Ww)
+    assert g.CB >= 12 and B * g.S * 2 >= 8
+    x = rand_polys(21, B * g.CB * g.S * 2, prm)
+    w = rand_polys(22, cv.M * g.CB, prm)
+    want = oracle.conv_mac(x, w, B, g, cv.M, prm)
+    dx, dw = to_dev(x), to_dev(w)
+    before = ctx.get_tuning().as_dict()
+    for grid in (1, 0):
+        for lds in (2, 3, 4):
+            for mt, rt in ((4, 4), (6, 4), (4, 2), (2, 4), (2, 2)):
+                ctx.set_tuning(mac_mt=mt, mac_rt=rt, mac_lds=lds, mac_grid=grid)
+                out = empty_words(want.size)
+                out.fill_(-1)
+                ctx.conv_ntt_mac(d, B, dx, dw, out)
+                assert np.array_equal(to_host(out).reshape(want.shape), want), (grid, mt, rt, lds)
+    ctx.set_tuning(**before)
